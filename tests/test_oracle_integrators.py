@@ -1,0 +1,312 @@
+"""Pins of the oracle's integrators (Methods: ERK method, MRI method).
+
+Tableaux are pinned by their order conditions in exact rational arithmetic;
+the stepping code by the exact discrete solution of linear relaxation
+problems; the embedded estimate by its closed form; MIS by its two reducing
+special cases and its observed order.
+"""
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import integrators as I
+from tests import problems
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _paper_params():
+    out = {}
+    for line in open(os.path.join(GOLD, "paper_parameters.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()[:2]
+            out[k] = float(v)
+    return out
+
+
+def _full_A(tab):
+    S = len(tab["b"])
+    return [list(r) + [Fr(0)] * (S - len(r)) for r in tab["A"]]
+
+
+def _order_conditions(b, A, c, order):
+    """Butcher order conditions up to `order` (trees up to order 4)."""
+    S = len(b)
+    Ac = [sum(A[i][j] * c[j] for j in range(S)) for i in range(S)]
+    Acc = [sum(A[i][j] * c[j] ** 2 for j in range(S)) for i in range(S)]
+    AAc = [sum(A[i][j] * Ac[j] for j in range(S)) for i in range(S)]
+    conds = {
+        1: [(sum(b), Fr(1))],
+        2: [(sum(b[i] * c[i] for i in range(S)), Fr(1, 2))],
+        3: [(sum(b[i] * c[i] ** 2 for i in range(S)), Fr(1, 3)),
+            (sum(b[i] * Ac[i] for i in range(S)), Fr(1, 6))],
+        4: [(sum(b[i] * c[i] ** 3 for i in range(S)), Fr(1, 4)),
+            (sum(b[i] * c[i] * Ac[i] for i in range(S)), Fr(1, 8)),
+            (sum(b[i] * Acc[i] for i in range(S)), Fr(1, 12)),
+            (sum(b[i] * AAc[i] for i in range(S)), Fr(1, 24))],
+    }
+    return [lhs == rhs for p in range(1, order + 1) for lhs, rhs in conds[p]]
+
+
+def test_paper_parameters_in_controller_defaults():
+    pp = _paper_params()
+    c = I.Controls()
+    assert (c.k1, c.k2, c.k3, c.order) == (pp["pid_a1"], pp["pid_a2"], pp["pid_a3"], pp["pid_order"])
+    assert len(I.ZONNEVELD["b"]) == pp["erk_stages"]
+
+
+def test_zonneveld_order_conditions():
+    t = I.ZONNEVELD
+    A = _full_A(t)
+    # row sums equal c (consistency of the abscissae)
+    assert all(sum(A[i]) == t["c"][i] for i in range(5))
+    assert all(_order_conditions(t["b"], A, t["c"], 4))
+    assert all(_order_conditions(t["bt"], A, t["c"], 3))
+    assert not all(_order_conditions(t["bt"], A, t["c"], 4))   # embedding is exactly order 3
+
+
+def test_rk4_and_knoth_wolke_order_conditions():
+    A = _full_A(I.RK4)
+    assert all(_order_conditions(I.RK4["b"], A, I.RK4["c"], 4))
+    kw = I.KNOTH_WOLKE3
+    A = _full_A(kw)
+    assert all(sum(A[i]) == kw["c"][i] for i in range(3))
+    assert all(_order_conditions(kw["b"], A, kw["c"], 3))
+
+
+def test_mis_coupling_telescopes_to_base_weights():
+    chat, Om = I.mis_coupling(I.KNOTH_WOLKE3)
+    assert chat == [0, Fr(1, 3), Fr(3, 4), 1]
+    # the slow increments of all stages add up to b (consistency, order 1)
+    tot = [sum(Om[i][j] for i in range(4)) for j in range(3)]
+    assert tot == I.KNOTH_WOLKE3["b"]
+    # stage i's cumulative coupling equals row i of A (reduces to the ERK)
+    A = _full_A(I.KNOTH_WOLKE3)
+    for i in range(1, 3):
+        assert [sum(Om[m][j] for m in range(i + 1)) for j in range(3)] == A[i]
+    # the printed last row (b - A_{S-1}) would break consistency
+    bad = [I.KNOTH_WOLKE3["b"][j] - A[1][j] for j in range(3)]
+    assert [Om[1][j] + Om[2][j] + bad[j] for j in range(3)] != I.KNOTH_WOLKE3["b"]
+
+
+def _stab_poly(b, A):
+    """Stability polynomial coefficients of b^T (I - zA)^{-1} 1 (exact)."""
+    S = len(b)
+    coeffs = [Fr(1)]
+    v = [Fr(1)] * S   # A^k 1
+    for _ in range(S):
+        coeffs.append(sum(b[i] * v[i] for i in range(S)))
+        v = [sum(A[i][j] * v[j] for j in range(S)) for i in range(S)]
+    return coeffs
+
+
+def test_rk4_exact_discrete_solution_on_relaxation():
+    """On y' = -(y - y_eq)/tau, RK4 gives y_n - y_eq = (y_0 - y_eq) R(z)^n with
+    R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24, z = -h/tau."""
+    for make in (problems.pp_rta, problems.eph_rta):
+        P, y0, n = make(scale=50.0)
+        o = oracle.Oracle(P)
+        rows = np.arange(n) + (1 if make is problems.pp_rta else 0)
+        lam, yeq = problems.linear_fit(o.rhs, y0, rows)
+        h = 0.4 / np.max(-lam)
+        y = y0.copy()
+        for _ in range(40):
+            y = I.rk4_step(o.rhs, y, h)
+        z = lam * h
+        R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+        expect = yeq + (y0[rows] - yeq) * R ** 40
+        assert np.allclose(y[rows], expect, rtol=1e-12, atol=0)
+        # bath states untouched
+        mask = np.ones(len(y0), bool); mask[rows] = False
+        assert np.array_equal(y[mask], y0[mask])
+
+
+def test_zonneveld_solution_and_lte_closed_forms():
+    """Main solution R(z) = RK4 polynomial; LTE = (R(z) - Rtilde(z)) (y - y_eq)
+    with both polynomials from the tableau, and R - Rtilde = -(z^4 + z^5)/24."""
+    A = _full_A(I.ZONNEVELD)
+    R = _stab_poly(I.ZONNEVELD["b"], A)
+    Rt = _stab_poly(I.ZONNEVELD["bt"], A)
+    assert R[:5] == [1, 1, Fr(1, 2), Fr(1, 6), Fr(1, 24)] and R[5] == 0
+    diff = [R[i] - Rt[i] for i in range(6)]
+    assert diff == [0, 0, 0, 0, Fr(-1, 24), Fr(-1, 24)]
+    P, y0, n = problems.pp_rta(scale=50.0)
+    o = oracle.Oracle(P)
+    rows = np.arange(1, 1 + n)
+    lam, yeq = problems.linear_fit(o.rhs, y0, rows)
+    h = 0.7 / np.max(-lam)
+    ynew, lte = I.erk_attempt(o.rhs, y0, h)
+    z = lam * h
+    assert np.allclose(ynew[rows] - yeq, (y0[rows] - yeq) * sum(float(R[i]) * z ** i for i in range(6)),
+                       rtol=1e-12, atol=0)
+    assert np.allclose(lte[rows], -(z ** 4 + z ** 5) / 24 * (y0[rows] - yeq), rtol=1e-9, atol=0)
+
+
+def test_wrms_norm_definition():
+    v = np.array([3.0, -4.0])
+    y = np.array([1.0, 0.0])
+    # w = 1/(rtol|y| + atol): (1/(0.5+1), 1/1) -> sqrt(((3/1.5)^2 + 4^2)/2)
+    assert np.isclose(I.wrms(v, y, 0.5, np.array([1.0, 1.0])), np.sqrt((4.0 + 16.0) / 2), rtol=1e-15)
+
+
+def test_pid_properties():
+    c = I.Controls()
+    # unit error history and unit error: the ratio is the safety factor
+    assert I.pid_eta(1.0, 1.0, 1.0, True, False, c) == pytest.approx(c.safety, rel=1e-15)
+    # scaling law in the current error: eta ~ eps^(-k1/p)
+    r = I.pid_eta(0.01, 0.3, 0.2, True, False, c) / I.pid_eta(0.02, 0.3, 0.2, True, False, c)
+    assert r == pytest.approx(2.0 ** (c.k1 / c.order), rel=1e-13)
+    # printed form: every exponent negative -> larger past errors shrink the step
+    assert I.pid_eta(0.5, 0.9, 1.0, True, False, c) < I.pid_eta(0.5, 0.1, 1.0, True, False, c)
+    assert I.pid_eta(0.5, 1.0, 0.9, True, False, c) < I.pid_eta(0.5, 1.0, 0.1, True, False, c)
+    # alternate sign on eps_{k-1}
+    ca = I.Controls(alt_sign=True)
+    assert I.pid_eta(0.5, 0.9, 1.0, True, False, ca) > I.pid_eta(0.5, 0.1, 1.0, True, False, ca)
+    # growth limits and rejection band
+    assert I.pid_eta(1e-30, 1.0, 1.0, True, False, c) == c.eta_max
+    # below the error floor the ratio no longer grows; on the first step it may exceed eta_max
+    assert I.pid_eta(1e-30, 1.0, 1.0, True, True, c) == I.pid_eta(c.eps_floor, 1.0, 1.0, True, True, c)
+    assert c.eta_max < I.pid_eta(1e-30, 1.0, 1.0, True, True, c) <= c.eta_max_first
+    assert I.pid_eta(1e12, 1.0, 1.0, False, False, c) == c.eta_fail_min
+    assert I.pid_eta(1.01, 1.0, 1.0, False, False, c) == c.eta_fail_max
+
+
+def test_adaptive_meets_tolerance_on_relaxation():
+    """Global error of the adaptive ERK on a linear relaxation problem stays
+    within a small multiple of the tolerance and shrinks with it."""
+    P, y0, n = problems.pp_rta(scale=50.0)
+    o = oracle.Oracle(P)
+    rows = np.arange(1, 1 + n)
+    lam, yeq = problems.linear_fit(o.rhs, y0, rows)
+    T = 3.0 / np.min(-lam)
+    exact = yeq + (y0[rows] - yeq) * np.exp(lam * T)
+    errs = []
+    for rtol in (1e-4, 1e-6, 1e-8):
+        c = I.Controls(rtol=rtol, atol_ph=1e-14, atol_el=1e-14)
+        a = I.Adaptive(rhs=o.rhs, atol_vec=np.full(len(y0), 1e-14), c=c)
+        y, t = a.advance(y0.copy(), 0.0, T)
+        assert t == T
+        errs.append(np.max(np.abs(y[rows] - exact) / np.abs(exact)))
+        assert errs[-1] < 50 * rtol
+        assert a.n_accept > 3
+    assert errs[0] > errs[1] > errs[2]
+
+
+def test_adaptive_replay_reproduces_run():
+    wl = synth.build("toy2d")
+    o = oracle.Oracle(wl.problem_arrays())
+    atol = np.concatenate([np.full(wl.n_el, 1e-9), np.full(wl.n_ph, 1e-12)])
+    a = I.Adaptive(rhs=o.rhs, atol_vec=atol, c=I.Controls(rtol=1e-5))
+    y, t = a.advance(wl.y0.copy(), 0.0, 20.0)
+    hs = [h for (_, h, _) in a.history]
+    assert abs(sum(hs) - 20.0) < 1e-12
+    y2 = I.replay(o.rhs, wl.y0.copy(), hs)
+    assert np.array_equal(y, y2)
+
+
+def _coupled_problem(scale_eph=0.03, scale_pp=0.003):
+    """tiny2d with fast e-ph (spectral radius ~0.27/fs) and slow ph-ph (~0.027/fs), from
+    random populations so that every part is active."""
+    wl = synth.build("tiny2d")
+    P = dict(wl.problem_arrays())
+    P["eph_g2"] = P["eph_g2"] * scale_eph
+    P["pp_v2"] = P["pp_v2"] * scale_pp
+    rng = np.random.default_rng(17)
+    wl.y0 = np.concatenate([rng.uniform(0.05, 0.95, wl.n_el), rng.uniform(0.0, 2.0, wl.n_ph)])
+    return wl, oracle.Oracle(P)
+
+
+def test_rk4_and_mis_convergence_orders():
+    wl, o = _coupled_problem()
+    fast = lambda v: o.rhs(v, parts=3)
+    slow = lambda v: o.rhs(v, parts=4)
+    full = lambda v: o.rhs(v, parts=7)
+    T = 40.0
+    # reference: RK4 with a tiny step
+    yref = wl.y0.copy()
+    for _ in range(3200):
+        yref = I.rk4_step(full, yref, T / 3200)
+    errs_rk4, errs_mis = [], []
+    for m in (8, 16, 32):
+        h = T / m
+        y = wl.y0.copy()
+        for _ in range(m):
+            y = I.rk4_step(full, y, h)
+        errs_rk4.append(np.linalg.norm(y - yref))
+        y = wl.y0.copy()
+        solver = I.rk4_fixed_solver(h / 64)
+        for _ in range(m):
+            y = I.mis_step(fast, slow, y, h, solver)
+        errs_mis.append(np.linalg.norm(y - yref))
+    p_rk4 = np.log2(errs_rk4[1] / errs_rk4[2])
+    p_mis = np.log2(errs_mis[1] / errs_mis[2])
+    assert 3.6 < p_rk4 < 4.6, errs_rk4
+    assert 2.6 < p_mis < 3.6, errs_mis
+
+
+def test_embedded_order_three():
+    wl, o = _coupled_problem()
+    full = lambda v: o.rhs(v, parts=7)
+    T = 40.0
+    yref = wl.y0.copy()
+    for _ in range(3200):
+        yref = I.rk4_step(full, yref, T / 3200)
+    errs = []
+    for m in (32, 64, 128):
+        y = wl.y0.copy()
+        for _ in range(m):
+            ynew, lte = I.erk_attempt(full, y, T / m)
+            y = ynew - lte          # the embedded solution
+        errs.append(np.linalg.norm(y - yref))
+    p = np.log2(errs[1] / errs[2])
+    assert 2.6 < p < 3.6, errs
+
+
+def test_mis_reduces_to_base_erk_without_fast_part():
+    wl, o = _coupled_problem()
+    slow = lambda v: o.rhs(v, parts=4)
+    zero = lambda v: np.zeros_like(v)
+    h = 3.0
+    y_mis = I.mis_step(zero, slow, wl.y0.copy(), h, I.rk4_fixed_solver(h / 7))
+    kw = dict(I.KNOTH_WOLKE3)
+    kw = dict(c=kw["c"], A=kw["A"], b=kw["b"], bt=kw["b"])
+    y_erk, _ = I.erk_attempt(slow, wl.y0.copy(), h, tab=kw)
+    assert np.allclose(y_mis, y_erk, rtol=0, atol=1e-15 * np.abs(wl.y0).max())
+
+
+def test_mis_reduces_to_fast_integrator_without_slow_part():
+    wl, o = _coupled_problem()
+    fast = lambda v: o.rhs(v, parts=3)
+    zero = lambda v: np.zeros_like(v)
+    h = 3.0
+    hf = 0.25
+    y_mis = I.mis_step(fast, zero, wl.y0.copy(), h, I.rk4_fixed_solver(hf))
+    # the same fast integrator over the three stage intervals
+    y = wl.y0.copy()
+    solver = I.rk4_fixed_solver(hf)
+    for a, b in ((0.0, 1.0), (1.0, 2.25), (2.25, 3.0)):
+        y = solver(y, a, b, fast)
+    assert np.array_equal(y_mis, y)
+
+
+def test_nonfinite_state_fails_the_step():
+    wl = synth.build("toy2d")
+    o = oracle.Oracle(wl.problem_arrays())
+    y = wl.y0.copy(); y[3] = np.nan
+    atol = np.full(wl.n_y, 1e-9)
+    a = I.Adaptive(rhs=o.rhs, atol_vec=atol, c=I.Controls(), h=0.1)
+    with pytest.raises(I.StepFailure):
+        a.advance(y, 0.0, 1.0)
+
+
+def test_too_many_failures_raise():
+    wl = synth.build("toy2d")
+    o = oracle.Oracle(wl.problem_arrays())
+    atol = np.full(wl.n_y, 1e-30)
+    a = I.Adaptive(rhs=o.rhs, atol_vec=atol, c=I.Controls(rtol=1e-15, max_fails=1), h=5.0)
+    with pytest.raises(I.StepFailure):
+        a.advance(wl.y0.copy(), 0.0, 10.0)
