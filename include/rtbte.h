@@ -1,0 +1,209 @@
+/*
+ * rtbte -- collision integrals and time integrators of the coupled
+ * electron-phonon real-time Boltzmann equation on AMD MI355X (gfx950).
+ *
+ * The problem (paper: Eq. (bte)) is
+ *     df_nk/dt  = I^{e-ph}[f, N]_nk
+ *     dN_nuq/dt = I^{ph-e}[f, N]_nuq + I^{ph-ph}[N]_nuq
+ * with the collision integrals of Methods, Eq. (e-ph) and Eq. (ph-ph), the
+ * Gaussian delta_sigma(E) = exp(-(E/sigma)^2)/(sigma sqrt(pi)) truncated at
+ * |E| <= nsigma*sigma, and a phonon frequency cutoff hw_cut (Methods, grid-size
+ * paragraphs).  The state vector is y = [f; N] (Eq. (state_vec)); the
+ * integrators are the adaptive embedded ERK method with WRMS error norm and
+ * PID step control (Methods, ERK method) and the third-order MIS multirate
+ * method with e-ph as the fast and ph-ph as the slow part (Eq. (mri_rhs),
+ * Methods, MRI method).
+ *
+ * Conventions
+ *   - Energies in eV, times in fs.  hbar = 0.6582119569 eV fs.
+ *   - All arrays in rtbte_problem are HOST memory, read during rtbte_create
+ *     and deep-copied; the caller may free them on return.
+ *   - y, ydot, t, h arguments of the stepping calls are caller-owned DEVICE
+ *     buffers of doubles on the context's device.  y holds the instances
+ *     back to back at the offsets reported by rtbte_layout; within an
+ *     instance it is [f (n_el); N (n_ph)].  t, h hold one entry per instance.
+ *   - All device work is enqueued on the HIP stream passed in (NULL: the
+ *     null stream).  Calls that return results to the host synchronise that
+ *     stream; rtbte_rhs does not.
+ *   - Every call returns an RTBTE_* status; no C++ exception crosses the ABI.
+ *     rtbte_last_error(ctx) describes the last failure (ctx may be NULL for
+ *     a failed create).  A context is not thread-safe; distinct contexts are
+ *     independent.
+ */
+#ifndef RTBTE_H
+#define RTBTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RTBTE_OK = 0,
+  RTBTE_E_INVAL = -1,       /* bad argument or problem data                         */
+  RTBTE_E_NOMEM = -2,       /* host or device allocation failed                     */
+  RTBTE_E_HIP = -3,         /* a HIP runtime call failed                            */
+  RTBTE_E_STEP = -4,        /* more than max_fails consecutive error-test failures  */
+  RTBTE_E_NONFINITE = -5,   /* a non-finite error estimate (NaN/Inf in the state)   */
+  RTBTE_E_UNSUPPORTED = -6  /* option combination not implemented                   */
+};
+
+/* Parts of the right-hand side (Eq. (erk_rhs)); OR them together. */
+enum {
+  RTBTE_PART_EPH = 1,   /* I^{e-ph}: electron rows                         */
+  RTBTE_PART_PHE = 2,   /* I^{ph-e}: phonon rows, e-ph absorption channels */
+  RTBTE_PART_PHPH = 4,  /* I^{ph-ph}: phonon rows, three-phonon channels   */
+  RTBTE_PART_ALL = 7
+};
+
+enum { RTBTE_FP64 = 0, RTBTE_MIXED = 1 };
+
+typedef struct rtbte_ctx rtbte_ctx;
+
+/* One rt-BTE instance, stated as in Methods, Eq. (e-ph) and Eq. (ph-ph).
+ *   n_el          windowed electron states (n,k) kept in the dynamics
+ *   n_ph          phonon states (nu,q)
+ *   n_k_total,    sizes of the FULL k and q grids: the 1/N_k and 1/N_q
+ *   n_q_total     prefactors use them even when a window keeps fewer states
+ *   eps[n_el]     band energies eps_nk (eV)
+ *   hw[n_ph]      phonon energies hbar*omega_nuq (eV)
+ *   n_eph entries of the e-ph matrix, one per process nk -> mk+q with
+ *                 phonon nu q:  eph_row = nk, eph_partner = mk+q,
+ *                 eph_phonon = nu q, eph_g2 = |g_mn nu(k,q)|^2 (eV^2).
+ *                 Each entry gives an emission and an absorption channel on
+ *                 the electron side (kept when its energy mismatch is within
+ *                 nsigma*sigma_eph) and, for a kept absorption channel, one
+ *                 phonon-side I^{ph-e} channel in row nu q.
+ *   n_pp entries  of the ph-ph matrix, one per ordered (lambda; lambda',
+ *                 lambda'') with q + q' + q'' = 0: pp_row = lambda,
+ *                 pp_a = lambda', pp_b = lambda'', pp_v2 = |V3|^2 (eV^2).
+ *                 Each gives an emission channel (delta(-hw + hw' + hw''))
+ *                 and an absorption channel (factor 2, delta(hw - hw' + hw'')).
+ *   sigma_eph, sigma_pp   Gaussian widths (eV) > 0
+ *   nsigma        truncation in units of sigma (> 0)
+ *   hw_cut        channels touching a phonon with hw < hw_cut are dropped
+ * Channels of one destination row are summed in the order their entries
+ * appear in the input; listing partners in grid order keeps the gathers of
+ * the populations local.
+ */
+typedef struct {
+  int32_t n_el, n_ph;
+  int32_t n_k_total, n_q_total;
+  const double *eps, *hw;
+  int64_t n_eph;
+  const int32_t *eph_row, *eph_partner, *eph_phonon;
+  const double *eph_g2;
+  int64_t n_pp;
+  const int32_t *pp_row, *pp_a, *pp_b;
+  const double *pp_v2;
+  double sigma_eph, sigma_pp, nsigma, hw_cut;
+} rtbte_problem;
+
+/* Options; rtbte_default_options fills every field. */
+typedef struct {
+  int32_t precision;       /* RTBTE_FP64 (default) or RTBTE_MIXED                           */
+  int32_t device;          /* HIP device ordinal                                           */
+  /* ERK error test (Eq. (wrms_weights)): w_i = 1/(rtol |y_i| + atol_i),
+     atol_i = atol_el on electron components and atol_ph on phonon components */
+  double rtol, atol_el, atol_ph;
+  /* MIS fast integrator: 0 adaptive ERK with fast_* tolerances, 1 fixed RK4
+     with step h_fast (the last substep of a stage interval is shortened) */
+  int32_t fast_mode;
+  double h_fast;
+  double fast_rtol, fast_atol_el, fast_atol_ph;
+  /* PID controller (Eq. (pid_controller)): h' = h * safety * eps_k^(-k1/p) *
+     eps_{k-1}^(-k2/p) * eps_{k-2}^(-k3/p); pid_alt_sign = 1 uses +k2/p.
+     Ratio limited to <= eta_max (eta_max_first on the first step) after an
+     accepted step and to [eta_fail_min, eta_fail_max] after a rejected one;
+     errors below eps_floor count as eps_floor. */
+  double pid_k1, pid_k2, pid_k3;
+  int32_t pid_order, pid_alt_sign;
+  double safety, eta_max, eta_max_first, eta_fail_min, eta_fail_max, eps_floor;
+  int32_t max_fails;
+  int32_t use_graph;        /* replay each step through a captured HIP graph (1) or launch (0) */
+  int32_t steps_per_poll;   /* steps enqueued between host checks of the done flags           */
+  int32_t threads_per_row;  /* 0: tuned/auto; else 16, 32, 64, 128 or 256 lanes per row     */
+  int32_t tune;             /* 1: time the launch shapes at create and keep the fastest      */
+  const char *tune_cache;   /* file caching tuning results (NULL: env RTBTE_TUNE_CACHE)       */
+} rtbte_options;
+
+typedef struct {
+  int64_t n_rhs_eph, n_rhs_phe, n_rhs_phph; /* evaluations of each part                 */
+  int64_t n_accept, n_reject;               /* ERK (or MIS slow) steps of this instance */
+  int64_t n_fast_accept, n_fast_reject;     /* fast steps inside MIS                    */
+  double t, h_last, h_min, h_max, eps_last;
+  int32_t status;                           /* RTBTE_* status of the last stepping call */
+} rtbte_stats;
+
+void rtbte_default_options(rtbte_options *opts);
+
+/* Build a context for n_inst independent instances (problems[0..n_inst)).
+ * Computes every channel weight (delta, prefactor, cutoff), derives the
+ * I^{ph-e} lists, groups channels by destination row and uploads them.
+ * Errors: RTBTE_E_INVAL (index out of range, sigma <= 0, nsigma <= 0,
+ * negative counts, n_inst < 1), RTBTE_E_NOMEM, RTBTE_E_HIP. */
+int rtbte_create(const rtbte_problem *problems, int32_t n_inst, const rtbte_options *opts,
+                 rtbte_ctx **out);
+void rtbte_destroy(rtbte_ctx *ctx);
+const char *rtbte_last_error(const rtbte_ctx *ctx);
+
+/* Offset of instance `inst` in y, and its sizes. */
+int rtbte_layout(const rtbte_ctx *ctx, int32_t inst, int64_t *y_offset, int32_t *n_el,
+                 int32_t *n_ph);
+/* Total length of y over all instances. */
+int64_t rtbte_ny(const rtbte_ctx *ctx);
+/* Stored channels of instance `inst` (-1: all): counts[0] electron-side e-ph
+ * (emission + absorption), counts[1] phonon-side ph-e, counts[2] ph-ph. */
+int rtbte_counts(const rtbte_ctx *ctx, int32_t inst, int64_t counts[3]);
+
+/* ydot = the parts of f(y) selected by `parts` (Eq. (erk_rhs); parts of
+ * Eq. (mri_rhs)).  Rows a part does not touch are written with 0.  y and ydot
+ * are device arrays of rtbte_ny() doubles and must not overlap. */
+int rtbte_rhs(rtbte_ctx *ctx, const double *y, double *ydot, int32_t parts, void *stream);
+
+/* Adaptive Zonneveld 4(3) ERK (Methods, ERK method) on the full RHS, every
+ * instance with its own t, step size and PID history, until every instance
+ * reaches t_out (one_step = 0) or has taken one accepted step (one_step = 1).
+ * y (device) is updated in place; t[inst] and h[inst] (device) hold the
+ * current time and the next step size on return.  h[inst] <= 0 asks for a
+ * starting step (Hairer-Norsett-Wanner estimate).  The PID error history is
+ * kept in the context between calls (rtbte_reset clears it).
+ * On RTBTE_E_STEP / RTBTE_E_NONFINITE, y and t hold the last accepted state. */
+int rtbte_step_adaptive(rtbte_ctx *ctx, double *y, double *t, double *h, double t_out,
+                        int32_t one_step, void *stream);
+
+/* Fixed-step classical RK4 on the full RHS (the prior-work baseline):
+ * n_steps steps of size h_step from *t (device t, one entry per instance). */
+int rtbte_step_rk4(rtbte_ctx *ctx, double *y, double *t, double h_step, int64_t n_steps,
+                   void *stream);
+
+/* Third-order MIS multirate method (Methods, MRI method; Eq. (mis_coef) with
+ * the Knoth-Wolke 3-stage base method): slow part I^{ph-ph} at fixed step
+ * h_slow, fast part I^{e-ph} + I^{ph-e} integrated over each stage interval
+ * with forcing, by the fast integrator chosen in the options.  Advances to
+ * t_out (the last slow step is shortened to land on it) or by one slow step
+ * (one_step = 1).  h_fast[inst] (device) carries the adaptive fast step.
+ * Only n_inst == 1 contexts support it (RTBTE_E_UNSUPPORTED otherwise). */
+int rtbte_step_multirate(rtbte_ctx *ctx, double *y, double *t, double *h_fast, double t_out,
+                         double h_slow, int32_t one_step, void *stream);
+
+/* Clear the integrator state kept between calls (PID histories, counters). */
+int rtbte_reset(rtbte_ctx *ctx);
+int rtbte_get_stats(const rtbte_ctx *ctx, int32_t inst, rtbte_stats *out);
+
+/* Launch shape in use: lanes per destination row. */
+int rtbte_get_tuning(const rtbte_ctx *ctx, int32_t *threads_per_row);
+
+/* Checkpoint of the integrator state kept in the context (PID histories,
+ * step sizes, counters; not y, which the caller owns).  With buf == NULL,
+ * *len receives the size needed. */
+int rtbte_get_state(const rtbte_ctx *ctx, void *buf, size_t *len);
+int rtbte_set_state(rtbte_ctx *ctx, const void *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTBTE_H */

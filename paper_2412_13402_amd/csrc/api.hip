@@ -1,0 +1,955 @@
+// rtbte C ABI: context creation (channel preparation), right-hand side, and
+// the device-driven integrators (adaptive ERK, fixed RK4, MIS multirate).
+//
+// Host code here does bookkeeping only: argument checks, integer grouping of
+// the input entries by destination row, buffer management, and the launch
+// sequence.  Every floating-point step of the method -- channel weights,
+// collision integrals, stage updates, error norms, step control -- runs in the
+// kernels of kernels.hip.
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rtbte.h"
+#include "internal.h"
+
+using namespace rtbte;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Zonneveld 5-stage pair (main order 4, embedding order 3), the default ERK of
+// the integrators the paper uses (Methods, ERK method).
+const double ZA[5][5] = {{0, 0, 0, 0, 0},
+                         {0.5, 0, 0, 0, 0},
+                         {0, 0.5, 0, 0, 0},
+                         {0, 0, 1.0, 0, 0},
+                         {5.0 / 32, 7.0 / 32, 13.0 / 32, -1.0 / 32, 0}};
+const double ZB[5] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6, 0.0};
+const double ZBT[5] = {-0.5, 7.0 / 3, 7.0 / 3, 13.0 / 6, -16.0 / 3};
+
+// Classical RK4.
+const double RA[4][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1.0, 0}};
+const double RB[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+
+// MIS with the Knoth-Wolke 3-stage base method: abscissae c_hat = (0, 1/3, 3/4, 1)
+// and the constant forcing of stage i, r_i = sum_j (Omega_ij / dc_i) f^s(z_j),
+// Omega from Eq. (mis_coef) (last row b_j - A_{S,j}).
+const double MIS_C[4] = {0.0, 1.0 / 3, 3.0 / 4, 1.0};
+const double MIS_R[4][3] = {{0, 0, 0},
+                            {1.0, 0, 0},
+                            {-5.0 / 4, 9.0 / 4, 0},
+                            {17.0 / 12, -51.0 / 20, 32.0 / 15}};
+
+struct Tableau {
+  int S;
+  double A[5][5], b[5], d[5];
+  bool embedded;
+};
+
+Tableau zonneveld() {
+  Tableau t{};
+  t.S = 5;
+  for (int i = 0; i < 5; ++i) {
+    for (int j = 0; j < 5; ++j) t.A[i][j] = ZA[i][j];
+    t.b[i] = ZB[i];
+    t.d[i] = ZB[i] - ZBT[i];
+  }
+  t.embedded = true;
+  return t;
+}
+
+Tableau rk4() {
+  Tableau t{};
+  t.S = 4;
+  for (int i = 0; i < 4; ++i) {
+    for (int j = 0; j < 4; ++j) t.A[i][j] = RA[i][j];
+    t.b[i] = RB[i];
+    t.d[i] = 0.0;
+  }
+  t.embedded = false;
+  return t;
+}
+
+template <class T>
+T* dalloc(size_t n, hipError_t* err) {
+  void* p = nullptr;
+  *err = hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
+  return static_cast<T*>(p);
+}
+
+}  // namespace
+
+struct rtbte_ctx {
+  int device = 0;
+  rtbte_options opt{};
+  std::string err;
+  int n_inst = 0;
+  std::vector<InstInfo> info;
+  int64_t ny = 0;
+  std::vector<int64_t> counts;     // [3 * n_inst]
+  int64_t n_ch = 0;
+  int tpr = 64;
+  int nchunk = 1;
+  // device
+  Channel* ch = nullptr;
+  int64_t* ptr = nullptr;
+  int64_t* split = nullptr;
+  uint32_t* order = nullptr;
+  int32_t* row_inst = nullptr;
+  InstInfo* info_d = nullptr;
+  InstState* st = nullptr;       // main integrator
+  InstState* st_fast = nullptr;  // MIS fast integrator
+  double* kbuf[5] = {};
+  double* zb[2] = {};
+  double* ynew = nullptr;
+  double* lte = nullptr;
+  double* tmp = nullptr;
+  double* tmp2 = nullptr;
+  double* fs[3] = {};
+  double* forcing = nullptr;
+  double* partial = nullptr;     // [3][n_inst * nchunk]
+  double* tvec = nullptr;        // [2 * n_inst] scratch t / h for inner solves
+  int32_t* summary_d = nullptr;
+  int32_t* summary_h = nullptr;  // pinned
+  double* scal_h = nullptr;      // pinned host scalars
+  // host tallies of right-hand-side evaluations outside the predicated step loop
+  int64_t extra_rhs[3] = {0, 0, 0};
+  int64_t slow_steps = 0;
+  int last_status = 0;
+};
+
+static int fail(rtbte_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP, "%s: %s", \
+                  #expr, hipGetErrorString(e_));                                           \
+  } while (0)
+
+extern "C" {
+
+void rtbte_default_options(rtbte_options* o) {
+  std::memset(o, 0, sizeof *o);
+  o->precision = RTBTE_FP64;
+  o->device = 0;
+  o->rtol = 1e-6;
+  o->atol_el = 1e-9;
+  o->atol_ph = 1e-12;
+  o->fast_mode = 0;
+  o->h_fast = 1.0;
+  o->fast_rtol = 1e-5;
+  o->fast_atol_el = 1e-9;
+  o->fast_atol_ph = 1e-11;
+  o->pid_k1 = 0.58;
+  o->pid_k2 = 0.21;
+  o->pid_k3 = 0.10;
+  o->pid_order = 4;
+  o->pid_alt_sign = 0;
+  o->safety = 0.96;
+  o->eta_max = 20.0;
+  o->eta_max_first = 1e4;
+  o->eta_fail_min = 0.1;
+  o->eta_fail_max = 0.9;
+  o->eps_floor = 1e-10;
+  o->max_fails = 7;
+  o->use_graph = 0;
+  o->steps_per_poll = 8;
+  o->threads_per_row = 0;
+  o->tune = 0;
+  o->tune_cache = nullptr;
+}
+
+const char* rtbte_last_error(const rtbte_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- create
+namespace {
+
+// Stable grouping of n keys in [0, nkeys) (counting sort).  Returns the
+// visiting permutation (empty if the keys are already non-decreasing) and the
+// group pointers.
+void group_keys(int64_t n, const int32_t* key, int32_t nkeys, std::vector<int64_t>& perm,
+                std::vector<int64_t>& gptr) {
+  gptr.assign((size_t)nkeys + 1, 0);
+  bool sorted = true;
+  for (int64_t i = 0; i < n; ++i) {
+    gptr[(size_t)key[i] + 1]++;
+    if (i && key[i] < key[i - 1]) sorted = false;
+  }
+  for (int32_t k = 0; k < nkeys; ++k) gptr[k + 1] += gptr[k];
+  perm.clear();
+  if (sorted) return;
+  perm.resize((size_t)n);
+  const int nt = std::max(1, omp_get_max_threads());
+  // per-thread histograms over contiguous chunks keep the order stable
+  std::vector<std::vector<int64_t>> cur((size_t)nt);
+  const int64_t chunk = (n + nt - 1) / nt;
+#pragma omp parallel num_threads(nt)
+  {
+    const int t = omp_get_thread_num();
+    std::vector<int64_t>& h = cur[t];
+    h.assign((size_t)nkeys, 0);
+    const int64_t lo = std::min(n, t * chunk), hi = std::min(n, lo + chunk);
+    for (int64_t i = lo; i < hi; ++i) h[key[i]]++;
+  }
+  for (int32_t k = 0; k < nkeys; ++k) {
+    int64_t pos = gptr[k];
+    for (int t = 0; t < nt; ++t) {
+      int64_t c = cur[t][k];
+      cur[t][k] = pos;
+      pos += c;
+    }
+  }
+#pragma omp parallel num_threads(nt)
+  {
+    const int t = omp_get_thread_num();
+    std::vector<int64_t>& h = cur[t];
+    const int64_t lo = std::min(n, t * chunk), hi = std::min(n, lo + chunk);
+    for (int64_t i = lo; i < hi; ++i) perm[h[key[i]]++] = i;
+  }
+}
+
+int check_problem(const rtbte_problem& p, int inst) {
+  if (p.n_el < 0 || p.n_ph < 0 || p.n_eph < 0 || p.n_pp < 0)
+    return fail(nullptr, RTBTE_E_INVAL, "instance %d: negative size", inst);
+  if (p.n_k_total <= 0 || p.n_q_total <= 0)
+    return fail(nullptr, RTBTE_E_INVAL, "instance %d: n_k_total and n_q_total must be > 0", inst);
+  if (!(p.sigma_eph > 0) || !(p.sigma_pp > 0) || !(p.nsigma > 0))
+    return fail(nullptr, RTBTE_E_INVAL, "instance %d: sigma and nsigma must be > 0", inst);
+  if ((p.n_el && !p.eps) || (p.n_ph && !p.hw))
+    return fail(nullptr, RTBTE_E_INVAL, "instance %d: missing energies", inst);
+  if (p.n_eph && (!p.eph_row || !p.eph_partner || !p.eph_phonon || !p.eph_g2))
+    return fail(nullptr, RTBTE_E_INVAL, "instance %d: missing e-ph arrays", inst);
+  if (p.n_pp && (!p.pp_row || !p.pp_a || !p.pp_b || !p.pp_v2))
+    return fail(nullptr, RTBTE_E_INVAL, "instance %d: missing ph-ph arrays", inst);
+  int64_t bad = -1;
+#pragma omp parallel for reduction(max : bad)
+  for (int64_t i = 0; i < p.n_eph; ++i)
+    if (p.eph_row[i] < 0 || p.eph_row[i] >= p.n_el || p.eph_partner[i] < 0 ||
+        p.eph_partner[i] >= p.n_el || p.eph_phonon[i] < 0 || p.eph_phonon[i] >= p.n_ph)
+      bad = std::max(bad, i);
+  if (bad >= 0) return fail(nullptr, RTBTE_E_INVAL, "instance %d: e-ph entry %lld out of range", inst, (long long)bad);
+#pragma omp parallel for reduction(max : bad)
+  for (int64_t i = 0; i < p.n_pp; ++i)
+    if (p.pp_row[i] < 0 || p.pp_row[i] >= p.n_ph || p.pp_a[i] < 0 || p.pp_a[i] >= p.n_ph ||
+        p.pp_b[i] < 0 || p.pp_b[i] >= p.n_ph)
+      bad = std::max(bad, i);
+  if (bad >= 0) return fail(nullptr, RTBTE_E_INVAL, "instance %d: ph-ph entry %lld out of range", inst, (long long)bad);
+  return RTBTE_OK;
+}
+
+struct DevRaw {
+  int32_t *er = nullptr, *es = nullptr, *ep = nullptr, *pr = nullptr, *pa = nullptr, *pb = nullptr;
+  double *eg = nullptr, *pv = nullptr, *eps = nullptr, *hw = nullptr;
+  int64_t *perm_e = nullptr, *perm_pe = nullptr, *perm_pp = nullptr;
+  int64_t *ptr_e = nullptr, *ptr_pe = nullptr, *ptr_pp = nullptr;
+  int64_t *cnt_e = nullptr, *cnt_pe = nullptr, *cnt_pp = nullptr;
+  int64_t *base_e = nullptr, *base_pe = nullptr, *base_pp = nullptr;
+  void release() {
+    void* ps[] = {er, es, ep, pr, pa, pb, eg, pv, eps, hw, perm_e, perm_pe, perm_pp, ptr_e, ptr_pe,
+                  ptr_pp, cnt_e, cnt_pe, cnt_pp, base_e, base_pe, base_pp};
+    for (void* p : ps)
+      if (p) (void)hipFree(p);
+    *this = DevRaw{};
+  }
+};
+
+template <class T>
+hipError_t upload(T** d, const T* h, size_t n) {
+  hipError_t e = hipMalloc((void**)d, std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (n) e = hipMemcpy(*d, h, n * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+void free_ctx(rtbte_ctx* c) {
+  if (!c) return;
+  void* ps[] = {c->ch, c->ptr, c->split, c->order, c->row_inst, c->info_d, c->st, c->st_fast,
+                c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
+                c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
+                c->partial, c->tvec, c->summary_d};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  if (c->summary_h) (void)hipHostFree(c->summary_h);
+  if (c->scal_h) (void)hipHostFree(c->scal_h);
+  delete c;
+}
+
+int choose_tpr(const rtbte_ctx* c) {
+  if (c->opt.threads_per_row) return c->opt.threads_per_row;
+  const double avg = c->ny ? (double)c->n_ch / (double)c->ny : 0.0;
+  if (avg < 48) return 16;
+  if (avg < 192) return 32;
+  return 64;
+}
+
+}  // namespace
+
+extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const rtbte_options* opts,
+                            rtbte_ctx** out) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, RTBTE_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!problems || n_inst < 1) return fail(nullptr, RTBTE_E_INVAL, "need n_inst >= 1 problems");
+  rtbte_options o;
+  if (opts) o = *opts;
+  else rtbte_default_options(&o);
+  if (o.precision != RTBTE_FP64)
+    return fail(nullptr, RTBTE_E_UNSUPPORTED, "precision %d not available in this build", o.precision);
+  const int tprs[] = {0, 16, 32, 64, 128, 256};
+  if (std::find(std::begin(tprs), std::end(tprs), o.threads_per_row) == std::end(tprs))
+    return fail(nullptr, RTBTE_E_INVAL, "threads_per_row must be 0, 16, 32, 64, 128 or 256");
+  if (!(o.rtol >= 0) || !(o.atol_el >= 0) || !(o.atol_ph >= 0) || o.pid_order <= 0 ||
+      o.steps_per_poll < 1 || o.max_fails < 0)
+    return fail(nullptr, RTBTE_E_INVAL, "invalid tolerances or controller options");
+  for (int i = 0; i < n_inst; ++i) {
+    int rc = check_problem(problems[i], i);
+    if (rc) return rc;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(nullptr, RTBTE_E_HIP, "no HIP device available");
+  if (o.device < 0 || o.device >= ndev) return fail(nullptr, RTBTE_E_INVAL, "device %d out of range", o.device);
+  if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, RTBTE_E_HIP, "hipSetDevice failed");
+
+  rtbte_ctx* c = new rtbte_ctx();
+  c->device = o.device;
+  c->opt = o;
+  c->n_inst = n_inst;
+  c->info.resize(n_inst);
+  int64_t off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    c->info[i].off = off;
+    c->info[i].n_el = problems[i].n_el;
+    c->info[i].n_ph = problems[i].n_ph;
+    off += (int64_t)problems[i].n_el + problems[i].n_ph;
+  }
+  c->ny = off;
+  if (c->ny >= (int64_t)kIdxMask) {
+    free_ctx(c);
+    return fail(nullptr, RTBTE_E_INVAL, "state vector too long (%lld)", (long long)off);
+  }
+  c->counts.assign(3 * (size_t)n_inst, 0);
+
+  // Pass 1: upload raw entries and count kept channels per destination row.
+  std::vector<DevRaw> raws((size_t)n_inst);
+  std::vector<std::vector<int64_t>> cnt_e(n_inst), cnt_pe(n_inst), cnt_pp(n_inst);
+  auto cleanup = [&](int code) {
+    for (auto& r : raws) r.release();
+    std::string msg = c->err;
+    free_ctx(c);
+    if (!msg.empty()) g_create_error = msg;
+    return code;
+  };
+  std::vector<PrepArgs> pe(n_inst), ppe(n_inst), ppp(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const rtbte_problem& p = problems[i];
+    DevRaw& d = raws[i];
+    std::vector<int64_t> perm, gptr;
+    hipError_t e = hipSuccess;
+#define UP(dst, src, n)                                                             \
+  do {                                                                              \
+    e = upload(&(dst), (src), (size_t)(n));                                         \
+    if (e != hipSuccess) {                                                          \
+      fail(c, e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP, "upload: %s", \
+           hipGetErrorString(e));                                                   \
+      return cleanup(e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP);       \
+    }                                                                               \
+  } while (0)
+    UP(d.eps, p.eps, p.n_el);
+    UP(d.hw, p.hw, p.n_ph);
+    UP(d.er, p.eph_row, p.n_eph);
+    UP(d.es, p.eph_partner, p.n_eph);
+    UP(d.ep, p.eph_phonon, p.n_eph);
+    UP(d.eg, p.eph_g2, p.n_eph);
+    UP(d.pr, p.pp_row, p.n_pp);
+    UP(d.pa, p.pp_a, p.n_pp);
+    UP(d.pb, p.pp_b, p.n_pp);
+    UP(d.pv, p.pp_v2, p.n_pp);
+    // electron side: group by electron row
+    group_keys(p.n_eph, p.eph_row, p.n_el, perm, gptr);
+    if (!perm.empty()) UP(d.perm_e, perm.data(), perm.size());
+    UP(d.ptr_e, gptr.data(), gptr.size());
+    // phonon side: the same entries grouped by phonon
+    group_keys(p.n_eph, p.eph_phonon, p.n_ph, perm, gptr);
+    if (!perm.empty()) UP(d.perm_pe, perm.data(), perm.size());
+    UP(d.ptr_pe, gptr.data(), gptr.size());
+    // ph-ph: group by phonon row
+    group_keys(p.n_pp, p.pp_row, p.n_ph, perm, gptr);
+    if (!perm.empty()) UP(d.perm_pp, perm.data(), perm.size());
+    UP(d.ptr_pp, gptr.data(), gptr.size());
+#undef UP
+    d.cnt_e = dalloc<int64_t>(p.n_el, &e);
+    if (e == hipSuccess) d.cnt_pe = dalloc<int64_t>(p.n_ph, &e);
+    if (e == hipSuccess) d.cnt_pp = dalloc<int64_t>(p.n_ph, &e);
+    if (e != hipSuccess) {
+      fail(c, RTBTE_E_NOMEM, "count buffers: %s", hipGetErrorString(e));
+      return cleanup(RTBTE_E_NOMEM);
+    }
+    const double pre_el = (2.0 * kPi / kHbarEvFs) / (double)p.n_q_total;
+    const double pre_ph = (4.0 * kPi / kHbarEvFs) / (double)p.n_k_total;
+    const double pre_pp = (36.0 * kPi / kHbarEvFs) / (double)p.n_q_total;
+    PrepArgs a{};
+    a.eps = d.eps;
+    a.hw = d.hw;
+    a.y_off = c->info[i].off;
+    a.n_el = p.n_el;
+    a.hw_cut = p.hw_cut;
+    // e-ph electron side
+    a.row = d.er; a.i0 = d.es; a.i1 = d.ep; a.val = d.eg; a.perm = d.perm_e; a.raw_ptr = d.ptr_e;
+    a.n_dest = p.n_el; a.sigma = p.sigma_eph; a.cut = p.nsigma * p.sigma_eph; a.pre = pre_el;
+    a.pre2 = pre_el; a.kind = 0; a.count = d.cnt_e;
+    pe[i] = a;
+    // ph-e
+    a.perm = d.perm_pe; a.raw_ptr = d.ptr_pe; a.n_dest = p.n_ph; a.pre = pre_ph; a.pre2 = pre_ph;
+    a.kind = 1; a.count = d.cnt_pe;
+    ppe[i] = a;
+    // ph-ph
+    a.row = d.pr; a.i0 = d.pa; a.i1 = d.pb; a.val = d.pv; a.perm = d.perm_pp; a.raw_ptr = d.ptr_pp;
+    a.n_dest = p.n_ph; a.sigma = p.sigma_pp; a.cut = p.nsigma * p.sigma_pp; a.pre = pre_pp;
+    a.pre2 = 2.0 * pre_pp; a.kind = 2; a.count = d.cnt_pp;
+    ppp[i] = a;
+    e = launch_prep_count(pe[i], 0);
+    if (e == hipSuccess) e = launch_prep_count(ppe[i], 0);
+    if (e == hipSuccess) e = launch_prep_count(ppp[i], 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    cnt_e[i].resize(p.n_el);
+    cnt_pe[i].resize(p.n_ph);
+    cnt_pp[i].resize(p.n_ph);
+    if (e == hipSuccess && p.n_el) e = hipMemcpy(cnt_e[i].data(), d.cnt_e, p.n_el * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && p.n_ph) e = hipMemcpy(cnt_pe[i].data(), d.cnt_pe, p.n_ph * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && p.n_ph) e = hipMemcpy(cnt_pp[i].data(), d.cnt_pp, p.n_ph * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      fail(c, RTBTE_E_HIP, "channel count: %s", hipGetErrorString(e));
+      return cleanup(RTBTE_E_HIP);
+    }
+  }
+
+  // Row pointers over the concatenated state vector.
+  std::vector<int64_t> hptr((size_t)c->ny + 1, 0), hsplit((size_t)c->ny, 0), rowlen((size_t)c->ny, 0);
+  {
+    int64_t pos = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      const InstInfo& in = c->info[i];
+      for (int32_t r = 0; r < in.n_el; ++r) {
+        const int64_t g = in.off + r;
+        hptr[g] = pos;
+        pos += cnt_e[i][r];
+        hsplit[g] = pos;
+        rowlen[g] = cnt_e[i][r];
+        c->counts[3 * i] += cnt_e[i][r];
+      }
+      for (int32_t q = 0; q < in.n_ph; ++q) {
+        const int64_t g = in.off + in.n_el + q;
+        hptr[g] = pos;
+        pos += cnt_pe[i][q];
+        hsplit[g] = pos;
+        pos += cnt_pp[i][q];
+        rowlen[g] = cnt_pe[i][q] + cnt_pp[i][q];
+        c->counts[3 * i + 1] += cnt_pe[i][q];
+        c->counts[3 * i + 2] += cnt_pp[i][q];
+      }
+    }
+    hptr[c->ny] = pos;
+    c->n_ch = pos;
+  }
+  hipError_t e = hipSuccess;
+  c->ch = dalloc<Channel>((size_t)c->n_ch, &e);
+  if (e != hipSuccess) {
+    fail(c, RTBTE_E_NOMEM, "channel lists (%lld channels): %s", (long long)c->n_ch, hipGetErrorString(e));
+    return cleanup(RTBTE_E_NOMEM);
+  }
+  // Unwritten slots would never be read, but keep them harmless (index 0, weight 0).
+  e = hipMemset(c->ch, 0, (size_t)std::max<int64_t>(c->n_ch, 1) * sizeof(Channel));
+  if (e != hipSuccess) {
+    fail(c, RTBTE_E_HIP, "channel clear: %s", hipGetErrorString(e));
+    return cleanup(RTBTE_E_HIP);
+  }
+  // Pass 2: write the channels.
+  for (int i = 0; i < n_inst; ++i) {
+    const InstInfo& in = c->info[i];
+    DevRaw& d = raws[i];
+    std::vector<int64_t> be(in.n_el), bpe(in.n_ph), bpp(in.n_ph);
+    for (int32_t r = 0; r < in.n_el; ++r) be[r] = hptr[in.off + r];
+    for (int32_t q = 0; q < in.n_ph; ++q) {
+      bpe[q] = hptr[in.off + in.n_el + q];
+      bpp[q] = hsplit[in.off + in.n_el + q];
+    }
+    e = upload(&d.base_e, be.data(), be.size());
+    if (e == hipSuccess) e = upload(&d.base_pe, bpe.data(), bpe.size());
+    if (e == hipSuccess) e = upload(&d.base_pp, bpp.data(), bpp.size());
+    pe[i].base = d.base_e; pe[i].out = c->ch;
+    ppe[i].base = d.base_pe; ppe[i].out = c->ch;
+    ppp[i].base = d.base_pp; ppp[i].out = c->ch;
+    if (e == hipSuccess) e = launch_prep_fill(pe[i], 0);
+    if (e == hipSuccess) e = launch_prep_fill(ppe[i], 0);
+    if (e == hipSuccess) e = launch_prep_fill(ppp[i], 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      fail(c, RTBTE_E_HIP, "channel fill: %s", hipGetErrorString(e));
+      return cleanup(RTBTE_E_HIP);
+    }
+    d.release();
+  }
+
+  // Processing order: longest rows first (stable), phonon rows flagged.
+  std::vector<uint32_t> order((size_t)c->ny);
+  {
+    std::vector<int64_t> idx((size_t)c->ny);
+    for (int64_t g = 0; g < c->ny; ++g) idx[g] = g;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return rowlen[a] > rowlen[b]; });
+    std::vector<uint8_t> isph((size_t)c->ny, 0);
+    for (int i = 0; i < n_inst; ++i)
+      for (int32_t q = 0; q < c->info[i].n_ph; ++q) isph[c->info[i].off + c->info[i].n_el + q] = 1;
+    for (int64_t j = 0; j < c->ny; ++j)
+      order[j] = (uint32_t)idx[j] | (isph[idx[j]] ? kPhononRowBit : 0u);
+  }
+  e = upload(&c->ptr, hptr.data(), hptr.size());
+  if (e == hipSuccess) e = upload(&c->split, hsplit.data(), hsplit.size());
+  if (e == hipSuccess) e = upload(&c->order, order.data(), order.size());
+  if (e == hipSuccess && n_inst > 1) {
+    std::vector<int32_t> ri((size_t)c->ny);
+    for (int i = 0; i < n_inst; ++i)
+      for (int64_t j = 0; j < (int64_t)c->info[i].n_el + c->info[i].n_ph; ++j) ri[c->info[i].off + j] = i;
+    e = upload(&c->row_inst, ri.data(), ri.size());
+  }
+  if (e == hipSuccess) e = upload(&c->info_d, c->info.data(), c->info.size());
+  // integrator state and work vectors
+  int64_t maxrows = 1;
+  for (auto& in : c->info) maxrows = std::max<int64_t>(maxrows, (int64_t)in.n_el + in.n_ph);
+  c->nchunk = (int)std::min<int64_t>(64, std::max<int64_t>(1, maxrows / 8192));
+  const size_t ny = (size_t)std::max<int64_t>(c->ny, 1);
+  for (int j = 0; j < 5 && e == hipSuccess; ++j) c->kbuf[j] = dalloc<double>(ny, &e);
+  for (int j = 0; j < 2 && e == hipSuccess; ++j) c->zb[j] = dalloc<double>(ny, &e);
+  for (int j = 0; j < 3 && e == hipSuccess; ++j) c->fs[j] = dalloc<double>(ny, &e);
+  if (e == hipSuccess) c->ynew = dalloc<double>(ny, &e);
+  if (e == hipSuccess) c->lte = dalloc<double>(ny, &e);
+  if (e == hipSuccess) c->tmp = dalloc<double>(ny, &e);
+  if (e == hipSuccess) c->tmp2 = dalloc<double>(ny, &e);
+  if (e == hipSuccess) c->forcing = dalloc<double>(ny, &e);
+  if (e == hipSuccess) c->partial = dalloc<double>(3 * (size_t)n_inst * c->nchunk, &e);
+  if (e == hipSuccess) c->tvec = dalloc<double>(2 * (size_t)n_inst, &e);
+  if (e == hipSuccess) c->summary_d = dalloc<int32_t>(2, &e);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->summary_h, 2 * sizeof(int32_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->scal_h, 8 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemset(c->forcing, 0, ny * sizeof(double));
+  if (e == hipSuccess) c->st = dalloc<InstState>((size_t)n_inst, &e);
+  if (e == hipSuccess) c->st_fast = dalloc<InstState>((size_t)n_inst, &e);
+  if (e != hipSuccess) {
+    fail(c, e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP, "work buffers: %s", hipGetErrorString(e));
+    return cleanup(e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP);
+  }
+  c->tpr = choose_tpr(c);
+  *out = c;
+  if (rtbte_reset(c) != RTBTE_OK) {
+    std::string msg = c->err;
+    free_ctx(c);
+    *out = nullptr;
+    return fail(nullptr, RTBTE_E_HIP, "%s", msg.c_str());
+  }
+  return RTBTE_OK;
+}
+
+extern "C" void rtbte_destroy(rtbte_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_ctx(ctx);
+}
+
+extern "C" int rtbte_reset(rtbte_ctx* c) {
+  if (!c) return RTBTE_E_INVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  std::vector<InstState> s((size_t)c->n_inst);
+  for (auto& x : s) {
+    std::memset(&x, 0, sizeof x);
+    x.e1 = x.e2 = 1.0;
+    x.first = 1;
+    x.h_min = INFINITY;
+    x.h_max = 0.0;
+    x.done = 1;
+  }
+  HIPCHK(c, hipMemcpy(c->st, s.data(), s.size() * sizeof(InstState), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->st_fast, s.data(), s.size() * sizeof(InstState), hipMemcpyHostToDevice));
+  c->extra_rhs[0] = c->extra_rhs[1] = c->extra_rhs[2] = 0;
+  c->slow_steps = 0;
+  c->last_status = 0;
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_layout(const rtbte_ctx* c, int32_t inst, int64_t* y_offset, int32_t* n_el,
+                            int32_t* n_ph) {
+  if (!c || inst < 0 || inst >= c->n_inst) return RTBTE_E_INVAL;
+  if (y_offset) *y_offset = c->info[inst].off;
+  if (n_el) *n_el = c->info[inst].n_el;
+  if (n_ph) *n_ph = c->info[inst].n_ph;
+  return RTBTE_OK;
+}
+
+extern "C" int64_t rtbte_ny(const rtbte_ctx* c) { return c ? c->ny : -1; }
+
+extern "C" int rtbte_counts(const rtbte_ctx* c, int32_t inst, int64_t counts[3]) {
+  if (!c || !counts || inst < -1 || inst >= c->n_inst) return RTBTE_E_INVAL;
+  counts[0] = counts[1] = counts[2] = 0;
+  for (int i = 0; i < c->n_inst; ++i)
+    if (inst < 0 || inst == i)
+      for (int k = 0; k < 3; ++k) counts[k] += c->counts[3 * i + k];
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_get_tuning(const rtbte_ctx* c, int32_t* tpr) {
+  if (!c || !tpr) return RTBTE_E_INVAL;
+  *tpr = c->tpr;
+  return RTBTE_OK;
+}
+
+// ------------------------------------------------------------ right-hand side
+namespace {
+
+RowArgs row_args(const rtbte_ctx* c, const double* z, int parts) {
+  RowArgs a{};
+  a.ch = c->ch;
+  a.ptr = c->ptr;
+  a.split = c->split;
+  a.order = c->order;
+  a.row_inst = c->row_inst;
+  a.n_rows = c->ny;
+  a.parts = parts;
+  a.z = z;
+  return a;
+}
+
+}  // namespace
+
+extern "C" int rtbte_rhs(rtbte_ctx* c, const double* y, double* ydot, int32_t parts, void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (!y || !ydot || parts < 1 || parts > 7) return fail(c, RTBTE_E_INVAL, "rtbte_rhs: bad arguments");
+  if (y == ydot) return fail(c, RTBTE_E_INVAL, "rtbte_rhs: y and ydot must not overlap");
+  HIPCHK(c, hipSetDevice(c->device));
+  RowArgs a = row_args(c, y, parts);
+  a.out = ydot;
+  HIPCHK(c, launch_rows(a, c->tpr, false, (hipStream_t)stream));
+  for (int k = 0; k < 3; ++k)
+    if (parts & (1 << k)) c->extra_rhs[k]++;
+  return RTBTE_OK;
+}
+
+// ---------------------------------------------------------------- integrators
+namespace {
+
+Ctl make_ctl(const rtbte_options& o, bool fast, bool fixed) {
+  Ctl t{};
+  t.k1 = o.pid_k1;
+  t.k2 = o.pid_k2;
+  t.k3 = o.pid_k3;
+  t.order = o.pid_order;
+  t.safety = o.safety;
+  t.eta_max = o.eta_max;
+  t.eta_max_first = o.eta_max_first;
+  t.eta_fail_min = o.eta_fail_min;
+  t.eta_fail_max = o.eta_fail_max;
+  t.eps_floor = o.eps_floor;
+  t.rtol = fast ? o.fast_rtol : o.rtol;
+  t.atol_el = fast ? o.fast_atol_el : o.atol_el;
+  t.atol_ph = fast ? o.fast_atol_ph : o.atol_ph;
+  t.max_fails = o.max_fails;
+  t.alt_sign = o.pid_alt_sign;
+  t.fixed = fixed ? 1 : 0;
+  t.stages = fixed ? 4 : 5;
+  return t;
+}
+
+// Enqueue one attempted step of tableau `tb` for every live instance of `st`.
+int enqueue_step(rtbte_ctx* c, double* y, int parts, const double* forcing, InstState* st,
+                 const Ctl& ctl, const Tableau& tb, hipStream_t s) {
+  RowArgs a = row_args(c, nullptr, parts);
+  a.y = y;
+  a.st = st;
+  a.forcing = forcing;
+  for (int j = 0; j < 5; ++j) a.k[j] = c->kbuf[j];
+  for (int i = 0; i < tb.S; ++i) {
+    a.z = i == 0 ? y : c->zb[i % 2];
+    a.zout = c->zb[(i + 1) % 2];
+    a.stage = i;
+    a.last = i == tb.S - 1;
+    for (int j = 0; j < 5; ++j) {
+      a.a[j] = (!a.last && j <= i) ? tb.A[i + 1][j] : 0.0;
+      a.b[j] = tb.b[j];
+      a.d[j] = tb.d[j];
+    }
+    a.ynew = c->ynew;
+    a.lte = c->lte;
+    HIPCHK(c, launch_rows(a, c->tpr, true, s));
+  }
+  if (tb.embedded) HIPCHK(c, launch_wrms(c->lte, y, c->info_d, st, c->partial, c->n_inst, c->nchunk, ctl, s));
+  HIPCHK(c, launch_control(st, c->partial, c->info_d, c->n_inst, c->nchunk, ctl, s));
+  HIPCHK(c, launch_commit(y, c->ynew, c->row_inst, st, c->ny, s));
+  return RTBTE_OK;
+}
+
+// Starting step (Hairer-Norsett-Wanner) for instances flagged need_h0.
+int enqueue_h0(rtbte_ctx* c, double* y, int parts, const double* forcing, InstState* st, const Ctl& ctl,
+               hipStream_t s) {
+  const size_t np = (size_t)c->n_inst * c->nchunk;
+  double* py = c->partial;
+  double* pf = c->partial + np;
+  RowArgs a = row_args(c, y, parts);
+  a.out = c->tmp;  // f0
+  HIPCHK(c, launch_rows(a, c->tpr, false, s));
+  if (forcing) {
+    const double* v[2] = {c->tmp, forcing};
+    const double cf[2] = {1.0, 1.0};
+    for (int i = 0; i < c->n_inst; ++i)
+      HIPCHK(c, launch_lincomb(c->tmp, v, cf, 2, c->info[i].off + c->info[i].n_el, c->info[i].n_ph, s));
+  }
+  HIPCHK(c, launch_wrms(y, y, c->info_d, nullptr, py, c->n_inst, c->nchunk, ctl, s));
+  HIPCHK(c, launch_wrms(c->tmp, y, c->info_d, nullptr, pf, c->n_inst, c->nchunk, ctl, s));
+  HIPCHK(c, launch_h0_stage1(st, py, pf, c->info_d, c->n_inst, c->nchunk, s));
+  HIPCHK(c, launch_h0_axpy(c->zb[0], y, c->tmp, c->row_inst, st, c->ny, s));
+  a.z = c->zb[0];
+  a.out = c->tmp2;  // f1
+  HIPCHK(c, launch_rows(a, c->tpr, false, s));
+  if (forcing) {
+    const double* v[2] = {c->tmp2, forcing};
+    const double cf[2] = {1.0, 1.0};
+    for (int i = 0; i < c->n_inst; ++i)
+      HIPCHK(c, launch_lincomb(c->tmp2, v, cf, 2, c->info[i].off + c->info[i].n_el, c->info[i].n_ph, s));
+  }
+  HIPCHK(c, launch_sub(c->tmp2, c->tmp2, c->tmp, c->ny, s));
+  HIPCHK(c, launch_wrms(c->tmp2, y, c->info_d, nullptr, py, c->n_inst, c->nchunk, ctl, s));
+  HIPCHK(c, launch_h0_stage2(st, py, c->info_d, c->n_inst, c->nchunk, (double)c->opt.pid_order, s));
+  for (int k = 0; k < 3; ++k)
+    if (parts & (1 << k)) c->extra_rhs[k] += 2;
+  return RTBTE_OK;
+}
+
+int poll(rtbte_ctx* c, InstState* st, double* t, double* h, hipStream_t s, bool* all_done, int* worst) {
+  HIPCHK(c, launch_finish(st, t, h, c->n_inst, c->summary_d, s));
+  HIPCHK(c, hipMemcpyAsync(c->summary_h, c->summary_d, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  *all_done = c->summary_h[0] != 0;
+  *worst = c->summary_h[1];
+  return RTBTE_OK;
+}
+
+// Run an integrator on `st` until every instance is done.
+int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_step, int parts,
+        const double* forcing, InstState* st, const Ctl& ctl, const Tableau& tb, double h_cap,
+        int64_t fixed_steps, double fixed_h, hipStream_t s) {
+  HIPCHK(c, launch_begin(st, t, h, c->n_inst, t_out, one_step, h_cap, fixed_steps, fixed_h, s));
+  if (h && fixed_steps <= 0) {
+    std::vector<double> hh((size_t)c->n_inst);
+    HIPCHK(c, hipMemcpyAsync(hh.data(), h, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    bool need = false;
+    for (double v : hh) need |= !(v > 0.0);
+    if (need) {
+      int rc = enqueue_h0(c, y, parts, forcing, st, ctl, s);
+      if (rc) return rc;
+    }
+  }
+  const int per_poll = one_step ? 1 : c->opt.steps_per_poll;
+  bool done = false;
+  int worst = 0;
+  while (!done) {
+    for (int m = 0; m < per_poll; ++m) {
+      int rc = enqueue_step(c, y, parts, forcing, st, ctl, tb, s);
+      if (rc) return rc;
+    }
+    int rc = poll(c, st, t, h, s, &done, &worst);
+    if (rc) return rc;
+  }
+  c->last_status = worst;
+  if (worst == RTBTE_E_STEP) return fail(c, RTBTE_E_STEP, "too many consecutive error-test failures");
+  if (worst == RTBTE_E_NONFINITE) return fail(c, RTBTE_E_NONFINITE, "non-finite error estimate");
+  return RTBTE_OK;
+}
+
+}  // namespace
+
+extern "C" int rtbte_step_adaptive(rtbte_ctx* c, double* y, double* t, double* h, double t_out,
+                                   int32_t one_step, void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (!y || !t || !h || !std::isfinite(t_out)) return fail(c, RTBTE_E_INVAL, "step_adaptive: bad arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Ctl ctl = make_ctl(c->opt, false, false);
+  return run(c, y, t, h, t_out, one_step ? 1 : 0, RTBTE_PART_ALL, nullptr, c->st, ctl, zonneveld(), 0.0,
+             0, 0.0, (hipStream_t)stream);
+}
+
+extern "C" int rtbte_step_rk4(rtbte_ctx* c, double* y, double* t, double h_step, int64_t n_steps,
+                              void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (!y || !t || !(h_step > 0) || n_steps < 0) return fail(c, RTBTE_E_INVAL, "step_rk4: bad arguments");
+  if (n_steps == 0) return RTBTE_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const Ctl ctl = make_ctl(c->opt, false, true);
+  return run(c, y, t, nullptr, 0.0, 0, RTBTE_PART_ALL, nullptr, c->st, ctl, rk4(), 0.0, n_steps, h_step,
+             (hipStream_t)stream);
+}
+
+extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* h_fast, double t_out,
+                                    double h_slow, int32_t one_step, void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (c->n_inst != 1) return fail(c, RTBTE_E_UNSUPPORTED, "multirate stepping needs a single instance");
+  if (!y || !t || !h_fast || !(h_slow > 0) || !std::isfinite(t_out))
+    return fail(c, RTBTE_E_INVAL, "step_multirate: bad arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const bool fixed = c->opt.fast_mode == 1;
+  if (fixed && !(c->opt.h_fast > 0)) return fail(c, RTBTE_E_INVAL, "fixed fast mode needs h_fast > 0");
+  const Ctl ctl = make_ctl(c->opt, true, fixed);
+  const Tableau tb = fixed ? rk4() : zonneveld();
+  const InstInfo& in = c->info[0];
+  const int64_t phoff = in.off + in.n_el;
+  // host copy of t
+  HIPCHK(c, hipMemcpyAsync(c->scal_h, t, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->scal_h + 1, h_fast, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  double tc = c->scal_h[0];
+  double* t_in = c->tvec;      // fast solver time (device scalar)
+  double* h_in = c->tvec + 1;  // fast solver step (device scalar)
+  HIPCHK(c, hipMemcpyAsync(h_in, h_fast, sizeof(double), hipMemcpyDeviceToDevice, s));
+  while (tc < t_out) {
+    double hs = h_slow;
+    const bool last = tc + hs >= t_out;
+    if (last) hs = t_out - tc;
+    // slow right-hand side at z_1
+    RowArgs a = row_args(c, y, RTBTE_PART_PHPH);
+    a.out = c->fs[0];
+    HIPCHK(c, launch_rows(a, c->tpr, false, s));
+    c->extra_rhs[2]++;
+    for (int i = 1; i < 4; ++i) {
+      const double* v[3] = {c->fs[0], c->fs[1], c->fs[2]};
+      HIPCHK(c, launch_lincomb(c->forcing, v, MIS_R[i], i, phoff, in.n_ph, s));
+      const double t0 = tc + MIS_C[i - 1] * hs, t1 = tc + MIS_C[i] * hs;
+      c->scal_h[2] = t0;
+      HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 2, sizeof(double), hipMemcpyHostToDevice, s));
+      int rc;
+      if (!fixed) {
+        rc = run(c, y, t_in, h_in, t1, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl, tb,
+                 t1 - t0, 0, 0.0, s);
+      } else {
+        // fixed RK4 substeps of h_fast, the last one cut to land on t1
+        int64_t nfull = 0;
+        double tt = t0;
+        while (tt < t1) {
+          if (tt + c->opt.h_fast >= t1) break;
+          tt += c->opt.h_fast;
+          ++nfull;
+        }
+        rc = RTBTE_OK;
+        if (nfull > 0)
+          rc = run(c, y, t_in, nullptr, 0.0, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl,
+                   tb, 0.0, nfull, c->opt.h_fast, s);
+        if (rc == RTBTE_OK && t1 - tt > 0) {
+          c->scal_h[3] = tt;
+          HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 3, sizeof(double), hipMemcpyHostToDevice, s));
+          rc = run(c, y, t_in, nullptr, 0.0, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl,
+                   tb, 0.0, 1, t1 - tt, s);
+        }
+      }
+      if (rc) return rc;
+      if (i < 3) {
+        a.z = y;
+        a.out = c->fs[i];
+        HIPCHK(c, launch_rows(a, c->tpr, false, s));
+        c->extra_rhs[2]++;
+      }
+    }
+    tc = last ? t_out : tc + hs;
+    c->slow_steps++;
+    if (one_step) break;
+  }
+  c->scal_h[4] = tc;
+  HIPCHK(c, hipMemcpyAsync(t, c->scal_h + 4, sizeof(double), hipMemcpyHostToDevice, s));
+  if (!fixed) HIPCHK(c, hipMemcpyAsync(h_fast, h_in, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* out) {
+  if (!c || !out || inst < 0 || inst >= c->n_inst) return RTBTE_E_INVAL;
+  InstState s, f;
+  if (hipSetDevice(c->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(&s, c->st + inst, sizeof s, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&f, c->st_fast + inst, sizeof f, hipMemcpyDeviceToHost) != hipSuccess)
+    return RTBTE_E_HIP;
+  std::memset(out, 0, sizeof *out);
+  out->n_accept = s.n_accept;
+  out->n_reject = s.n_reject;
+  out->n_fast_accept = f.n_accept;
+  out->n_fast_reject = f.n_reject;
+  const int64_t main_evals = s.n_evals, fast_evals = f.n_evals;
+  out->n_rhs_eph = main_evals + fast_evals + c->extra_rhs[0];
+  out->n_rhs_phe = main_evals + fast_evals + c->extra_rhs[1];
+  out->n_rhs_phph = main_evals + c->extra_rhs[2];
+  out->t = s.t;
+  out->h_last = s.h;
+  out->h_min = s.h_min;
+  out->h_max = s.h_max;
+  out->eps_last = s.eps;
+  out->status = c->last_status;
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_get_state(const rtbte_ctx* c, void* buf, size_t* len) {
+  if (!c || !len) return RTBTE_E_INVAL;
+  const size_t need = 2 * (size_t)c->n_inst * sizeof(InstState) + 4 * sizeof(int64_t);
+  if (!buf) {
+    *len = need;
+    return RTBTE_OK;
+  }
+  if (*len < need) return RTBTE_E_INVAL;
+  char* p = (char*)buf;
+  if (hipSetDevice(c->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(p, c->st, c->n_inst * sizeof(InstState), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(p + c->n_inst * sizeof(InstState), c->st_fast, c->n_inst * sizeof(InstState),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return RTBTE_E_HIP;
+  int64_t tail[4] = {c->extra_rhs[0], c->extra_rhs[1], c->extra_rhs[2], c->slow_steps};
+  std::memcpy(p + 2 * c->n_inst * sizeof(InstState), tail, sizeof tail);
+  *len = need;
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_set_state(rtbte_ctx* c, const void* buf, size_t len) {
+  if (!c || !buf) return RTBTE_E_INVAL;
+  const size_t need = 2 * (size_t)c->n_inst * sizeof(InstState) + 4 * sizeof(int64_t);
+  if (len != need) return fail(c, RTBTE_E_INVAL, "state size %zu, expected %zu", len, need);
+  const char* p = (const char*)buf;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipMemcpy(c->st, p, c->n_inst * sizeof(InstState), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->st_fast, p + c->n_inst * sizeof(InstState), c->n_inst * sizeof(InstState),
+                      hipMemcpyHostToDevice));
+  int64_t tail[4];
+  std::memcpy(tail, p + 2 * c->n_inst * sizeof(InstState), sizeof tail);
+  c->extra_rhs[0] = tail[0];
+  c->extra_rhs[1] = tail[1];
+  c->extra_rhs[2] = tail[2];
+  c->slow_steps = tail[3];
+  return RTBTE_OK;
+}

@@ -1,0 +1,119 @@
+// Internal declarations shared by the rtbte host code and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rtbte {
+
+constexpr double kHbarEvFs = 0.6582119569;          // eV fs
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.7724538509055160273;
+constexpr uint32_t kEmBit = 0x80000000u;            // channel kind bit: emission
+constexpr uint32_t kIdxMask = 0x7fffffffu;
+constexpr uint32_t kPhononRowBit = 0x80000000u;     // row-order flag: phonon row
+
+// A stored channel, 16 bytes, streamed once per right-hand-side evaluation.
+//   electron row r  (I^{e-ph}):  i0 = partner electron s, i1 = phonon p | em bit
+//   phonon row p, ph-e range     i0 = electron r,         i1 = electron s (absorption)
+//   phonon row l, ph-ph range    i0 = phonon a,           i1 = phonon b | em bit
+// Indices are positions in the concatenated state vector y; w already holds
+// prefactor * |M|^2 * delta (and the factor 2 of ph-ph absorption).
+struct Channel {
+  int32_t i0;
+  uint32_t i1;
+  double w;
+};
+static_assert(sizeof(Channel) == 16, "channel must be 16 bytes");
+
+// Per-instance integrator state, resident on the device.
+struct InstState {
+  double t, t_out, t_start, h, h_use, h_cap, e1, e2, eps, h_min, h_max, h0_d0, h0_d1;
+  int32_t first, fails, done, status, accepted, last, one_step, need_h0;
+  int64_t n_accept, n_reject, n_attempt, n_evals, steps_left;
+};
+
+struct InstInfo {
+  int64_t off;   // offset of the instance in y
+  int32_t n_el, n_ph;
+};
+
+// Controller constants (PID of Eq. (pid_controller) and its safeguards).
+struct Ctl {
+  double k1, k2, k3, order, safety, eta_max, eta_max_first, eta_fail_min, eta_fail_max, eps_floor;
+  double rtol, atol_el, atol_ph;
+  int32_t max_fails, alt_sign, fixed;  // fixed: fixed step, every step accepted
+  int32_t stages;                      // right-hand-side evaluations per attempt
+};
+
+// Arguments of the destination-row kernel.
+struct RowArgs {
+  const Channel* ch;
+  const int64_t* ptr;       // [n_rows + 1] row starts
+  const int64_t* split;     // [n_rows] end of the ph-e range (phonon rows); = end for electron rows
+  const uint32_t* order;    // [n_rows] processing order; bit 31 marks phonon rows
+  const int32_t* row_inst;  // [n_rows] instance of each row, or nullptr (single instance)
+  int64_t n_rows;
+  int32_t parts;
+  const double* z;          // populations the integrals are evaluated at
+  double* out;              // plain mode: f(z)
+  // stage mode
+  const double* y;          // y_{n-1}
+  double* k[5];             // stage derivatives k_j (k[stage] written)
+  double* zout;             // next stage state (not last)
+  double* ynew;             // last stage: candidate solution
+  double* lte;              // last stage: local error estimate
+  const double* forcing;    // MIS forcing added on phonon rows, or nullptr
+  const InstState* st;
+  double a[5], b[5], d[5];  // z_{i+1} = y + h sum_j a_j k_j; ynew = y + h sum b_j k_j; lte = h sum d_j k_j
+  int32_t stage, last;
+};
+
+// Launchers (kernels.hip)
+hipError_t launch_rows(const RowArgs& a, int tpr, bool stage_mode, hipStream_t s);
+hipError_t launch_wrms(const double* v, const double* y, const InstInfo* info, const InstState* st,
+                       double* partial, int n_inst, int nchunk, Ctl c, hipStream_t s);
+hipError_t launch_control(InstState* st, const double* partial, const InstInfo* info, int n_inst,
+                          int nchunk, Ctl c, hipStream_t s);
+hipError_t launch_commit(double* y, const double* ynew, const int32_t* row_inst,
+                         const InstState* st, int64_t n, hipStream_t s);
+hipError_t launch_begin(InstState* st, const double* t_in, const double* h_in, int n_inst,
+                        double t_out, int one_step, double h_cap, int64_t fixed_steps,
+                        double fixed_h, hipStream_t s);
+hipError_t launch_finish(const InstState* st, double* t_out_buf, double* h_out_buf, int n_inst,
+                         int32_t* summary, hipStream_t s);
+hipError_t launch_h0_stage1(InstState* st, const double* partial_y, const double* partial_f,
+                            const InstInfo* info, int n_inst, int nchunk, hipStream_t s);
+hipError_t launch_h0_axpy(double* out, const double* y, const double* f, const int32_t* row_inst,
+                          const InstState* st, int64_t n, hipStream_t s);
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
+hipError_t launch_h0_stage2(InstState* st, const double* partial_d, const InstInfo* info, int n_inst,
+                            int nchunk, double order, hipStream_t s);
+hipError_t launch_lincomb(double* out, const double* const* vecs, const double* coef, int nv,
+                          int64_t off, int64_t n, hipStream_t s);
+
+// Create-time channel preparation (kernels.hip)
+struct PrepArgs {
+  // raw entries of one instance (device), optionally visited through perm
+  const int32_t* row;
+  const int32_t* i0;
+  const int32_t* i1;
+  const double* val;
+  const int64_t* perm;      // nullptr: identity
+  const int64_t* raw_ptr;   // [n_dest + 1] raw entries of each destination row (in visiting order)
+  int32_t n_dest;
+  const double* eps;        // instance band energies (device)
+  const double* hw;         // instance phonon energies (device)
+  double sigma, cut, pre, pre2, hw_cut;
+  int64_t y_off;            // instance offset in y
+  int32_t n_el;
+  int32_t kind;             // 0 e-ph electron side, 1 ph-e, 2 ph-ph
+  int64_t* count;           // [n_dest] kept channels per row (count pass)
+  const int64_t* base;      // [n_dest] first output slot of each row (fill pass)
+  Channel* out;
+};
+hipError_t launch_prep_count(const PrepArgs& p, hipStream_t s);
+hipError_t launch_prep_fill(const PrepArgs& p, hipStream_t s);
+
+}  // namespace rtbte

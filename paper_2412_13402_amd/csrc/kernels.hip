@@ -1,0 +1,564 @@
+// HIP kernels for gfx950: collision integrals over destination-sorted channel
+// lists, ERK stage updates, WRMS reduction, step control, and the create-time
+// channel preparation.
+//
+// Collision integrals (Methods, Eq. (e-ph) and Eq. (ph-ph)).  One group of TPR
+// lanes owns one destination row of y' and streams that row's channels once,
+// 16 bytes each, with non-temporal loads; lanes stride by TPR so every load
+// instruction of a wavefront reads a contiguous block.  The two populations a
+// channel needs are gathered from the (L2-resident) state vector.  The row sum
+// is reduced inside the group (cross-lane shuffles, LDS when a row spans
+// several wavefronts); no atomics, so results are deterministic.  Rows are
+// visited in a precomputed order, longest first, so long rows never straggle
+// at the end of the grid.
+#include "internal.h"
+
+namespace rtbte {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4i ld_stream(const Channel* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p));
+}
+
+__device__ __forceinline__ double chan_w(const v4i c) { return __hiloint2double(c.w, c.z); }
+
+enum { K_EPH = 0, K_PHE = 1, K_PP = 2 };
+
+// Occupation factors (Methods, after Eq. (e-ph) and Eq. (ph-ph)), each as
+// gain - loss.  Row invariants (x, 1-x or N, N+1) are passed precomputed.
+//   e-ph, electron row r, partner s, phonon p:
+//     F_em  = f_r (1-f_s)(1+N_p) - (1-f_r) f_s N_p
+//     F_abs = f_r (1-f_s) N_p    - (1-f_r) f_s (1+N_p)
+//   ph-e, phonon row p, electrons r, s:  F_abs(f_r, f_s, N_p)
+//   ph-ph, phonon row l, partners a, b:
+//     G_em  = N (N_a+1)(N_b+1) - (N+1) N_a N_b
+//     G_abs = N (N_a+1) N_b    - (N+1) N_a (N_b+1)
+template <int KIND>
+__device__ __forceinline__ double term(const v4i c, double g0, double g1, double xr, double xr1) {
+  const double w = chan_w(c);
+  const bool em = (c.y < 0);
+  if (KIND == K_EPH) {            // xr = f_r, xr1 = 1 - f_r, g0 = f_s, g1 = N_p
+    const double n1 = g1 + 1.0;
+    const double gain = xr * (1.0 - g0) * (em ? n1 : g1);
+    const double loss = xr1 * g0 * (em ? g1 : n1);
+    return w * (gain - loss);
+  } else if (KIND == K_PHE) {     // xr = N_p, xr1 = N_p + 1, g0 = f_r, g1 = f_s
+    const double gain = g0 * (1.0 - g1) * xr;
+    const double loss = (1.0 - g0) * g1 * xr1;
+    return w * (gain - loss);
+  } else {                        // xr = N, xr1 = N + 1, g0 = N_a, g1 = N_b
+    const double b1 = g1 + 1.0;
+    const double gain = xr * (g0 + 1.0) * (em ? b1 : g1);
+    const double loss = xr1 * g0 * (em ? g1 : b1);
+    return w * (gain - loss);
+  }
+}
+
+template <int TPR, int KIND>
+__device__ __forceinline__ double seg_sum(const Channel* __restrict__ ch, int64_t s, int64_t e,
+                                          int lane, const double* __restrict__ z, double xr,
+                                          double xr1) {
+  double acc0 = 0.0, acc1 = 0.0;
+  int64_t i = s + lane;
+  for (; i + 3 * TPR < e; i += 4 * TPR) {
+    const v4i c0 = ld_stream(ch + i);
+    const v4i c1 = ld_stream(ch + i + TPR);
+    const v4i c2 = ld_stream(ch + i + 2 * TPR);
+    const v4i c3 = ld_stream(ch + i + 3 * TPR);
+    const double a0 = z[c0.x], b0 = z[c0.y & kIdxMask];
+    const double a1 = z[c1.x], b1 = z[c1.y & kIdxMask];
+    const double a2 = z[c2.x], b2 = z[c2.y & kIdxMask];
+    const double a3 = z[c3.x], b3 = z[c3.y & kIdxMask];
+    acc0 += term<KIND>(c0, a0, b0, xr, xr1);
+    acc1 += term<KIND>(c1, a1, b1, xr, xr1);
+    acc0 += term<KIND>(c2, a2, b2, xr, xr1);
+    acc1 += term<KIND>(c3, a3, b3, xr, xr1);
+  }
+  for (; i < e; i += TPR) {
+    const v4i c0 = ld_stream(ch + i);
+    acc0 += term<KIND>(c0, z[c0.x], z[c0.y & kIdxMask], xr, xr1);
+  }
+  return acc0 + acc1;
+}
+
+// Sum over the TPR lanes of a group; the result is valid in the group's lane 0.
+template <int TPR>
+__device__ __forceinline__ double group_sum(double v, double* red) {
+  constexpr int W = TPR < 64 ? TPR : 64;
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  if (TPR > 64) {
+    const int wave = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    if ((threadIdx.x % TPR) == 0) {
+      v = 0.0;
+      for (int j = 0; j < TPR / 64; ++j) v += red[wave + j];
+    }
+  }
+  return v;
+}
+
+template <int TPR, bool STAGE>
+__global__ __launch_bounds__(256) void k_rows(RowArgs a) {
+  constexpr int RPB = 256 / TPR;
+  __shared__ double red[4];
+  const int lane = threadIdx.x % TPR;
+  const int64_t gi = (int64_t)blockIdx.x * RPB + threadIdx.x / TPR;
+  bool active = gi < a.n_rows;
+  const uint32_t ro = active ? a.order[gi] : 0u;
+  const int64_t row = ro & kIdxMask;
+  const bool phonon = (ro & kPhononRowBit) != 0;
+  const int inst = (active && a.row_inst) ? a.row_inst[row] : 0;
+  if (STAGE && active && a.st[inst].done) active = false;
+  double acc = 0.0;
+  if (active) {
+    const double xr = a.z[row];
+    const int64_t s = a.ptr[row], m = a.split[row], e = a.ptr[row + 1];
+    if (!phonon) {
+      if (a.parts & 1) acc = seg_sum<TPR, K_EPH>(a.ch, s, e, lane, a.z, xr, 1.0 - xr);
+    } else {
+      if (a.parts & 2) acc = seg_sum<TPR, K_PHE>(a.ch, s, m, lane, a.z, xr, xr + 1.0);
+      if (a.parts & 4) acc += seg_sum<TPR, K_PP>(a.ch, m, e, lane, a.z, xr, xr + 1.0);
+    }
+  }
+  acc = group_sum<TPR>(acc, red);
+  if (!active || lane != 0) return;
+  double kv = -acc;
+  if (!STAGE) {
+    a.out[row] = kv;
+    return;
+  }
+  if (a.forcing && phonon) kv += a.forcing[row];
+  const double h = a.st[inst].h_use;
+  const double yr = a.y[row];
+  a.k[a.stage][row] = kv;
+  if (!a.last) {
+    double sum = 0.0;
+    for (int j = 0; j < a.stage; ++j) sum += a.a[j] * a.k[j][row];
+    sum += a.a[a.stage] * kv;
+    a.zout[row] = yr + h * sum;
+  } else {
+    double sb = 0.0, sd = 0.0;
+    for (int j = 0; j < a.stage; ++j) {
+      const double kj = a.k[j][row];
+      sb += a.b[j] * kj;
+      sd += a.d[j] * kj;
+    }
+    sb += a.b[a.stage] * kv;
+    sd += a.d[a.stage] * kv;
+    a.ynew[row] = yr + h * sb;
+    a.lte[row] = h * sd;
+  }
+}
+
+template <int TPR>
+static hipError_t launch_rows_t(const RowArgs& a, bool stage, hipStream_t s) {
+  constexpr int RPB = 256 / TPR;
+  const int64_t nb = (a.n_rows + RPB - 1) / RPB;
+  if (nb == 0) return hipSuccess;
+  if (stage)
+    hipLaunchKernelGGL((k_rows<TPR, true>), dim3((unsigned)nb), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_rows<TPR, false>), dim3((unsigned)nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows(const RowArgs& a, int tpr, bool stage, hipStream_t s) {
+  switch (tpr) {
+    case 16: return launch_rows_t<16>(a, stage, s);
+    case 32: return launch_rows_t<32>(a, stage, s);
+    case 64: return launch_rows_t<64>(a, stage, s);
+    case 128: return launch_rows_t<128>(a, stage, s);
+    case 256: return launch_rows_t<256>(a, stage, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------------ WRMS norm
+// Partial sums of (v_i w_i)^2, w_i = 1/(rtol |y_i| + atol_i) (Eq. (wrms_norm),
+// Eq. (wrms_weights)); grid (nchunk, n_inst), fixed summation order.
+__global__ __launch_bounds__(256) void k_wrms(const double* __restrict__ v, const double* __restrict__ y,
+                                              const InstInfo* info, const InstState* st,
+                                              double* partial, int nchunk, Ctl c) {
+  __shared__ double red[4];
+  const int inst = blockIdx.y;
+  if (st && st[inst].done) return;
+  const InstInfo in = info[inst];
+  const int64_t n = (int64_t)in.n_el + in.n_ph;
+  const int64_t cs = (n + nchunk - 1) / nchunk;
+  const int64_t lo = (int64_t)blockIdx.x * cs;
+  const int64_t hi = lo + cs < n ? lo + cs : n;
+  double acc = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double atol = i < in.n_el ? c.atol_el : c.atol_ph;
+    const double q = v[in.off + i] / (c.rtol * fabs(y[in.off + i]) + atol);
+    acc += q * q;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[(int64_t)inst * nchunk + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t launch_wrms(const double* v, const double* y, const InstInfo* info, const InstState* st,
+                       double* partial, int n_inst, int nchunk, Ctl c, hipStream_t s) {
+  hipLaunchKernelGGL(k_wrms, dim3(nchunk, n_inst), dim3(256), 0, s, v, y, info, st, partial, nchunk, c);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ double wrms_total(const double* partial, int inst, int nchunk, int64_t n) {
+  double s = 0.0;
+  for (int j = 0; j < nchunk; ++j) s += partial[(int64_t)inst * nchunk + j];
+  return sqrt(s / (double)n);
+}
+
+// ------------------------------------------------------------- step control
+// PID ratio of Eq. (pid_controller) with the safeguards of the options.
+__device__ double pid_eta(double eps, double e1, double e2, bool accepted, bool first, const Ctl& c) {
+  const double e0 = fmax(eps, c.eps_floor);
+  const double s2 = c.alt_sign ? 1.0 : -1.0;
+  double eta = c.safety * pow(e0, -c.k1 / c.order) * pow(fmax(e1, c.eps_floor), s2 * c.k2 / c.order) *
+               pow(fmax(e2, c.eps_floor), -c.k3 / c.order);
+  if (accepted) return fmin(eta, first ? c.eta_max_first : c.eta_max);
+  return fmin(fmax(eta, c.eta_fail_min), c.eta_fail_max);
+}
+
+__device__ void plan_next(InstState& s) {
+  if (s.done) return;
+  const double hc = s.h_cap > 0.0 ? fmin(s.h, s.h_cap) : s.h;
+  const bool last = s.t + hc >= s.t_out;
+  s.last = last;
+  s.h_use = last ? s.t_out - s.t : hc;
+}
+
+__global__ void k_control(InstState* st, const double* partial, const InstInfo* info, int n_inst,
+                          int nchunk, Ctl c) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= n_inst) return;
+  InstState s = st[inst];
+  if (s.done) return;
+  s.n_attempt++;
+  s.n_evals += c.stages;
+  if (c.fixed) {
+    s.accepted = 1;
+    s.n_accept++;
+    s.steps_left--;
+    s.t = s.steps_left <= 0 ? s.t_out : s.t + s.h_use;
+    if (s.steps_left <= 0) s.done = 1;
+    if (!s.done) { s.h_use = s.h; s.last = s.steps_left == 1; }
+    st[inst] = s;
+    return;
+  }
+  const int64_t n = (int64_t)info[inst].n_el + info[inst].n_ph;
+  const double eps = wrms_total(partial, inst, nchunk, n);
+  s.eps = eps;
+  if (!isfinite(eps)) {
+    s.status = -5;  // RTBTE_E_NONFINITE
+    s.done = 1;
+    s.accepted = 0;
+    st[inst] = s;
+    return;
+  }
+  if (!(s.t + s.h_use > s.t)) {  // the step no longer advances time
+    s.status = -4;                // RTBTE_E_STEP
+    s.done = 1;
+    s.accepted = 0;
+    st[inst] = s;
+    return;
+  }
+  if (eps <= 1.0) {
+    s.accepted = 1;
+    const double hu = s.h_use;
+    s.h = hu * pid_eta(eps, s.e1, s.e2, true, s.first != 0, c);
+    s.e2 = s.e1;
+    s.e1 = fmax(eps, c.eps_floor);
+    s.first = 0;
+    s.fails = 0;
+    s.t = s.last ? s.t_out : s.t + hu;
+    s.n_accept++;
+    s.h_min = fmin(s.h_min, hu);
+    s.h_max = fmax(s.h_max, hu);
+    if (s.t >= s.t_out || s.one_step) s.done = 1;
+  } else {
+    s.accepted = 0;
+    s.h = s.h_use * pid_eta(eps, s.e1, s.e2, false, s.first != 0, c);
+    s.fails++;
+    s.n_reject++;
+    if (s.fails > c.max_fails) {
+      s.status = -4;  // RTBTE_E_STEP
+      s.done = 1;
+    }
+  }
+  plan_next(s);
+  st[inst] = s;
+}
+
+hipError_t launch_control(InstState* st, const double* partial, const InstInfo* info, int n_inst,
+                          int nchunk, Ctl c, hipStream_t s) {
+  hipLaunchKernelGGL(k_control, dim3((n_inst + 63) / 64), dim3(64), 0, s, st, partial, info, n_inst,
+                     nchunk, c);
+  return hipGetLastError();
+}
+
+__global__ void k_commit(double* __restrict__ y, const double* __restrict__ ynew,
+                         const int32_t* row_inst, const InstState* st, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int inst = row_inst ? row_inst[i] : 0;
+  if (st[inst].accepted) y[i] = ynew[i];
+}
+
+hipError_t launch_commit(double* y, const double* ynew, const int32_t* row_inst,
+                         const InstState* st, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_commit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, ynew, row_inst, st, n);
+  return hipGetLastError();
+}
+
+// Start of a stepping call: time, target, first step size of every instance.
+__global__ void k_begin(InstState* st, const double* t_in, const double* h_in, int n_inst, double t_out,
+                        int one_step, double h_cap, int64_t fixed_steps, double fixed_h) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= n_inst) return;
+  InstState s = st[inst];
+  s.t = t_in[inst];
+  s.t_start = s.t;
+  s.done = 0;
+  s.status = 0;
+  s.accepted = 0;
+  s.fails = 0;
+  s.one_step = one_step;
+  s.h_cap = h_cap;
+  s.need_h0 = 0;
+  if (fixed_steps > 0) {
+    s.steps_left = fixed_steps;
+    s.h = fixed_h;
+    s.h_use = fixed_h;
+    s.t_out = s.t + (double)fixed_steps * fixed_h;
+    s.last = fixed_steps == 1;
+  } else {
+    s.t_out = t_out;
+    if (h_in) {
+      if (h_in[inst] > 0.0) s.h = h_in[inst];
+      else s.need_h0 = 1;
+    }
+    if (!(s.t < s.t_out)) s.done = 1;
+    if (!s.need_h0) plan_next(s);
+  }
+  st[inst] = s;
+}
+
+hipError_t launch_begin(InstState* st, const double* t_in, const double* h_in, int n_inst,
+                        double t_out, int one_step, double h_cap, int64_t fixed_steps,
+                        double fixed_h, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin, dim3((n_inst + 63) / 64), dim3(64), 0, s, st, t_in, h_in, n_inst, t_out,
+                     one_step, h_cap, fixed_steps, fixed_h);
+  return hipGetLastError();
+}
+
+// Write t, h back and summarise: summary[0] = all done, summary[1] = worst status.
+__global__ void k_finish(const InstState* st, double* t_out_buf, double* h_out_buf, int n_inst,
+                         int32_t* summary) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int all = 1, worst = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    all &= st[i].done;
+    if (st[i].status < worst) worst = st[i].status;
+    if (t_out_buf) t_out_buf[i] = st[i].t;
+    if (h_out_buf) h_out_buf[i] = st[i].h;
+  }
+  summary[0] = all;
+  summary[1] = worst;
+}
+
+hipError_t launch_finish(const InstState* st, double* t_out_buf, double* h_out_buf, int n_inst,
+                         int32_t* summary, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, t_out_buf, h_out_buf, n_inst, summary);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------- starting step size
+// Hairer, Norsett & Wanner (Solving ODEs I, II.4), in the WRMS norm:
+// d0 = ||y0||, d1 = ||f0||, h0 = 0.01 d0/d1 (1e-6 if either < 1e-5);
+// d2 = ||f(y0 + h0 f0) - f0|| / h0; h1 = (0.01/max(d1,d2))^(1/(p+1));
+// h = min(100 h0, h1).
+__global__ void k_h0_stage1(InstState* st, const double* py, const double* pf, const InstInfo* info,
+                            int n_inst, int nchunk) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= n_inst) return;
+  InstState s = st[inst];
+  if (!s.need_h0) return;
+  const int64_t n = (int64_t)info[inst].n_el + info[inst].n_ph;
+  const double d0 = wrms_total(py, inst, nchunk, n), d1 = wrms_total(pf, inst, nchunk, n);
+  s.h0_d0 = d0;
+  s.h0_d1 = d1;
+  s.h = (d0 >= 1e-5 && d1 >= 1e-5) ? 0.01 * d0 / d1 : 1e-6;
+  st[inst] = s;
+}
+
+hipError_t launch_h0_stage1(InstState* st, const double* partial_y, const double* partial_f,
+                            const InstInfo* info, int n_inst, int nchunk, hipStream_t s) {
+  hipLaunchKernelGGL(k_h0_stage1, dim3((n_inst + 63) / 64), dim3(64), 0, s, st, partial_y, partial_f,
+                     info, n_inst, nchunk);
+  return hipGetLastError();
+}
+
+__global__ void k_h0_axpy(double* out, const double* y, const double* f, const int32_t* row_inst,
+                          const InstState* st, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int inst = row_inst ? row_inst[i] : 0;
+  out[i] = y[i] + st[inst].h * f[i];
+}
+
+hipError_t launch_h0_axpy(double* out, const double* y, const double* f, const int32_t* row_inst,
+                          const InstState* st, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_h0_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, y, f, row_inst, st, n);
+  return hipGetLastError();
+}
+
+__global__ void k_sub(double* out, const double* a, const double* b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, a, b, n);
+  return hipGetLastError();
+}
+
+__global__ void k_h0_stage2(InstState* st, const double* pd, const InstInfo* info, int n_inst, int nchunk,
+                            double order) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= n_inst) return;
+  InstState s = st[inst];
+  if (!s.need_h0) return;
+  const int64_t n = (int64_t)info[inst].n_el + info[inst].n_ph;
+  const double h0 = s.h;
+  const double d2 = wrms_total(pd, inst, nchunk, n) / h0;
+  const double m = fmax(s.h0_d1, d2);
+  const double h1 = m > 1e-15 ? pow(0.01 / m, 1.0 / (order + 1.0)) : fmax(1e-6, h0 * 1e-3);
+  s.h = fmin(100.0 * h0, h1);
+  s.need_h0 = 0;
+  plan_next(s);
+  st[inst] = s;
+}
+
+hipError_t launch_h0_stage2(InstState* st, const double* partial_d, const InstInfo* info, int n_inst,
+                            int nchunk, double order, hipStream_t s) {
+  hipLaunchKernelGGL(k_h0_stage2, dim3((n_inst + 63) / 64), dim3(64), 0, s, st, partial_d, info, n_inst,
+                     nchunk, order);
+  return hipGetLastError();
+}
+
+// out[off + i] = sum_j coef[j] * vecs[j][off + i], i < n (MIS forcing).
+struct LinComb { const double* v[4]; double c[4]; };
+__global__ void k_lincomb(double* out, LinComb lc, int nv, int64_t off, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < nv; ++j) s += lc.c[j] * lc.v[j][off + i];
+  out[off + i] = s;
+}
+
+hipError_t launch_lincomb(double* out, const double* const* vecs, const double* coef, int nv,
+                          int64_t off, int64_t n, hipStream_t s) {
+  if (nv > 4) return hipErrorInvalidValue;
+  LinComb lc{};
+  for (int j = 0; j < nv; ++j) { lc.v[j] = vecs[j]; lc.c[j] = coef[j]; }
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, lc, nv, off, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ create-time channel preparation
+// One wavefront per destination row walks the row's raw entries in input
+// order, decides which channels are kept (energy mismatch within the
+// truncation, no phonon below the cutoff), and either counts them or writes
+// them with their weights prefactor * |M|^2 * delta(mismatch).  Positions
+// inside the row come from ballots, so the output order is the input order
+// (emission before absorption for one entry).
+__device__ __forceinline__ double gdelta(double x, double sigma) {
+  const double u = x / sigma;
+  return exp(-u * u) / (sigma * kSqrtPi);
+}
+
+struct Kept { bool em, ab; double wem, wab; int32_t o0; uint32_t o1; };
+
+__device__ __forceinline__ Kept classify(const PrepArgs& p, int64_t j) {
+  Kept k{false, false, 0.0, 0.0, 0, 0u};
+  const int64_t e = p.perm ? p.perm[j] : j;
+  const int32_t r = p.row[e], a = p.i0[e], b = p.i1[e];
+  const double v = p.val[e];
+  if (p.kind == 2) {  // ph-ph: row l, partners a, b
+    const double w = p.hw[r], wa = p.hw[a], wb = p.hw[b];
+    if (w < p.hw_cut || wa < p.hw_cut || wb < p.hw_cut) return k;
+    const double x_em = -w + wa + wb;
+    const double x_ab = w - wa + wb;
+    k.em = fabs(x_em) <= p.cut;
+    k.ab = fabs(x_ab) <= p.cut;
+    if (k.em) k.wem = p.pre * v * gdelta(x_em, p.sigma);
+    if (k.ab) k.wab = p.pre2 * v * gdelta(x_ab, p.sigma);
+    const int64_t base = p.y_off + p.n_el;
+    k.o0 = (int32_t)(base + a);
+    k.o1 = (uint32_t)(base + b);
+    return k;
+  }
+  // e-ph entry: electron r -> electron a (partner) with phonon b
+  const double w = p.hw[b];
+  if (w < p.hw_cut) return k;
+  const double x_em = p.eps[r] - w - p.eps[a];
+  const double x_ab = p.eps[r] + w - p.eps[a];
+  if (p.kind == 0) {
+    k.em = fabs(x_em) <= p.cut;
+    k.ab = fabs(x_ab) <= p.cut;
+    if (k.em) k.wem = p.pre * v * gdelta(x_em, p.sigma);
+    if (k.ab) k.wab = p.pre * v * gdelta(x_ab, p.sigma);
+    k.o0 = (int32_t)(p.y_off + a);
+    k.o1 = (uint32_t)(p.y_off + p.n_el + b);
+  } else {  // ph-e: the absorption process seen from the phonon
+    k.ab = fabs(x_ab) <= p.cut;
+    if (k.ab) k.wab = p.pre * v * gdelta(x_ab, p.sigma);
+    k.o0 = (int32_t)(p.y_off + r);
+    k.o1 = (uint32_t)(p.y_off + a);
+  }
+  return k;
+}
+
+__global__ __launch_bounds__(256) void k_prep(PrepArgs p, int fill) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= p.n_dest) return;
+  const int64_t lo = p.raw_ptr[row], hi = p.raw_ptr[row + 1];
+  int64_t pos = fill ? p.base[row] : 0;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t j0 = lo; j0 < hi; j0 += 64) {
+    const int64_t j = j0 + lane;
+    Kept k{false, false, 0.0, 0.0, 0, 0u};
+    if (j < hi) k = classify(p, j);
+    const unsigned long long bem = __ballot(k.em), bab = __ballot(k.ab);
+    if (fill) {
+      int64_t my = pos + __popcll(bem & below) + __popcll(bab & below);
+      if (k.em) { p.out[my] = Channel{k.o0, k.o1 | kEmBit, k.wem}; ++my; }
+      if (k.ab) p.out[my] = Channel{k.o0, k.o1, k.wab};
+    }
+    pos += __popcll(bem) + __popcll(bab);
+  }
+  if (!fill && lane == 0) p.count[row] = pos;
+}
+
+hipError_t launch_prep_count(const PrepArgs& p, hipStream_t s) {
+  if (p.n_dest == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((p.n_dest + 3) / 4)), dim3(256), 0, s, p, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_fill(const PrepArgs& p, hipStream_t s) {
+  if (p.n_dest == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)((p.n_dest + 3) / 4)), dim3(256), 0, s, p, 1);
+  return hipGetLastError();
+}
+
+}  // namespace rtbte

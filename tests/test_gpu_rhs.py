@@ -1,0 +1,185 @@
+"""GPU parity of the collision integrals (HIP library vs the FP64 oracle).
+
+Every row of f(y) from rtbte_rhs must match the oracle to 1e-12 relative to
+the row's magnitude sum, and to 1e-12 normwise.  Inputs are the seeded
+synthetic workloads plus random populations; cases span many tiles, ragged
+row tails, every launch shape, empty lists and multi-instance contexts.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import assert_rows_close, say, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def medium2d():
+    grid = dict(dim=2, L=24, lattice=1, n_bands=2, n_modes=6, t_hop=3.09, win_lo=-10.0, win_hi=10.0,
+                with_eph=1, with_pp=1, shell_eph=0.13, shell_pp=0.013, keep_eph=1.0, keep_pp=0.5,
+                g2_mu=-6.5, g2_sig=1.0, v2_mu=-16.0, v2_sig=1.0)
+    prob = dict(sigma_eph=0.020, sigma_pp=0.002, nsigma=6.0, hw_cut=0.001)
+    return synth.generate(grid, prob, dict(T_el=4000.0, T_ph=300.0), seed=synth.MASTER_SEED + 21,
+                          name="medium2d")
+
+
+@functools.lru_cache(maxsize=None)
+def workload(name):
+    if name == "medium2d":
+        return medium2d()
+    return synth.build(name)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_of(name):
+    return oracle.Oracle(workload(name).problem_arrays())
+
+
+def random_state(wl, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.uniform(0.0, 1.0, wl.n_el), rng.uniform(0.0, 4.0, wl.n_ph)])
+
+
+CASES = ["toy2d", "tiny2d", "tiny3d", "lattice2d", "medium2d"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rhs_matches_oracle(name):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = workload(name)
+    o = oracle_of(name)
+    say(f"[rhs] {name} n_y={wl.n_y} entries={len(wl.eph_row)}+{len(wl.pp_row)}")
+    ctx = P.Context(wl.problem_arrays())
+    assert ctx.counts() == o.counts()
+    for seed, y in ((0, wl.y0), (1, random_state(wl, 1)), (2, random_state(wl, 2))):
+        yd = to_dev(y)
+        for parts in (1, 2, 4, 3, 7):
+            out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.rhs(yd, out, parts)
+            torch.cuda.synchronize()
+            ref, S, A = o.rhs(y, parts=parts, scales=True)
+            assert_rows_close(out.cpu().numpy(), ref, A, TOL, f"{name} seed {seed} parts {parts}")
+
+
+@pytest.mark.parametrize("tpr", [16, 32, 64, 128, 256])
+def test_every_launch_shape(tpr):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = workload("medium2d")
+    o = oracle_of("medium2d")
+    say(f"[rhs] medium2d tpr={tpr}")
+    ctx = P.Context(wl.problem_arrays(), threads_per_row=tpr)
+    assert ctx.tuning() == tpr
+    y = random_state(wl, 5)
+    out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.rhs(to_dev(y), out, 7)
+    torch.cuda.synchronize()
+    ref, S, A = o.rhs(y, parts=7, scales=True)
+    assert_rows_close(out.cpu().numpy(), ref, A, TOL, f"tpr {tpr}")
+
+
+def test_empty_lists_give_zero():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = workload("tiny2d")
+    Pr = dict(wl.problem_arrays())
+    for k in ("eph_row", "eph_partner", "eph_phonon", "pp_row", "pp_a", "pp_b"):
+        Pr[k] = np.zeros(0, np.int32)
+    Pr["eph_g2"] = np.zeros(0)
+    Pr["pp_v2"] = np.zeros(0)
+    say("[rhs] empty lists")
+    ctx = P.Context(Pr)
+    assert ctx.counts() == (0, 0, 0)
+    out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.rhs(to_dev(wl.y0), out, 7)
+    torch.cuda.synchronize()
+    assert np.all(out.cpu().numpy() == 0.0)
+
+
+def test_unsorted_input_order_is_handled():
+    """Entries given in a scrambled order: grouping by destination row is the
+    library's job; sums may differ only by rounding."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = workload("tiny3d")
+    Pr = dict(wl.problem_arrays())
+    rng = np.random.default_rng(3)
+    pe = rng.permutation(len(wl.eph_row))
+    pp = rng.permutation(len(wl.pp_row))
+    for k in ("eph_row", "eph_partner", "eph_phonon", "eph_g2"):
+        Pr[k] = np.ascontiguousarray(Pr[k][pe])
+    for k in ("pp_row", "pp_a", "pp_b", "pp_v2"):
+        Pr[k] = np.ascontiguousarray(Pr[k][pp])
+    say("[rhs] scrambled input order")
+    ctx = P.Context(Pr)
+    y = random_state(wl, 4)
+    out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+    ctx.rhs(to_dev(y), out, 7)
+    torch.cuda.synchronize()
+    ref, S, A = oracle_of("tiny3d").rhs(y, parts=7, scales=True)
+    assert_rows_close(out.cpu().numpy(), ref, A, TOL, "scrambled")
+
+
+def test_multi_instance_context_matches_single():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    names = ["toy2d", "tiny2d", "tiny3d"]
+    probs = [workload(n).problem_arrays() for n in names]
+    say("[rhs] three instances in one context")
+    multi = P.Context(probs, threads_per_row=32)
+    ys = [random_state(workload(n), 9 + i) for i, n in enumerate(names)]
+    y = np.concatenate(ys)
+    assert multi.ny == len(y)
+    out = torch.full((multi.ny,), float("nan"), dtype=torch.float64, device="cuda")
+    multi.rhs(to_dev(y), out, 7)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i, n in enumerate(names):
+        off, ne, nph = multi.layout(i)
+        single = P.Context(probs[i], threads_per_row=32)
+        o1 = torch.empty((ne + nph,), dtype=torch.float64, device="cuda")
+        single.rhs(to_dev(ys[i]), o1, 7)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[off:off + ne + nph], o1.cpu().numpy())
+        ref, S, A = oracle_of(n).rhs(ys[i], parts=7, scales=True)
+        assert_rows_close(got[off:off + ne + nph], ref, A, TOL, f"instance {i}")
+        assert multi.counts(i) == oracle_of(n).counts()
+
+
+def test_rhs_is_deterministic():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = workload("medium2d")
+    ctx = P.Context(wl.problem_arrays())
+    yd = to_dev(random_state(wl, 6))
+    a = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    ctx.rhs(yd, a, 7)
+    ctx.rhs(yd, b, 7)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("bad", ["row", "sigma", "tpr"])
+def test_invalid_create_is_rejected(bad):
+    torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = workload("tiny2d")
+    Pr = dict(wl.problem_arrays())
+    kw = {}
+    if bad == "row":
+        Pr["pp_row"] = Pr["pp_row"].copy()
+        Pr["pp_row"][7] = wl.n_ph
+    elif bad == "sigma":
+        Pr["sigma_eph"] = -1.0
+    else:
+        kw["threads_per_row"] = 48
+    with pytest.raises(P.RtbteError) as e:
+        P.Context(Pr, **kw)
+    assert e.value.code == P.rtbte.E_INVAL
