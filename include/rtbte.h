@@ -202,6 +202,15 @@ int rtbte_get_tuning(const rtbte_ctx *ctx, int32_t *threads_per_row);
 int rtbte_get_state(const rtbte_ctx *ctx, void *buf, size_t *len);
 int rtbte_set_state(rtbte_ctx *ctx, const void *buf, size_t len);
 
+/* Timing of the collision-kernel launches (the dominant kernels): with
+ * enable = 1 every launch is bracketed by HIP events on its own stream.
+ * rtbte_profile resets the totals; rtbte_profile_read synchronises the device
+ * and returns the summed kernel time (ms), the number of launches and their
+ * summed algorithmic bytes (every stored channel of the evaluated parts once,
+ * 16 B each, plus row bookkeeping and each state vector read or written once). */
+int rtbte_profile(rtbte_ctx *ctx, int32_t enable);
+int rtbte_profile_read(rtbte_ctx *ctx, double *total_ms, int64_t *launches, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

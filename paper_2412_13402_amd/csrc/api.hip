@@ -125,6 +125,13 @@ struct rtbte_ctx {
   int64_t extra_rhs[3] = {0, 0, 0};
   int64_t slow_steps = 0;
   int last_status = 0;
+  // timing of the collision-kernel launches with HIP events on their stream
+  bool prof = false;
+  struct Pending { hipEvent_t a, b; double bytes; };
+  std::vector<Pending> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  double prof_ms = 0.0, prof_bytes = 0.0;
+  int64_t prof_n = 0;
 };
 
 static int fail(rtbte_ctx* c, int code, const char* fmt, ...) {
@@ -293,6 +300,8 @@ void free_ctx(rtbte_ctx* c) {
                 c->partial, c->tvec, c->summary_d};
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  for (auto& p : c->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto& p : c->pool) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   if (c->summary_h) (void)hipHostFree(c->summary_h);
   if (c->scal_h) (void)hipHostFree(c->scal_h);
   delete c;
@@ -629,6 +638,50 @@ extern "C" int rtbte_get_tuning(const rtbte_ctx* c, int32_t* tpr) {
 // ------------------------------------------------------------ right-hand side
 namespace {
 
+// Algorithmic bytes of one collision-kernel launch: every stored channel of
+// the selected parts once (16 B), the row bookkeeping (start, split, order),
+// the populations once, and the epilogue's vectors (`vec_rw` reads + writes).
+double launch_bytes(const rtbte_ctx* c, int parts, int vec_rw) {
+  int64_t ch = 0;
+  for (int i = 0; i < c->n_inst; ++i)
+    for (int k = 0; k < 3; ++k)
+      if (parts & (1 << k)) ch += c->counts[3 * i + k];
+  return 16.0 * (double)ch + (double)c->ny * (8.0 + 8.0 + 4.0 + 8.0 + 8.0 * vec_rw);
+}
+
+hipError_t harvest(rtbte_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e != hipSuccess) return e;
+    c->prof_ms += ms;
+    c->prof_bytes += p.bytes;
+    c->prof_n++;
+    c->pool.emplace_back(p.a, p.b);
+  }
+  c->pending.clear();
+  return hipSuccess;
+}
+
+hipError_t rows(rtbte_ctx* c, const RowArgs& a, bool stage, int vec_rw, hipStream_t s) {
+  if (!c->prof) return launch_rows(a, c->tpr, stage, s);
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (!c->pool.empty()) {
+    ev = c->pool.back();
+    c->pool.pop_back();
+  } else {
+    hipError_t e = hipEventCreate(&ev.first);
+    if (e == hipSuccess) e = hipEventCreate(&ev.second);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipEventRecord(ev.first, s);
+  if (e == hipSuccess) e = launch_rows(a, c->tpr, stage, s);
+  if (e == hipSuccess) e = hipEventRecord(ev.second, s);
+  c->pending.push_back({ev.first, ev.second, launch_bytes(c, a.parts, vec_rw)});
+  return e;
+}
+
+
 RowArgs row_args(const rtbte_ctx* c, const double* z, int parts) {
   RowArgs a{};
   a.ch = c->ch;
@@ -651,7 +704,7 @@ extern "C" int rtbte_rhs(rtbte_ctx* c, const double* y, double* ydot, int32_t pa
   HIPCHK(c, hipSetDevice(c->device));
   RowArgs a = row_args(c, y, parts);
   a.out = ydot;
-  HIPCHK(c, launch_rows(a, c->tpr, false, (hipStream_t)stream));
+  HIPCHK(c, rows(c, a, false, 1, (hipStream_t)stream));
   for (int k = 0; k < 3; ++k)
     if (parts & (1 << k)) c->extra_rhs[k]++;
   return RTBTE_OK;
@@ -702,7 +755,8 @@ int enqueue_step(rtbte_ctx* c, double* y, int parts, const double* forcing, Inst
     }
     a.ynew = c->ynew;
     a.lte = c->lte;
-    HIPCHK(c, launch_rows(a, c->tpr, true, s));
+    // epilogue vectors: y, k_0..k_{i-1} read; k_i and zout (or ynew, lte) written
+    HIPCHK(c, rows(c, a, true, 1 + i + 1 + (a.last ? 2 : 1) + (forcing ? 1 : 0), s));
   }
   if (tb.embedded) HIPCHK(c, launch_wrms(c->lte, y, c->info_d, st, c->partial, c->n_inst, c->nchunk, ctl, s));
   HIPCHK(c, launch_control(st, c->partial, c->info_d, c->n_inst, c->nchunk, ctl, s));
@@ -718,7 +772,7 @@ int enqueue_h0(rtbte_ctx* c, double* y, int parts, const double* forcing, InstSt
   double* pf = c->partial + np;
   RowArgs a = row_args(c, y, parts);
   a.out = c->tmp;  // f0
-  HIPCHK(c, launch_rows(a, c->tpr, false, s));
+  HIPCHK(c, rows(c, a, false, 1, s));
   if (forcing) {
     const double* v[2] = {c->tmp, forcing};
     const double cf[2] = {1.0, 1.0};
@@ -731,7 +785,7 @@ int enqueue_h0(rtbte_ctx* c, double* y, int parts, const double* forcing, InstSt
   HIPCHK(c, launch_h0_axpy(c->zb[0], y, c->tmp, c->row_inst, st, c->ny, s));
   a.z = c->zb[0];
   a.out = c->tmp2;  // f1
-  HIPCHK(c, launch_rows(a, c->tpr, false, s));
+  HIPCHK(c, rows(c, a, false, 1, s));
   if (forcing) {
     const double* v[2] = {c->tmp2, forcing};
     const double cf[2] = {1.0, 1.0};
@@ -750,6 +804,7 @@ int poll(rtbte_ctx* c, InstState* st, double* t, double* h, hipStream_t s, bool*
   HIPCHK(c, launch_finish(st, t, h, c->n_inst, c->summary_d, s));
   HIPCHK(c, hipMemcpyAsync(c->summary_h, c->summary_d, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  if (c->prof) HIPCHK(c, harvest(c));
   *all_done = c->summary_h[0] != 0;
   *worst = c->summary_h[1];
   return RTBTE_OK;
@@ -840,7 +895,7 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
     // slow right-hand side at z_1
     RowArgs a = row_args(c, y, RTBTE_PART_PHPH);
     a.out = c->fs[0];
-    HIPCHK(c, launch_rows(a, c->tpr, false, s));
+    HIPCHK(c, rows(c, a, false, 1, s));
     c->extra_rhs[2]++;
     for (int i = 1; i < 4; ++i) {
       const double* v[3] = {c->fs[0], c->fs[1], c->fs[2]};
@@ -876,7 +931,7 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
       if (i < 3) {
         a.z = y;
         a.out = c->fs[i];
-        HIPCHK(c, launch_rows(a, c->tpr, false, s));
+        HIPCHK(c, rows(c, a, false, 1, s));
         c->extra_rhs[2]++;
       }
     }
@@ -951,5 +1006,28 @@ extern "C" int rtbte_set_state(rtbte_ctx* c, const void* buf, size_t len) {
   c->extra_rhs[1] = tail[1];
   c->extra_rhs[2] = tail[2];
   c->slow_steps = tail[3];
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_profile(rtbte_ctx* c, int32_t enable) {
+  if (!c) return RTBTE_E_INVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipDeviceSynchronize());
+  HIPCHK(c, harvest(c));
+  c->prof = enable != 0;
+  c->prof_ms = 0.0;
+  c->prof_bytes = 0.0;
+  c->prof_n = 0;
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_profile_read(rtbte_ctx* c, double* total_ms, int64_t* launches, double* bytes) {
+  if (!c) return RTBTE_E_INVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipDeviceSynchronize());
+  HIPCHK(c, harvest(c));
+  if (total_ms) *total_ms = c->prof_ms;
+  if (launches) *launches = c->prof_n;
+  if (bytes) *bytes = c->prof_bytes;
   return RTBTE_OK;
 }

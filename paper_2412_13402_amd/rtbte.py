@@ -112,6 +112,8 @@ def load():
     L.rtbte_get_tuning.argtypes = [_vp, ctypes.POINTER(i32)]
     L.rtbte_get_state.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]
     L.rtbte_set_state.argtypes = [_vp, _vp, ctypes.c_size_t]
+    L.rtbte_profile.argtypes = [_vp, i32]
+    L.rtbte_profile_read.argtypes = [_vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     _LIB = L
     return L
 
@@ -240,6 +242,15 @@ class Context:
         t = ctypes.c_int32()
         self._check(load().rtbte_get_tuning(self._h, ctypes.byref(t)))
         return t.value
+
+    def profile(self, enable=True):
+        self._check(load().rtbte_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """(summed collision-kernel ms, launches, summed algorithmic bytes)."""
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        self._check(load().rtbte_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)))
+        return ms.value, n.value, by.value
 
     def get_state(self) -> bytes:
         n = ctypes.c_size_t()

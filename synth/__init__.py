@@ -127,6 +127,24 @@ RECIPES = {
         init=dict(T_el=2000.0, T_ph=300.0, mu=0.0),
         seed_offset=1,
     ),
+    # Graphene-like coupled workload: 120x120 triangular k = q grid, two
+    # nearest-neighbour pi bands (t = 3.09 eV, v = 1e6 m/s at K), six branches
+    # in 0-200 meV, sigma 20 meV (e-ph) / 2 meV (ph-ph), 1 meV cutoff (Methods,
+    # graphene grids).  The full pi bands are kept (~1.6e8 electron-side and
+    # ~0.8e8 phonon-side e-ph channels); ph-ph triplets are thinned to ~5e8
+    # channels (~7.8e8 stored entries: a third of the orderings of a triplet
+    # conserve energy in neither of their two processes).  |g|^2 is scaled so that the e-ph Jacobian's spectral radius is
+    # ~0.5/fs (explicit steps of a few fs), |V3|^2 so that the mean 300 K
+    # phonon decay rate is ~1/ps.  Carriers start hot (4000 K), phonons at 300 K.
+    "graphene2d": dict(
+        grid=dict(dim=2, L=120, lattice=1, n_bands=2, n_modes=6, t_hop=3.09,
+                  win_lo=-10.0, win_hi=10.0, with_eph=1, with_pp=1,
+                  shell_eph=0.13, shell_pp=0.013, keep_eph=1.0, keep_pp=0.115,
+                  g2_mu=-6.5, g2_sig=1.0, v2_mu=-16.33, v2_sig=1.0),
+        problem=dict(sigma_eph=0.020, sigma_pp=0.002, nsigma=6.0, hw_cut=0.001),
+        init=dict(T_el=4000.0, T_ph=300.0, mu=0.0),
+        seed_offset=2,
+    ),
     # Tiny coupled graphene-like grid (brute-force comparisons): wide Gaussians
     # so that a 6x6 grid still has channels of every kind.
     "tiny2d": dict(

@@ -294,17 +294,30 @@ void eph_row(const Model &m, int r, F &&emit) {
 template <class F>
 void pp_row(const Model &m, int lam, F &&emit) {
   const synth_params &p = m.p;
-  int q = lam / p.n_modes;
+  const int nm = p.n_modes;
+  int q = lam / nm;
   int mq = m.g.neg(q);
+  const double w0 = m.hw[lam];
   for (int q1 = 0; q1 < m.g.N; ++q1) {
     int q2 = m.g.add(mq, m.g.neg(q1));
-    for (int n1 = 0; n1 < p.n_modes; ++n1) {
-      int a = q1 * p.n_modes + n1;
-      for (int n2 = 0; n2 < p.n_modes; ++n2) {
-        int b = q2 * p.n_modes + n2;
-        double v2;
-        if (triplet_channel(m, lam, a, b, &v2)) emit(a, b, v2);
+    const double *w1 = &m.hw[(size_t)q1 * nm], *w2 = &m.hw[(size_t)q2 * nm];
+    // branch-free shell test of all (n1, n2) first (same selection as
+    // triplet_channel), then the full decision for the few that pass
+    uint64_t pass = 0;
+    for (int n1 = 0; n1 < nm; ++n1)
+      for (int n2 = 0; n2 < nm; ++n2) {
+        const double a = w0, b = w1[n1], c = w2[n2];
+        const double hi = std::max(std::max(a, b), c), lo = std::min(std::min(a, b), c);
+        const double mid = std::max(std::min(a, b), std::min(std::max(a, b), c));
+        pass |= (uint64_t)(std::fabs(hi - (mid + lo)) <= p.shell_pp) << (n1 * nm + n2);
       }
+    while (pass) {
+      const int bit = __builtin_ctzll(pass);
+      pass &= pass - 1;
+      const int n1 = bit / nm, n2 = bit % nm;
+      const int a = q1 * nm + n1, b = q2 * nm + n2;
+      double v2;
+      if (triplet_channel(m, lam, a, b, &v2)) emit(a, b, v2);
     }
   }
 }

@@ -1,0 +1,298 @@
+"""GPU parity of the device-driven integrators against the oracle's.
+
+Fixed-step RK4 and the MIS step with a fixed RK4 fast solver have no
+decisions, so GPU and oracle must agree to 1e-12.  The adaptive ERK is checked
+by step-sequence replay (the oracle re-runs the step sizes the GPU accepted),
+by the starting-step estimate, and by comparing the step-size sequences of
+free-running integrations; batched contexts must reproduce single-instance
+runs; error paths leave y at the last accepted state.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import integrators as I
+from tests.gpu_util import say, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def wl_of(name):
+    return synth.build(name)
+
+
+def coupled(scale_eph=0.03, scale_pp=0.003, seed=17):
+    """tiny2d with fast e-ph and slow ph-ph parts, random populations."""
+    wl = synth.build("tiny2d")
+    P = dict(wl.problem_arrays())
+    P["eph_g2"] = P["eph_g2"] * scale_eph
+    P["pp_v2"] = P["pp_v2"] * scale_pp
+    rng = np.random.default_rng(seed)
+    y0 = np.concatenate([rng.uniform(0.05, 0.95, wl.n_el), rng.uniform(0.0, 2.0, wl.n_ph)])
+    return P, y0
+
+
+def atol_vec(n_el, n_ph, a_el, a_ph):
+    return np.concatenate([np.full(n_el, a_el), np.full(n_ph, a_ph)])
+
+
+def close(a, b, tol=1e-12):
+    scale = max(1.0, float(np.max(np.abs(b))))
+    return float(np.max(np.abs(a - b))) <= tol * scale
+
+
+def test_rk4_fixed_steps_match_oracle():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of("toy2d")
+    say("[int] toy2d RK4 h=0.5 fs x 100")
+    ctx = P.Context(wl.problem_arrays())
+    y = to_dev(wl.y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.step_rk4(y, t, 0.5, 100)
+    torch.cuda.synchronize()
+    o = oracle.Oracle(wl.problem_arrays())
+    yr = wl.y0.copy()
+    for _ in range(100):
+        yr = I.rk4_step(o.rhs, yr, 0.5)
+    assert abs(t.item() - 50.0) < 1e-12
+    assert close(y.cpu().numpy(), yr)
+    st = ctx.stats()
+    assert st["n_accept"] == 100 and st["n_rhs_eph"] == 400
+
+
+def test_rk4_at_one_fs_diverges_on_toy():
+    """The toy's e-ph rates put RK4 at h = 1 fs beyond its stability limit:
+    the populations blow up on the GPU just as in the oracle."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of("toy2d")
+    say("[int] toy2d RK4 h=1 fs x 100 (unstable)")
+    ctx = P.Context(wl.problem_arrays())
+    y = to_dev(wl.y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.step_rk4(y, t, 1.0, 100)
+    torch.cuda.synchronize()
+    g = y.cpu().numpy()
+    assert (not np.all(np.isfinite(g))) or np.max(np.abs(g)) > 1e6
+
+
+def test_starting_step_matches_oracle():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    o = oracle.Oracle(Pr)
+    c = I.Controls(rtol=1e-6, atol_el=1e-9, atol_ph=1e-12)
+    av = atol_vec(Pr["n_el"], Pr["n_ph"], 1e-9, 1e-12)
+    h_ref = I.hnw_initial_step(o.rhs, y0, c, av)
+    say("[int] starting step")
+    ctx = P.Context(Pr, rtol=1e-6, atol_el=1e-9, atol_ph=1e-12)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.step_adaptive(y, t, h, 1e9, one_step=True)
+    torch.cuda.synchronize()
+    # the first attempt uses the estimate; its size is the first accepted step
+    # unless that attempt was rejected
+    st = ctx.stats()
+    if st["n_reject"] == 0:
+        assert abs(t.item() - h_ref) <= 1e-12 * h_ref
+
+
+@pytest.mark.parametrize("name", ["toy2d", "coupled"])
+def test_adaptive_steps_replay_on_oracle(name):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    if name == "coupled":
+        Pr, y0 = coupled()
+    else:
+        Pr, y0 = wl_of(name).problem_arrays(), wl_of(name).y0
+    n_el, n_ph = Pr["n_el"], Pr["n_ph"]
+    say(f"[int] adaptive replay {name}")
+    ctx = P.Context(Pr, rtol=1e-6, atol_el=1e-9, atol_ph=1e-12)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h = torch.full((1,), 0.05, dtype=torch.float64, device="cuda")
+    times = [0.0]
+    for _ in range(25):
+        ctx.step_adaptive(y, t, h, 1e9, one_step=True)
+        torch.cuda.synchronize()
+        times.append(t.item())
+    steps = np.diff(times)
+    assert np.all(steps > 0)
+    o = oracle.Oracle(Pr)
+    yr = I.replay(o.rhs, y0.copy(), steps)
+    assert close(y.cpu().numpy(), yr)
+    # free-running oracle with the same controller takes the same steps
+    a = I.Adaptive(rhs=o.rhs, atol_vec=atol_vec(n_el, n_ph, 1e-9, 1e-12),
+                   c=I.Controls(rtol=1e-6, atol_el=1e-9, atol_ph=1e-12), h=0.05)
+    yy = y0.copy()
+    tt = 0.0
+    for _ in range(25):
+        yy, tt = a.advance(yy, tt, 1e9, one_step=True)
+    h_or = np.array([hh for (_, hh, _) in a.history])
+    # the error estimate h*sum(d_i k_i) cancels to ~1e-7 of the stage values,
+    # so rounding differences reach ~1e-9 relative in eps and in h'
+    assert np.allclose(h_or, steps, rtol=1e-6, atol=0)
+    st = ctx.stats()
+    assert st["n_accept"] == 25 and st["n_reject"] == a.n_reject
+
+
+def test_adaptive_lands_on_t_out():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    say("[int] adaptive to t_out")
+    ctx = P.Context(Pr, rtol=1e-5)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.step_adaptive(y, t, h, 37.5)
+    torch.cuda.synchronize()
+    assert t.item() == 37.5 and h.item() > 0
+    st = ctx.stats()
+    assert st["n_accept"] > 3 and st["h_min"] > 0 and st["h_max"] >= st["h_min"]
+    # continue from where it stopped
+    ctx.step_adaptive(y, t, h, 60.0)
+    torch.cuda.synchronize()
+    assert t.item() == 60.0
+
+
+def test_multirate_fixed_fast_matches_oracle():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    hs, hf = 6.0, 0.7
+    say("[int] MIS with fixed RK4 fast steps")
+    ctx = P.Context(Pr, fast_mode=1, h_fast=hf)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hfd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.step_multirate(y, t, hfd, 4 * hs, hs)
+    torch.cuda.synchronize()
+    o = oracle.Oracle(Pr)
+    fast = lambda v: o.rhs(v, parts=3)
+    slow = lambda v: o.rhs(v, parts=4)
+    yr = y0.copy()
+    for _ in range(4):
+        yr = I.mis_step(fast, slow, yr, hs, I.rk4_fixed_solver(hf))
+    assert t.item() == 4 * hs
+    assert close(y.cpu().numpy(), yr)
+    st = ctx.stats()
+    assert st["n_rhs_phph"] == 4 * 3
+
+
+def test_multirate_adaptive_fast_matches_oracle():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    hs = 6.0
+    say("[int] MIS with adaptive fast ERK")
+    ctx = P.Context(Pr, fast_mode=0, fast_rtol=1e-7, fast_atol_el=1e-10, fast_atol_ph=1e-12)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hfd = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")
+    ctx.step_multirate(y, t, hfd, 3 * hs, hs)
+    torch.cuda.synchronize()
+    o = oracle.Oracle(Pr)
+    fast = lambda v: o.rhs(v, parts=3)
+    slow = lambda v: o.rhs(v, parts=4)
+    solver = I.AdaptiveFastSolver(atol_vec(Pr["n_el"], Pr["n_ph"], 1e-10, 1e-12),
+                                  I.Controls(rtol=1e-7, atol_el=1e-10, atol_ph=1e-12), 0.1)
+    yr = y0.copy()
+    for _ in range(3):
+        yr = I.mis_step(fast, slow, yr, hs, solver)
+    st = ctx.stats()
+    assert st["n_fast_accept"] == solver.n_accept and st["n_fast_reject"] == solver.n_reject
+    assert close(y.cpu().numpy(), yr, 1e-11)
+    assert abs(hfd.item() - solver.h) <= 1e-6 * solver.h   # see the replay test on eps conditioning
+
+
+def test_batched_instances_advance_independently():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    probs, ys = [], []
+    for i, (se, sp) in enumerate(((0.03, 0.003), (0.05, 0.002), (0.02, 0.004))):
+        Pr, y0 = coupled(se, sp, seed=30 + i)
+        probs.append(Pr)
+        ys.append(y0)
+    say("[int] three instances, own steps")
+    multi = P.Context(probs, rtol=1e-6, threads_per_row=32)
+    y = to_dev(np.concatenate(ys))
+    t = torch.zeros(3, dtype=torch.float64, device="cuda")
+    h = torch.full((3,), 0.1, dtype=torch.float64, device="cuda")
+    multi.step_adaptive(y, t, h, 20.0)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    assert np.all(t.cpu().numpy() == 20.0)
+    for i in range(3):
+        single = P.Context(probs[i], rtol=1e-6, threads_per_row=32)
+        yi = to_dev(ys[i])
+        ti = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hi = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")
+        single.step_adaptive(yi, ti, hi, 20.0)
+        torch.cuda.synchronize()
+        off, ne, nph = multi.layout(i)
+        assert np.array_equal(got[off:off + ne + nph], yi.cpu().numpy())
+        assert multi.stats(i)["n_accept"] == single.stats(0)["n_accept"]
+
+
+def test_nonfinite_state_is_reported_and_y_kept():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    y0 = y0.copy()
+    y0[5] = np.nan
+    say("[int] NaN in y")
+    ctx = P.Context(Pr)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.RtbteError) as e:
+        ctx.step_adaptive(y, t, h, 10.0)
+    assert e.value.code == P.rtbte.E_NONFINITE
+    torch.cuda.synchronize()
+    g = y.cpu().numpy()
+    assert np.isnan(g[5]) and np.array_equal(np.delete(g, 5), np.delete(y0, 5))
+    assert t.item() == 0.0
+
+
+def test_too_many_failures_reported():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    say("[int] max_fails")
+    ctx = P.Context(Pr, rtol=1e-15, atol_el=1e-30, atol_ph=1e-30, max_fails=1)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h = torch.full((1,), 5.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.RtbteError) as e:
+        ctx.step_adaptive(y, t, h, 10.0)
+    assert e.value.code == P.rtbte.E_STEP
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), y0) and t.item() == 0.0
+
+
+def test_checkpoint_resume_is_bitwise():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    say("[int] checkpoint / resume")
+    ctx = P.Context(Pr, rtol=1e-6)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")
+    ctx.step_adaptive(y, t, h, 10.0)
+    state = ctx.get_state()
+    ys, ts, hs = y.clone(), t.clone(), h.clone()
+    ctx.step_adaptive(y, t, h, 25.0)
+    torch.cuda.synchronize()
+    ya = y.cpu().numpy()
+    ctx.set_state(state)
+    ctx.step_adaptive(ys, ts, hs, 25.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(ya, ys.cpu().numpy()) and ts.item() == 25.0
