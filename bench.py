@@ -83,7 +83,9 @@ def main():
     ap.add_argument("--workload", default="graphene2d")
     ap.add_argument("--L", type=int, default=None, help="grid side override (smaller test runs)")
     ap.add_argument("--rtol", type=float, default=1e-6)
-    ap.add_argument("--tpr", type=int, default=0, help="lanes per row (0: library choice)")
+    ap.add_argument("--group-rows-el", type=int, default=0, help="electron rows per group (0: library choice)")
+    ap.add_argument("--group-rows-ph", type=int, default=0, help="phonon rows per group (0: library choice)")
+    ap.add_argument("--item-channels", type=int, default=0, help="channels per work item (0: library choice)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -107,13 +109,14 @@ def main():
         f"{len(wl.eph_row)} e-ph + {len(wl.pp_row)} ph-ph, generated in {gen_s:.1f} s")
     t0 = time.perf_counter()
     ctx = P.Context(wl.problem_arrays(), rtol=args.rtol, atol_el=1e-9, atol_ph=1e-12,
-                    threads_per_row=args.tpr)
+                    group_rows_el=args.group_rows_el, group_rows_ph=args.group_rows_ph,
+                    item_channels=args.item_channels)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     counts = ctx.counts()
     C = sum(counts)
     log(f"[bench] create {create_s:.1f} s; channels e-ph {counts[0]}, ph-e {counts[1]}, "
-        f"ph-ph {counts[2]} (total {C}); lanes/row {ctx.tuning()}")
+        f"ph-ph {counts[2]} (total {C}); rows per group (el, ph), channels per item {ctx.tuning()}")
 
     dev = torch.device("cuda:0")
     y = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
@@ -165,14 +168,15 @@ def main():
                         f"FP64, adaptive Zonneveld ERK rtol {args.rtol:g}",
             "channels_eph": counts[0], "channels_phe": counts[1], "channels_phph": counts[2],
             "n_y": wl.n_y, "rhs_per_step": evals / args.steps,
-            "lanes_per_row": ctx.tuning(),
+            "rows_per_group_el": ctx.tuning()[0], "rows_per_group_ph": ctx.tuning()[1],
+            "channels_per_item": ctx.tuning()[2],
         },
         "sim_ps_per_s": (t_end - t_start) * 1e-3 / wall,
         "hbm_frac": achieved / HBM_PEAK_GBS,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_rows (collision integrals + fused ERK stage epilogue)",
+            "kernel": "k_items (collision integrals: per-item row sums)",
             "launches": k_n, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch,
         },
         "create_s": create_s,

@@ -84,9 +84,12 @@ typedef struct rtbte_ctx rtbte_ctx;
  *   sigma_eph, sigma_pp   Gaussian widths (eV) > 0
  *   nsigma        truncation in units of sigma (> 0)
  *   hw_cut        channels touching a phonon with hw < hw_cut are dropped
- * Channels of one destination row are summed in the order their entries
- * appear in the input; listing partners in grid order keeps the gathers of
- * the populations local.
+ * Rows are processed in groups of up to 16 consecutive rows of one kind
+ * (group_rows_el, group_rows_ph); a group's channels are summed merged in the order of a partner index
+ * (e-ph electron rows: the phonon; ph-e: the initial electron; ph-ph: the
+ * first partner), entries with equal index keeping their input order.
+ * Numbering states in grid order therefore keeps the gathers of the
+ * populations local.
  */
 typedef struct {
   int32_t n_el, n_ph;
@@ -124,7 +127,11 @@ typedef struct {
   int32_t max_fails;
   int32_t use_graph;        /* replay each step through a captured HIP graph (1) or launch (0) */
   int32_t steps_per_poll;   /* steps enqueued between host checks of the done flags           */
-  int32_t threads_per_row;  /* 0: tuned/auto; else 16, 32, 64, 128 or 256 lanes per row     */
+  int32_t group_rows_el;    /* consecutive electron rows sharing one merged channel stream:
+                               1, 2, 4, 8, 12 or 16 (0: 8)                                     */
+  int32_t group_rows_ph;    /* the same for phonon rows (0: 16)                                 */
+  int64_t item_channels;    /* channels per work item of the collision kernel (0: sized so
+                               that there are ~40k items, within [2048, 65536])                */
   int32_t tune;             /* 1: time the launch shapes at create and keep the fastest      */
   const char *tune_cache;   /* file caching tuning results (NULL: env RTBTE_TUNE_CACHE)       */
 } rtbte_options;
@@ -193,8 +200,9 @@ int rtbte_step_multirate(rtbte_ctx *ctx, double *y, double *t, double *h_fast, d
 int rtbte_reset(rtbte_ctx *ctx);
 int rtbte_get_stats(const rtbte_ctx *ctx, int32_t inst, rtbte_stats *out);
 
-/* Launch shape in use: lanes per destination row. */
-int rtbte_get_tuning(const rtbte_ctx *ctx, int32_t *threads_per_row);
+/* Launch shape in use: electron and phonon rows per group, channels per item. */
+int rtbte_get_tuning(const rtbte_ctx *ctx, int32_t *group_rows_el, int32_t *group_rows_ph,
+                     int64_t *item_channels);
 
 /* Checkpoint of the integrator state kept in the context (PID histories,
  * step sizes, counters; not y, which the caller owns).  With buf == NULL,

@@ -17,7 +17,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rtbte.h"
+#include "rtbte.h"
 #include "internal.h"
 
 using namespace rtbte;
@@ -97,13 +97,20 @@ struct rtbte_ctx {
   int64_t ny = 0;
   std::vector<int64_t> counts;     // [3 * n_inst]
   int64_t n_ch = 0;
-  int tpr = 64;
+  int64_t n_groups = 0;
+  int64_t n_items = 0;
+  int group_rows_el = 8, group_rows_ph = 16;
+  int64_t item_channels = 0;
+  int slots = 16;
   int nchunk = 1;
   // device
   Channel* ch = nullptr;
-  int64_t* ptr = nullptr;
-  int64_t* split = nullptr;
-  uint32_t* order = nullptr;
+  Group* groups = nullptr;
+  Item* items = nullptr;
+  int32_t* order = nullptr;       // item processing order
+  int64_t* item_ptr = nullptr;    // [n_groups + 1]
+  int32_t* row_group = nullptr;   // [ny]
+  double* partial_items = nullptr;
   int32_t* row_inst = nullptr;
   InstInfo* info_d = nullptr;
   InstState* st = nullptr;       // main integrator
@@ -181,7 +188,9 @@ void rtbte_default_options(rtbte_options* o) {
   o->max_fails = 7;
   o->use_graph = 0;
   o->steps_per_poll = 8;
-  o->threads_per_row = 0;
+  o->group_rows_el = 0;
+  o->group_rows_ph = 0;
+  o->item_channels = 0;
   o->tune = 0;
   o->tune_cache = nullptr;
 }
@@ -195,47 +204,60 @@ const char* rtbte_last_error(const rtbte_ctx* ctx) {
 // ---------------------------------------------------------------- create
 namespace {
 
-// Stable grouping of n keys in [0, nkeys) (counting sort).  Returns the
-// visiting permutation (empty if the keys are already non-decreasing) and the
-// group pointers.
-void group_keys(int64_t n, const int32_t* key, int32_t nkeys, std::vector<int64_t>& perm,
-                std::vector<int64_t>& gptr) {
-  gptr.assign((size_t)nkeys + 1, 0);
+// Visiting order of n raw entries for the channel preparation: grouped by
+// destination group dest[i] / G (stable counting sort), and inside a group
+// with more than one row merged by `key` (stable: ties keep input order).
+// Returns the permutation (empty if it is the identity) and the group pointers.
+void group_entries(int64_t n, const int32_t* dest, int32_t nrows, int G, const int32_t* key,
+                   std::vector<int64_t>& perm, std::vector<int64_t>& gptr) {
+  const int32_t ng = (nrows + G - 1) / G;
+  gptr.assign((size_t)ng + 1, 0);
   bool sorted = true;
   for (int64_t i = 0; i < n; ++i) {
-    gptr[(size_t)key[i] + 1]++;
-    if (i && key[i] < key[i - 1]) sorted = false;
+    gptr[(size_t)(dest[i] / G) + 1]++;
+    if (i && dest[i] / G < dest[i - 1] / G) sorted = false;
   }
-  for (int32_t k = 0; k < nkeys; ++k) gptr[k + 1] += gptr[k];
+  for (int32_t k = 0; k < ng; ++k) gptr[k + 1] += gptr[k];
   perm.clear();
-  if (sorted) return;
+  if (sorted && G == 1) return;
   perm.resize((size_t)n);
   const int nt = std::max(1, omp_get_max_threads());
-  // per-thread histograms over contiguous chunks keep the order stable
-  std::vector<std::vector<int64_t>> cur((size_t)nt);
-  const int64_t chunk = (n + nt - 1) / nt;
+  if (sorted) {
+#pragma omp parallel for num_threads(nt)
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+  } else {
+    // per-thread histograms over contiguous chunks keep the order stable
+    std::vector<std::vector<int64_t>> cur((size_t)nt);
+    const int64_t chunk = (n + nt - 1) / nt;
 #pragma omp parallel num_threads(nt)
-  {
-    const int t = omp_get_thread_num();
-    std::vector<int64_t>& h = cur[t];
-    h.assign((size_t)nkeys, 0);
-    const int64_t lo = std::min(n, t * chunk), hi = std::min(n, lo + chunk);
-    for (int64_t i = lo; i < hi; ++i) h[key[i]]++;
-  }
-  for (int32_t k = 0; k < nkeys; ++k) {
-    int64_t pos = gptr[k];
-    for (int t = 0; t < nt; ++t) {
-      int64_t c = cur[t][k];
-      cur[t][k] = pos;
-      pos += c;
+    {
+      const int t = omp_get_thread_num();
+      std::vector<int64_t>& h = cur[t];
+      h.assign((size_t)ng, 0);
+      const int64_t lo = std::min(n, t * chunk), hi = std::min(n, lo + chunk);
+      for (int64_t i = lo; i < hi; ++i) h[dest[i] / G]++;
+    }
+    for (int32_t k = 0; k < ng; ++k) {
+      int64_t pos = gptr[k];
+      for (int t = 0; t < nt; ++t) {
+        int64_t c = cur[t][k];
+        cur[t][k] = pos;
+        pos += c;
+      }
+    }
+#pragma omp parallel num_threads(nt)
+    {
+      const int t = omp_get_thread_num();
+      std::vector<int64_t>& h = cur[t];
+      const int64_t lo = std::min(n, t * chunk), hi = std::min(n, lo + chunk);
+      for (int64_t i = lo; i < hi; ++i) perm[h[dest[i] / G]++] = i;
     }
   }
-#pragma omp parallel num_threads(nt)
-  {
-    const int t = omp_get_thread_num();
-    std::vector<int64_t>& h = cur[t];
-    const int64_t lo = std::min(n, t * chunk), hi = std::min(n, lo + chunk);
-    for (int64_t i = lo; i < hi; ++i) perm[h[key[i]]++] = i;
+  if (G > 1) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+    for (int32_t g = 0; g < ng; ++g)
+      std::stable_sort(perm.begin() + gptr[g], perm.begin() + gptr[g + 1],
+                       [&](int64_t x, int64_t y) { return key[x] < key[y]; });
   }
 }
 
@@ -294,7 +316,8 @@ hipError_t upload(T** d, const T* h, size_t n) {
 
 void free_ctx(rtbte_ctx* c) {
   if (!c) return;
-  void* ps[] = {c->ch, c->ptr, c->split, c->order, c->row_inst, c->info_d, c->st, c->st_fast,
+  void* ps[] = {c->ch, c->groups, c->items, c->order, c->item_ptr, c->row_group, c->partial_items,
+                c->row_inst, c->info_d, c->st, c->st_fast,
                 c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
                 c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
                 c->partial, c->tvec, c->summary_d};
@@ -307,13 +330,7 @@ void free_ctx(rtbte_ctx* c) {
   delete c;
 }
 
-int choose_tpr(const rtbte_ctx* c) {
-  if (c->opt.threads_per_row) return c->opt.threads_per_row;
-  const double avg = c->ny ? (double)c->n_ch / (double)c->ny : 0.0;
-  if (avg < 48) return 16;
-  if (avg < 192) return 32;
-  return 64;
-}
+bool valid_group_rows(int g) { return g == 1 || g == 2 || g == 4 || g == 8 || g == 12 || g == 16; }
 
 }  // namespace
 
@@ -328,9 +345,11 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
   else rtbte_default_options(&o);
   if (o.precision != RTBTE_FP64)
     return fail(nullptr, RTBTE_E_UNSUPPORTED, "precision %d not available in this build", o.precision);
-  const int tprs[] = {0, 16, 32, 64, 128, 256};
-  if (std::find(std::begin(tprs), std::end(tprs), o.threads_per_row) == std::end(tprs))
-    return fail(nullptr, RTBTE_E_INVAL, "threads_per_row must be 0, 16, 32, 64, 128 or 256");
+  if (o.group_rows_el == 0) o.group_rows_el = 8;
+  if (o.group_rows_ph == 0) o.group_rows_ph = 16;
+  if (!valid_group_rows(o.group_rows_el) || !valid_group_rows(o.group_rows_ph))
+    return fail(nullptr, RTBTE_E_INVAL, "group_rows_el / group_rows_ph must be 0, 1, 2, 4, 8, 12 or 16");
+  if (o.item_channels < 0) return fail(nullptr, RTBTE_E_INVAL, "item_channels must be >= 0");
   if (!(o.rtol >= 0) || !(o.atol_el >= 0) || !(o.atol_ph >= 0) || o.pid_order <= 0 ||
       o.steps_per_poll < 1 || o.max_fails < 0)
     return fail(nullptr, RTBTE_E_INVAL, "invalid tolerances or controller options");
@@ -344,6 +363,7 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
   if (o.device < 0 || o.device >= ndev) return fail(nullptr, RTBTE_E_INVAL, "device %d out of range", o.device);
   if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, RTBTE_E_HIP, "hipSetDevice failed");
 
+  const int GE = o.group_rows_el, GP = o.group_rows_ph;
   rtbte_ctx* c = new rtbte_ctx();
   c->device = o.device;
   c->opt = o;
@@ -357,13 +377,13 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
     off += (int64_t)problems[i].n_el + problems[i].n_ph;
   }
   c->ny = off;
-  if (c->ny >= (int64_t)kIdxMask) {
+  if (c->ny > (int64_t)kPosMask) {
     free_ctx(c);
-    return fail(nullptr, RTBTE_E_INVAL, "state vector too long (%lld)", (long long)off);
+    return fail(nullptr, RTBTE_E_INVAL, "state vector too long (%lld > %d)", (long long)off, kPosMask);
   }
   c->counts.assign(3 * (size_t)n_inst, 0);
 
-  // Pass 1: upload raw entries and count kept channels per destination row.
+  // Pass 1: upload raw entries and count kept channels per destination group.
   std::vector<DevRaw> raws((size_t)n_inst);
   std::vector<std::vector<int64_t>> cnt_e(n_inst), cnt_pe(n_inst), cnt_pp(n_inst);
   auto cleanup = [&](int code) {
@@ -398,22 +418,23 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
     UP(d.pa, p.pp_a, p.n_pp);
     UP(d.pb, p.pp_b, p.n_pp);
     UP(d.pv, p.pp_v2, p.n_pp);
-    // electron side: group by electron row
-    group_keys(p.n_eph, p.eph_row, p.n_el, perm, gptr);
+    // electron side: groups of electron rows, merged by phonon (the shared q)
+    group_entries(p.n_eph, p.eph_row, p.n_el, GE, p.eph_phonon, perm, gptr);
     if (!perm.empty()) UP(d.perm_e, perm.data(), perm.size());
     UP(d.ptr_e, gptr.data(), gptr.size());
-    // phonon side: the same entries grouped by phonon
-    group_keys(p.n_eph, p.eph_phonon, p.n_ph, perm, gptr);
+    // phonon side of e-ph: groups of phonon rows, merged by the initial electron
+    group_entries(p.n_eph, p.eph_phonon, p.n_ph, GP, p.eph_row, perm, gptr);
     if (!perm.empty()) UP(d.perm_pe, perm.data(), perm.size());
     UP(d.ptr_pe, gptr.data(), gptr.size());
-    // ph-ph: group by phonon row
-    group_keys(p.n_pp, p.pp_row, p.n_ph, perm, gptr);
+    // ph-ph: groups of phonon rows, merged by the first partner
+    group_entries(p.n_pp, p.pp_row, p.n_ph, GP, p.pp_a, perm, gptr);
     if (!perm.empty()) UP(d.perm_pp, perm.data(), perm.size());
     UP(d.ptr_pp, gptr.data(), gptr.size());
 #undef UP
-    d.cnt_e = dalloc<int64_t>(p.n_el, &e);
-    if (e == hipSuccess) d.cnt_pe = dalloc<int64_t>(p.n_ph, &e);
-    if (e == hipSuccess) d.cnt_pp = dalloc<int64_t>(p.n_ph, &e);
+    const int32_t nge = (p.n_el + GE - 1) / GE, ngp = (p.n_ph + GP - 1) / GP;
+    d.cnt_e = dalloc<int64_t>(nge, &e);
+    if (e == hipSuccess) d.cnt_pe = dalloc<int64_t>(ngp, &e);
+    if (e == hipSuccess) d.cnt_pp = dalloc<int64_t>(ngp, &e);
     if (e != hipSuccess) {
       fail(c, RTBTE_E_NOMEM, "count buffers: %s", hipGetErrorString(e));
       return cleanup(RTBTE_E_NOMEM);
@@ -427,63 +448,85 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
     a.y_off = c->info[i].off;
     a.n_el = p.n_el;
     a.hw_cut = p.hw_cut;
+    a.group_rows = GE;
     // e-ph electron side
     a.row = d.er; a.i0 = d.es; a.i1 = d.ep; a.val = d.eg; a.perm = d.perm_e; a.raw_ptr = d.ptr_e;
-    a.n_dest = p.n_el; a.sigma = p.sigma_eph; a.cut = p.nsigma * p.sigma_eph; a.pre = pre_el;
+    a.n_dest = nge; a.sigma = p.sigma_eph; a.cut = p.nsigma * p.sigma_eph; a.pre = pre_el;
     a.pre2 = pre_el; a.kind = 0; a.count = d.cnt_e;
     pe[i] = a;
     // ph-e
-    a.perm = d.perm_pe; a.raw_ptr = d.ptr_pe; a.n_dest = p.n_ph; a.pre = pre_ph; a.pre2 = pre_ph;
+    a.group_rows = GP;
+    a.perm = d.perm_pe; a.raw_ptr = d.ptr_pe; a.n_dest = ngp; a.pre = pre_ph; a.pre2 = pre_ph;
     a.kind = 1; a.count = d.cnt_pe;
     ppe[i] = a;
     // ph-ph
     a.row = d.pr; a.i0 = d.pa; a.i1 = d.pb; a.val = d.pv; a.perm = d.perm_pp; a.raw_ptr = d.ptr_pp;
-    a.n_dest = p.n_ph; a.sigma = p.sigma_pp; a.cut = p.nsigma * p.sigma_pp; a.pre = pre_pp;
+    a.n_dest = ngp; a.sigma = p.sigma_pp; a.cut = p.nsigma * p.sigma_pp; a.pre = pre_pp;
     a.pre2 = 2.0 * pre_pp; a.kind = 2; a.count = d.cnt_pp;
     ppp[i] = a;
     e = launch_prep_count(pe[i], 0);
     if (e == hipSuccess) e = launch_prep_count(ppe[i], 0);
     if (e == hipSuccess) e = launch_prep_count(ppp[i], 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    cnt_e[i].resize(p.n_el);
-    cnt_pe[i].resize(p.n_ph);
-    cnt_pp[i].resize(p.n_ph);
-    if (e == hipSuccess && p.n_el) e = hipMemcpy(cnt_e[i].data(), d.cnt_e, p.n_el * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && p.n_ph) e = hipMemcpy(cnt_pe[i].data(), d.cnt_pe, p.n_ph * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && p.n_ph) e = hipMemcpy(cnt_pp[i].data(), d.cnt_pp, p.n_ph * 8, hipMemcpyDeviceToHost);
+    cnt_e[i].resize(nge);
+    cnt_pe[i].resize(ngp);
+    cnt_pp[i].resize(ngp);
+    if (e == hipSuccess && nge) e = hipMemcpy(cnt_e[i].data(), d.cnt_e, nge * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ngp) e = hipMemcpy(cnt_pe[i].data(), d.cnt_pe, ngp * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ngp) e = hipMemcpy(cnt_pp[i].data(), d.cnt_pp, ngp * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
       fail(c, RTBTE_E_HIP, "channel count: %s", hipGetErrorString(e));
       return cleanup(RTBTE_E_HIP);
     }
   }
 
-  // Row pointers over the concatenated state vector.
-  std::vector<int64_t> hptr((size_t)c->ny + 1, 0), hsplit((size_t)c->ny, 0), rowlen((size_t)c->ny, 0);
+  // Group table over the concatenated state vector.
+  std::vector<Group> groups;
+  std::vector<int64_t> glen;
+  std::vector<std::vector<int64_t>> base_e(n_inst), base_pe(n_inst), base_pp(n_inst);
   {
     int64_t pos = 0;
     for (int i = 0; i < n_inst; ++i) {
       const InstInfo& in = c->info[i];
-      for (int32_t r = 0; r < in.n_el; ++r) {
-        const int64_t g = in.off + r;
-        hptr[g] = pos;
-        pos += cnt_e[i][r];
-        hsplit[g] = pos;
-        rowlen[g] = cnt_e[i][r];
-        c->counts[3 * i] += cnt_e[i][r];
+      const int32_t nge = (int32_t)cnt_e[i].size(), ngp = (int32_t)cnt_pe[i].size();
+      base_e[i].resize(nge);
+      base_pe[i].resize(ngp);
+      base_pp[i].resize(ngp);
+      for (int32_t g = 0; g < nge; ++g) {
+        Group gr{};
+        gr.start = pos;
+        base_e[i][g] = pos;
+        pos += cnt_e[i][g];
+        gr.split = gr.end = pos;
+        gr.row0 = (int32_t)(in.off + (int64_t)g * GE);
+        gr.inst = i;
+        gr.nrows = std::min(GE, in.n_el - g * GE);
+        gr.phonon = 0;
+        groups.push_back(gr);
+        glen.push_back(cnt_e[i][g]);
+        c->counts[3 * i] += cnt_e[i][g];
       }
-      for (int32_t q = 0; q < in.n_ph; ++q) {
-        const int64_t g = in.off + in.n_el + q;
-        hptr[g] = pos;
-        pos += cnt_pe[i][q];
-        hsplit[g] = pos;
-        pos += cnt_pp[i][q];
-        rowlen[g] = cnt_pe[i][q] + cnt_pp[i][q];
-        c->counts[3 * i + 1] += cnt_pe[i][q];
-        c->counts[3 * i + 2] += cnt_pp[i][q];
+      for (int32_t g = 0; g < ngp; ++g) {
+        Group gr{};
+        gr.start = pos;
+        base_pe[i][g] = pos;
+        pos += cnt_pe[i][g];
+        gr.split = pos;
+        base_pp[i][g] = pos;
+        pos += cnt_pp[i][g];
+        gr.end = pos;
+        gr.row0 = (int32_t)(in.off + in.n_el + (int64_t)g * GP);
+        gr.inst = i;
+        gr.nrows = std::min(GP, in.n_ph - g * GP);
+        gr.phonon = 1;
+        groups.push_back(gr);
+        glen.push_back(cnt_pe[i][g] + cnt_pp[i][g]);
+        c->counts[3 * i + 1] += cnt_pe[i][g];
+        c->counts[3 * i + 2] += cnt_pp[i][g];
       }
     }
-    hptr[c->ny] = pos;
     c->n_ch = pos;
+    c->n_groups = (int64_t)groups.size();
   }
   hipError_t e = hipSuccess;
   c->ch = dalloc<Channel>((size_t)c->n_ch, &e);
@@ -499,17 +542,10 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
   }
   // Pass 2: write the channels.
   for (int i = 0; i < n_inst; ++i) {
-    const InstInfo& in = c->info[i];
     DevRaw& d = raws[i];
-    std::vector<int64_t> be(in.n_el), bpe(in.n_ph), bpp(in.n_ph);
-    for (int32_t r = 0; r < in.n_el; ++r) be[r] = hptr[in.off + r];
-    for (int32_t q = 0; q < in.n_ph; ++q) {
-      bpe[q] = hptr[in.off + in.n_el + q];
-      bpp[q] = hsplit[in.off + in.n_el + q];
-    }
-    e = upload(&d.base_e, be.data(), be.size());
-    if (e == hipSuccess) e = upload(&d.base_pe, bpe.data(), bpe.size());
-    if (e == hipSuccess) e = upload(&d.base_pp, bpp.data(), bpp.size());
+    e = upload(&d.base_e, base_e[i].data(), base_e[i].size());
+    if (e == hipSuccess) e = upload(&d.base_pe, base_pe[i].data(), base_pe[i].size());
+    if (e == hipSuccess) e = upload(&d.base_pp, base_pp[i].data(), base_pp[i].size());
     pe[i].base = d.base_e; pe[i].out = c->ch;
     ppe[i].base = d.base_pe; ppe[i].out = c->ch;
     ppp[i].base = d.base_pp; ppp[i].out = c->ch;
@@ -524,21 +560,40 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
     d.release();
   }
 
-  // Processing order: longest rows first (stable), phonon rows flagged.
-  std::vector<uint32_t> order((size_t)c->ny);
-  {
-    std::vector<int64_t> idx((size_t)c->ny);
-    for (int64_t g = 0; g < c->ny; ++g) idx[g] = g;
-    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return rowlen[a] > rowlen[b]; });
-    std::vector<uint8_t> isph((size_t)c->ny, 0);
-    for (int i = 0; i < n_inst; ++i)
-      for (int32_t q = 0; q < c->info[i].n_ph; ++q) isph[c->info[i].off + c->info[i].n_el + q] = 1;
-    for (int64_t j = 0; j < c->ny; ++j)
-      order[j] = (uint32_t)idx[j] | (isph[idx[j]] ? kPhononRowBit : 0u);
+  // Work items: each group's channels cut into pieces of at most
+  // item_channels; processing order longest first (stable).
+  int64_t ich = o.item_channels;
+  if (ich == 0) ich = std::min<int64_t>(65536, std::max<int64_t>(2048, c->n_ch / 40960));
+  c->item_channels = ich;
+  std::vector<Item> items;
+  std::vector<int64_t> iptr((size_t)c->n_groups + 1, 0);
+  std::vector<int32_t> rgroup((size_t)c->ny, 0);
+  for (int64_t gi = 0; gi < c->n_groups; ++gi) {
+    const Group& gr = groups[gi];
+    for (int32_t j = 0; j < gr.nrows; ++j) rgroup[(size_t)gr.row0 + j] = (int32_t)gi;
+    const int64_t len = gr.end - gr.start;
+    const int64_t n = len ? (len + ich - 1) / ich : 0;
+    for (int64_t q = 0; q < n; ++q) {
+      Item it{};
+      it.lo = gr.start + len * q / n;
+      it.hi = gr.start + len * (q + 1) / n;
+      it.group = (int32_t)gi;
+      items.push_back(it);
+    }
+    iptr[gi + 1] = (int64_t)items.size();
   }
-  e = upload(&c->ptr, hptr.data(), hptr.size());
-  if (e == hipSuccess) e = upload(&c->split, hsplit.data(), hsplit.size());
+  c->n_items = (int64_t)items.size();
+  std::vector<int32_t> order((size_t)c->n_items);
+  for (int64_t j = 0; j < c->n_items; ++j) order[j] = (int32_t)j;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return items[x].hi - items[x].lo > items[y].hi - items[y].lo;
+  });
+  e = upload(&c->groups, groups.data(), groups.size());
+  if (e == hipSuccess) e = upload(&c->items, items.data(), items.size());
   if (e == hipSuccess) e = upload(&c->order, order.data(), order.size());
+  if (e == hipSuccess) e = upload(&c->item_ptr, iptr.data(), iptr.size());
+  if (e == hipSuccess) e = upload(&c->row_group, rgroup.data(), rgroup.size());
+  if (e == hipSuccess) c->partial_items = dalloc<double>((size_t)std::max<int64_t>(c->n_items, 1) * kMaxGroupRows, &e);
   if (e == hipSuccess && n_inst > 1) {
     std::vector<int32_t> ri((size_t)c->ny);
     for (int i = 0; i < n_inst; ++i)
@@ -571,7 +626,9 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
     fail(c, e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP, "work buffers: %s", hipGetErrorString(e));
     return cleanup(e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP);
   }
-  c->tpr = choose_tpr(c);
+  c->group_rows_el = GE;
+  c->group_rows_ph = GP;
+  c->slots = std::max(GE, GP) == 1 ? 1 : (std::max(GE, GP) <= 8 ? 8 : 16);
   *out = c;
   if (rtbte_reset(c) != RTBTE_OK) {
     std::string msg = c->err;
@@ -629,9 +686,12 @@ extern "C" int rtbte_counts(const rtbte_ctx* c, int32_t inst, int64_t counts[3])
   return RTBTE_OK;
 }
 
-extern "C" int rtbte_get_tuning(const rtbte_ctx* c, int32_t* tpr) {
-  if (!c || !tpr) return RTBTE_E_INVAL;
-  *tpr = c->tpr;
+extern "C" int rtbte_get_tuning(const rtbte_ctx* c, int32_t* group_rows_el, int32_t* group_rows_ph,
+                                int64_t* item_channels) {
+  if (!c) return RTBTE_E_INVAL;
+  if (group_rows_el) *group_rows_el = c->group_rows_el;
+  if (group_rows_ph) *group_rows_ph = c->group_rows_ph;
+  if (item_channels) *item_channels = c->item_channels;
   return RTBTE_OK;
 }
 
@@ -639,14 +699,15 @@ extern "C" int rtbte_get_tuning(const rtbte_ctx* c, int32_t* tpr) {
 namespace {
 
 // Algorithmic bytes of one collision-kernel launch: every stored channel of
-// the selected parts once (16 B), the row bookkeeping (start, split, order),
-// the populations once, and the epilogue's vectors (`vec_rw` reads + writes).
-double launch_bytes(const rtbte_ctx* c, int parts, int vec_rw) {
+// the selected parts once (16 B), the populations once (8 B per state), the
+// group and item tables, and the item row sums written.
+double launch_bytes(const rtbte_ctx* c, int parts) {
   int64_t ch = 0;
   for (int i = 0; i < c->n_inst; ++i)
     for (int k = 0; k < 3; ++k)
       if (parts & (1 << k)) ch += c->counts[3 * i + k];
-  return 16.0 * (double)ch + (double)c->ny * (8.0 + 8.0 + 4.0 + 8.0 + 8.0 * vec_rw);
+  return 16.0 * (double)ch + 8.0 * (double)c->ny + (double)sizeof(Group) * (double)c->n_groups +
+         (double)(sizeof(Item) + 4 + 8 * kMaxGroupRows) * (double)c->n_items;
 }
 
 hipError_t harvest(rtbte_ctx* c) {
@@ -663,36 +724,47 @@ hipError_t harvest(rtbte_ctx* c) {
   return hipSuccess;
 }
 
-hipError_t rows(rtbte_ctx* c, const RowArgs& a, bool stage, int vec_rw, hipStream_t s) {
-  if (!c->prof) return launch_rows(a, c->tpr, stage, s);
-  std::pair<hipEvent_t, hipEvent_t> ev;
-  if (!c->pool.empty()) {
-    ev = c->pool.back();
-    c->pool.pop_back();
-  } else {
-    hipError_t e = hipEventCreate(&ev.first);
-    if (e == hipSuccess) e = hipEventCreate(&ev.second);
-    if (e != hipSuccess) return e;
-  }
-  hipError_t e = hipEventRecord(ev.first, s);
-  if (e == hipSuccess) e = launch_rows(a, c->tpr, stage, s);
-  if (e == hipSuccess) e = hipEventRecord(ev.second, s);
-  c->pending.push_back({ev.first, ev.second, launch_bytes(c, a.parts, vec_rw)});
-  return e;
-}
-
-
-RowArgs row_args(const rtbte_ctx* c, const double* z, int parts) {
+// The right-hand side in two launches: per-item row sums (the collision
+// kernel, the one that streams the channels and is timed when profiling),
+// then the per-row sums of items with the plain or stage epilogue.
+hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState* st, const FinishArgs& f,
+                      bool stage, hipStream_t s) {
   RowArgs a{};
   a.ch = c->ch;
-  a.ptr = c->ptr;
-  a.split = c->split;
+  a.groups = c->groups;
+  a.items = c->items;
   a.order = c->order;
-  a.row_inst = c->row_inst;
-  a.n_rows = c->ny;
+  a.n_items = c->n_items;
   a.parts = parts;
   a.z = z;
-  return a;
+  a.partial = c->partial_items;
+  a.st = st;
+  hipError_t e;
+  if (!c->prof) {
+    e = launch_items(a, c->slots, s);
+  } else {
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (!c->pool.empty()) {
+      ev = c->pool.back();
+      c->pool.pop_back();
+    } else {
+      e = hipEventCreate(&ev.first);
+      if (e == hipSuccess) e = hipEventCreate(&ev.second);
+      if (e != hipSuccess) return e;
+    }
+    e = hipEventRecord(ev.first, s);
+    if (e == hipSuccess) e = launch_items(a, c->slots, s);
+    if (e == hipSuccess) e = hipEventRecord(ev.second, s);
+    c->pending.push_back({ev.first, ev.second, launch_bytes(c, parts)});
+  }
+  if (e != hipSuccess) return e;
+  FinishArgs fa = f;
+  fa.groups = c->groups;
+  fa.row_group = c->row_group;
+  fa.item_ptr = c->item_ptr;
+  fa.partial = c->partial_items;
+  fa.n_rows = c->ny;
+  return launch_finish_rows(fa, stage, s);
 }
 
 }  // namespace
@@ -702,9 +774,9 @@ extern "C" int rtbte_rhs(rtbte_ctx* c, const double* y, double* ydot, int32_t pa
   if (!y || !ydot || parts < 1 || parts > 7) return fail(c, RTBTE_E_INVAL, "rtbte_rhs: bad arguments");
   if (y == ydot) return fail(c, RTBTE_E_INVAL, "rtbte_rhs: y and ydot must not overlap");
   HIPCHK(c, hipSetDevice(c->device));
-  RowArgs a = row_args(c, y, parts);
-  a.out = ydot;
-  HIPCHK(c, rows(c, a, false, 1, (hipStream_t)stream));
+  FinishArgs f{};
+  f.out = ydot;
+  HIPCHK(c, rhs_launch(c, y, parts, nullptr, f, false, (hipStream_t)stream));
   for (int k = 0; k < 3; ++k)
     if (parts & (1 << k)) c->extra_rhs[k]++;
   return RTBTE_OK;
@@ -738,25 +810,24 @@ Ctl make_ctl(const rtbte_options& o, bool fast, bool fixed) {
 // Enqueue one attempted step of tableau `tb` for every live instance of `st`.
 int enqueue_step(rtbte_ctx* c, double* y, int parts, const double* forcing, InstState* st,
                  const Ctl& ctl, const Tableau& tb, hipStream_t s) {
-  RowArgs a = row_args(c, nullptr, parts);
-  a.y = y;
-  a.st = st;
-  a.forcing = forcing;
-  for (int j = 0; j < 5; ++j) a.k[j] = c->kbuf[j];
+  FinishArgs f{};
+  f.y = y;
+  f.st = st;
+  f.forcing = forcing;
+  for (int j = 0; j < 5; ++j) f.k[j] = c->kbuf[j];
   for (int i = 0; i < tb.S; ++i) {
-    a.z = i == 0 ? y : c->zb[i % 2];
-    a.zout = c->zb[(i + 1) % 2];
-    a.stage = i;
-    a.last = i == tb.S - 1;
+    const double* z = i == 0 ? y : c->zb[i % 2];
+    f.zout = c->zb[(i + 1) % 2];
+    f.stage = i;
+    f.last = i == tb.S - 1;
     for (int j = 0; j < 5; ++j) {
-      a.a[j] = (!a.last && j <= i) ? tb.A[i + 1][j] : 0.0;
-      a.b[j] = tb.b[j];
-      a.d[j] = tb.d[j];
+      f.a[j] = (!f.last && j <= i) ? tb.A[i + 1][j] : 0.0;
+      f.b[j] = tb.b[j];
+      f.d[j] = tb.d[j];
     }
-    a.ynew = c->ynew;
-    a.lte = c->lte;
-    // epilogue vectors: y, k_0..k_{i-1} read; k_i and zout (or ynew, lte) written
-    HIPCHK(c, rows(c, a, true, 1 + i + 1 + (a.last ? 2 : 1) + (forcing ? 1 : 0), s));
+    f.ynew = c->ynew;
+    f.lte = c->lte;
+    HIPCHK(c, rhs_launch(c, z, parts, st, f, true, s));
   }
   if (tb.embedded) HIPCHK(c, launch_wrms(c->lte, y, c->info_d, st, c->partial, c->n_inst, c->nchunk, ctl, s));
   HIPCHK(c, launch_control(st, c->partial, c->info_d, c->n_inst, c->nchunk, ctl, s));
@@ -770,9 +841,9 @@ int enqueue_h0(rtbte_ctx* c, double* y, int parts, const double* forcing, InstSt
   const size_t np = (size_t)c->n_inst * c->nchunk;
   double* py = c->partial;
   double* pf = c->partial + np;
-  RowArgs a = row_args(c, y, parts);
-  a.out = c->tmp;  // f0
-  HIPCHK(c, rows(c, a, false, 1, s));
+  FinishArgs f{};
+  f.out = c->tmp;  // f0
+  HIPCHK(c, rhs_launch(c, y, parts, nullptr, f, false, s));
   if (forcing) {
     const double* v[2] = {c->tmp, forcing};
     const double cf[2] = {1.0, 1.0};
@@ -783,9 +854,8 @@ int enqueue_h0(rtbte_ctx* c, double* y, int parts, const double* forcing, InstSt
   HIPCHK(c, launch_wrms(c->tmp, y, c->info_d, nullptr, pf, c->n_inst, c->nchunk, ctl, s));
   HIPCHK(c, launch_h0_stage1(st, py, pf, c->info_d, c->n_inst, c->nchunk, s));
   HIPCHK(c, launch_h0_axpy(c->zb[0], y, c->tmp, c->row_inst, st, c->ny, s));
-  a.z = c->zb[0];
-  a.out = c->tmp2;  // f1
-  HIPCHK(c, rows(c, a, false, 1, s));
+  f.out = c->tmp2;  // f1
+  HIPCHK(c, rhs_launch(c, c->zb[0], parts, nullptr, f, false, s));
   if (forcing) {
     const double* v[2] = {c->tmp2, forcing};
     const double cf[2] = {1.0, 1.0};
@@ -893,9 +963,9 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
     const bool last = tc + hs >= t_out;
     if (last) hs = t_out - tc;
     // slow right-hand side at z_1
-    RowArgs a = row_args(c, y, RTBTE_PART_PHPH);
-    a.out = c->fs[0];
-    HIPCHK(c, rows(c, a, false, 1, s));
+    FinishArgs f{};
+    f.out = c->fs[0];
+    HIPCHK(c, rhs_launch(c, y, RTBTE_PART_PHPH, nullptr, f, false, s));
     c->extra_rhs[2]++;
     for (int i = 1; i < 4; ++i) {
       const double* v[3] = {c->fs[0], c->fs[1], c->fs[2]};
@@ -929,9 +999,8 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
       }
       if (rc) return rc;
       if (i < 3) {
-        a.z = y;
-        a.out = c->fs[i];
-        HIPCHK(c, rows(c, a, false, 1, s));
+        f.out = c->fs[i];
+        HIPCHK(c, rhs_launch(c, y, RTBTE_PART_PHPH, nullptr, f, false, s));
         c->extra_rhs[2]++;
       }
     }

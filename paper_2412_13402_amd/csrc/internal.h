@@ -12,12 +12,17 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kSqrtPi = 1.7724538509055160273;
 constexpr uint32_t kEmBit = 0x80000000u;            // channel kind bit: emission
 constexpr uint32_t kIdxMask = 0x7fffffffu;
-constexpr uint32_t kPhononRowBit = 0x80000000u;     // row-order flag: phonon row
+constexpr int32_t kTagShift = 27;                   // row tag inside a group: bits 27..30 of i0
+constexpr int32_t kPosMask = 0x07ffffff;            // state index: bits 0..26 of i0 / i1
+constexpr int kMaxGroupRows = 16;
 
 // A stored channel, 16 bytes, streamed once per right-hand-side evaluation.
-//   electron row r  (I^{e-ph}):  i0 = partner electron s, i1 = phonon p | em bit
-//   phonon row p, ph-e range     i0 = electron r,         i1 = electron s (absorption)
-//   phonon row l, ph-ph range    i0 = phonon a,           i1 = phonon b | em bit
+// Channels of a group of up to 16 consecutive destination rows are stored
+// together, merged in partner order; bits 27..30 of i0 say which row of the
+// group the channel belongs to.
+//   electron rows (I^{e-ph}):  i0 = partner electron s | tag, i1 = phonon p | em bit
+//   phonon rows, ph-e range    i0 = electron r | tag,         i1 = electron s (absorption)
+//   phonon rows, ph-ph range   i0 = phonon a | tag,           i1 = phonon b | em bit
 // Indices are positions in the concatenated state vector y; w already holds
 // prefactor * |M|^2 * delta (and the factor 2 of ph-ph absorption).
 struct Channel {
@@ -26,6 +31,18 @@ struct Channel {
   double w;
 };
 static_assert(sizeof(Channel) == 16, "channel must be 16 bytes");
+
+// A group of consecutive destination rows of one kind (electron or phonon)
+// of one instance, and its channel ranges.
+struct Group {
+  int64_t start;   // first channel
+  int64_t split;   // phonon groups: end of the ph-e channels, start of ph-ph; electron: = end
+  int64_t end;
+  int32_t row0;    // first row (position in y)
+  int32_t inst;
+  int32_t nrows;   // 1..16
+  int32_t phonon;  // 1: phonon rows
+};
 
 // Per-instance integrator state, resident on the device.
 struct InstState {
@@ -47,16 +64,35 @@ struct Ctl {
   int32_t stages;                      // right-hand-side evaluations per attempt
 };
 
-// Arguments of the destination-row kernel.
+// A work item: a bounded range of one group's channels, streamed by one
+// wavefront, which writes the item's sum for every row of the group.
+struct Item {
+  int64_t lo, hi;  // channel range, inside [start, end) of its group
+  int32_t group;
+  int32_t pad;
+};
+
+// Arguments of the collision kernel (per-item row sums).
 struct RowArgs {
   const Channel* ch;
-  const int64_t* ptr;       // [n_rows + 1] row starts
-  const int64_t* split;     // [n_rows] end of the ph-e range (phonon rows); = end for electron rows
-  const uint32_t* order;    // [n_rows] processing order; bit 31 marks phonon rows
-  const int32_t* row_inst;  // [n_rows] instance of each row, or nullptr (single instance)
-  int64_t n_rows;
+  const Group* groups;
+  const Item* items;
+  const int32_t* order;     // [n_items] processing order (longest first)
+  int64_t n_items;
   int32_t parts;
   const double* z;          // populations the integrals are evaluated at
+  double* partial;          // [n_items][kMaxGroupRows] row sums of each item
+  const InstState* st;      // stage mode: items of finished instances are skipped (else nullptr)
+};
+
+// Arguments of the row kernel: sums of the items of each row's group, the
+// sign of the collision integral, and the plain or ERK-stage epilogue.
+struct FinishArgs {
+  const Group* groups;
+  const int32_t* row_group; // [n_rows] group of each row
+  const int64_t* item_ptr;  // [n_groups + 1] items of each group
+  const double* partial;
+  int64_t n_rows;
   double* out;              // plain mode: f(z)
   // stage mode
   const double* y;          // y_{n-1}
@@ -71,7 +107,8 @@ struct RowArgs {
 };
 
 // Launchers (kernels.hip)
-hipError_t launch_rows(const RowArgs& a, int tpr, bool stage_mode, hipStream_t s);
+hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s);
+hipError_t launch_finish_rows(const FinishArgs& f, bool stage, hipStream_t s);
 hipError_t launch_wrms(const double* v, const double* y, const InstInfo* info, const InstState* st,
                        double* partial, int n_inst, int nchunk, Ctl c, hipStream_t s);
 hipError_t launch_control(InstState* st, const double* partial, const InstInfo* info, int n_inst,
@@ -95,22 +132,23 @@ hipError_t launch_lincomb(double* out, const double* const* vecs, const double* 
 
 // Create-time channel preparation (kernels.hip)
 struct PrepArgs {
-  // raw entries of one instance (device), optionally visited through perm
+  // raw entries of one instance (device), visited through perm (nullptr: identity)
   const int32_t* row;
   const int32_t* i0;
   const int32_t* i1;
   const double* val;
-  const int64_t* perm;      // nullptr: identity
-  const int64_t* raw_ptr;   // [n_dest + 1] raw entries of each destination row (in visiting order)
-  int32_t n_dest;
+  const int64_t* perm;
+  const int64_t* raw_ptr;   // [n_dest + 1] raw entries of each destination group (in visiting order)
+  int32_t n_dest;           // destination groups
+  int32_t group_rows;       // rows per group (groups start at multiples of it)
   const double* eps;        // instance band energies (device)
   const double* hw;         // instance phonon energies (device)
   double sigma, cut, pre, pre2, hw_cut;
   int64_t y_off;            // instance offset in y
   int32_t n_el;
   int32_t kind;             // 0 e-ph electron side, 1 ph-e, 2 ph-ph
-  int64_t* count;           // [n_dest] kept channels per row (count pass)
-  const int64_t* base;      // [n_dest] first output slot of each row (fill pass)
+  int64_t* count;           // [n_dest] kept channels per group (count pass)
+  const int64_t* base;      // [n_dest] first output slot of each group (fill pass)
   Channel* out;
 };
 hipError_t launch_prep_count(const PrepArgs& p, hipStream_t s);

@@ -2,15 +2,18 @@
 // lists, ERK stage updates, WRMS reduction, step control, and the create-time
 // channel preparation.
 //
-// Collision integrals (Methods, Eq. (e-ph) and Eq. (ph-ph)).  One group of TPR
-// lanes owns one destination row of y' and streams that row's channels once,
-// 16 bytes each, with non-temporal loads; lanes stride by TPR so every load
-// instruction of a wavefront reads a contiguous block.  The two populations a
-// channel needs are gathered from the (L2-resident) state vector.  The row sum
-// is reduced inside the group (cross-lane shuffles, LDS when a row spans
-// several wavefronts); no atomics, so results are deterministic.  Rows are
-// visited in a precomputed order, longest first, so long rows never straggle
-// at the end of the grid.
+// Collision integrals (Methods, Eq. (e-ph) and Eq. (ph-ph)).  Destination rows
+// of y' form groups of up to 16 consecutive rows of one kind; a group's
+// channels are cut into work items of bounded length, each streamed once by
+// one wavefront, 16 bytes per channel, with non-temporal loads; lanes stride
+// by 64 so every load instruction reads a contiguous 1 KB block.  The group's channels are stored
+// merged in partner order, so rows that share partners (the modes of one
+// phonon wave vector; neighbouring electron k-points) gather their
+// populations from the same cache lines at the same time.  Each lane keeps
+// one accumulator per row of the group in its own LDS slots; the slots are
+// summed in a fixed order at the end, with no atomics, so results are
+// deterministic.  Groups are visited longest first,
+// so long groups never straggle at the end of the grid.
 #include "internal.h"
 
 namespace rtbte {
@@ -55,125 +58,180 @@ __device__ __forceinline__ double term(const v4i c, double g0, double g1, double
   }
 }
 
-template <int TPR, int KIND>
-__device__ __forceinline__ double seg_sum(const Channel* __restrict__ ch, int64_t s, int64_t e,
-                                          int lane, const double* __restrict__ z, double xr,
-                                          double xr1) {
-  double acc0 = 0.0, acc1 = 0.0;
+// Per-lane accumulators of one wavefront: one slot per (row of the group,
+// lane), so every lane adds only to its own slots (in a fixed order: the
+// sums stay deterministic) without per-row selects in registers.
+template <int G>
+struct LaneAcc {
+  double* slot;   // this lane's first slot; row j at slot[64 * j]
+  double reg;     // G == 1: the accumulator itself
+  __device__ __forceinline__ void add(int tag, double v) {
+    if (G == 1) reg += v;
+    else slot[64 * tag] += v;
+  }
+};
+
+// One channel: w * factor with the gathered partner populations g0, g1 and
+// the row's own population (kept in LDS), added to the accumulator of its row.
+template <int G, int KIND>
+__device__ __forceinline__ void chan_acc(LaneAcc<G>& acc, const v4i c, double g0, double g1,
+                                         const double* rowv) {
+  const int tag = G == 1 ? 0 : ((c.x >> kTagShift) & 15);
+  const double xr = rowv[tag];
+  const double xr1 = KIND == K_EPH ? 1.0 - xr : xr + 1.0;
+  acc.add(tag, term<KIND>(c, g0, g1, xr, xr1));
+}
+
+// Stream [s, e) with a two-stage software pipeline: the gathers of batch k
+// are issued before the stream loads of batch k+1, so waiting for the
+// gathers (in-order completion counters) leaves the next batch in flight.
+template <int G, int LANES, int KIND>
+__device__ __forceinline__ void seg_sum(LaneAcc<G>& acc, const Channel* __restrict__ ch, int64_t s,
+                                        int64_t e, int lane, const double* __restrict__ z,
+                                        const double* rowv) {
+  constexpr int64_t STEP = 4 * LANES;
   int64_t i = s + lane;
-  for (; i + 3 * TPR < e; i += 4 * TPR) {
-    const v4i c0 = ld_stream(ch + i);
-    const v4i c1 = ld_stream(ch + i + TPR);
-    const v4i c2 = ld_stream(ch + i + 2 * TPR);
-    const v4i c3 = ld_stream(ch + i + 3 * TPR);
-    const double a0 = z[c0.x], b0 = z[c0.y & kIdxMask];
-    const double a1 = z[c1.x], b1 = z[c1.y & kIdxMask];
-    const double a2 = z[c2.x], b2 = z[c2.y & kIdxMask];
-    const double a3 = z[c3.x], b3 = z[c3.y & kIdxMask];
-    acc0 += term<KIND>(c0, a0, b0, xr, xr1);
-    acc1 += term<KIND>(c1, a1, b1, xr, xr1);
-    acc0 += term<KIND>(c2, a2, b2, xr, xr1);
-    acc1 += term<KIND>(c3, a3, b3, xr, xr1);
-  }
-  for (; i < e; i += TPR) {
-    const v4i c0 = ld_stream(ch + i);
-    acc0 += term<KIND>(c0, z[c0.x], z[c0.y & kIdxMask], xr, xr1);
-  }
-  return acc0 + acc1;
-}
-
-// Sum over the TPR lanes of a group; the result is valid in the group's lane 0.
-template <int TPR>
-__device__ __forceinline__ double group_sum(double v, double* red) {
-  constexpr int W = TPR < 64 ? TPR : 64;
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
-  if (TPR > 64) {
-    const int wave = threadIdx.x / 64;
-    if ((threadIdx.x & 63) == 0) red[wave] = v;
-    __syncthreads();
-    if ((threadIdx.x % TPR) == 0) {
-      v = 0.0;
-      for (int j = 0; j < TPR / 64; ++j) v += red[wave + j];
+  if (i + 3 * LANES < e) {
+    v4i c0 = ld_stream(ch + i), c1 = ld_stream(ch + i + LANES);
+    v4i c2 = ld_stream(ch + i + 2 * LANES), c3 = ld_stream(ch + i + 3 * LANES);
+    i += STEP;
+    for (;;) {
+      const double a0 = z[c0.x & kPosMask], b0 = z[c0.y & kPosMask];
+      const double a1 = z[c1.x & kPosMask], b1 = z[c1.y & kPosMask];
+      const double a2 = z[c2.x & kPosMask], b2 = z[c2.y & kPosMask];
+      const double a3 = z[c3.x & kPosMask], b3 = z[c3.y & kPosMask];
+      const bool more = i + 3 * LANES < e;
+      v4i n0 = c0, n1 = c1, n2 = c2, n3 = c3;
+      if (more) {
+        n0 = ld_stream(ch + i);
+        n1 = ld_stream(ch + i + LANES);
+        n2 = ld_stream(ch + i + 2 * LANES);
+        n3 = ld_stream(ch + i + 3 * LANES);
+      }
+      chan_acc<G, KIND>(acc, c0, a0, b0, rowv);
+      chan_acc<G, KIND>(acc, c1, a1, b1, rowv);
+      chan_acc<G, KIND>(acc, c2, a2, b2, rowv);
+      chan_acc<G, KIND>(acc, c3, a3, b3, rowv);
+      if (!more) break;
+      c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+      i += STEP;
     }
   }
-  return v;
+  for (; i < e; i += LANES) {
+    const v4i c = ld_stream(ch + i);
+    chan_acc<G, KIND>(acc, c, z[c.x & kPosMask], z[c.y & kPosMask], rowv);
+  }
 }
 
-template <int TPR, bool STAGE>
-__global__ __launch_bounds__(256) void k_rows(RowArgs a) {
-  constexpr int RPB = 256 / TPR;
-  __shared__ double red[4];
-  const int lane = threadIdx.x % TPR;
-  const int64_t gi = (int64_t)blockIdx.x * RPB + threadIdx.x / TPR;
-  bool active = gi < a.n_rows;
-  const uint32_t ro = active ? a.order[gi] : 0u;
-  const int64_t row = ro & kIdxMask;
-  const bool phonon = (ro & kPhononRowBit) != 0;
-  const int inst = (active && a.row_inst) ? a.row_inst[row] : 0;
-  if (STAGE && active && a.st[inst].done) active = false;
-  double acc = 0.0;
+template <int G>
+__global__ __launch_bounds__(256) void k_items(RowArgs a) {
+  __shared__ double acc_lds[4][G][64];
+  __shared__ double rowv[4][kMaxGroupRows];
+  const int wave = threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t ii = (int64_t)blockIdx.x * 4 + wave;
+  bool active = ii < a.n_items;
+  int64_t it = 0;
+  Item item{};
+  Group g{};
   if (active) {
-    const double xr = a.z[row];
-    const int64_t s = a.ptr[row], m = a.split[row], e = a.ptr[row + 1];
-    if (!phonon) {
-      if (a.parts & 1) acc = seg_sum<TPR, K_EPH>(a.ch, s, e, lane, a.z, xr, 1.0 - xr);
+    it = a.order[ii];
+    item = a.items[it];
+    g = a.groups[item.group];
+    if (a.st && a.st[g.inst].done) active = false;
+  }
+  if (G > 1) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) acc_lds[wave][j][lane] = 0.0;
+  }
+  if (active && lane < g.nrows) rowv[wave][lane] = a.z[g.row0 + lane];
+  __syncthreads();
+  LaneAcc<G> acc{&acc_lds[wave][0][lane], 0.0};
+  if (active) {
+    const double* rv = rowv[wave];
+    if (!g.phonon) {
+      if (a.parts & 1) seg_sum<G, 64, K_EPH>(acc, a.ch, item.lo, item.hi, lane, a.z, rv);
     } else {
-      if (a.parts & 2) acc = seg_sum<TPR, K_PHE>(a.ch, s, m, lane, a.z, xr, xr + 1.0);
-      if (a.parts & 4) acc += seg_sum<TPR, K_PP>(a.ch, m, e, lane, a.z, xr, xr + 1.0);
+      const int64_t m = g.split;
+      if (a.parts & 2) seg_sum<G, 64, K_PHE>(acc, a.ch, item.lo, item.hi < m ? item.hi : m, lane, a.z, rv);
+      if (a.parts & 4) seg_sum<G, 64, K_PP>(acc, a.ch, item.lo > m ? item.lo : m, item.hi, lane, a.z, rv);
     }
   }
-  acc = group_sum<TPR>(acc, red);
-  if (!active || lane != 0) return;
-  double kv = -acc;
-  if (!STAGE) {
-    a.out[row] = kv;
-    return;
-  }
-  if (a.forcing && phonon) kv += a.forcing[row];
-  const double h = a.st[inst].h_use;
-  const double yr = a.y[row];
-  a.k[a.stage][row] = kv;
-  if (!a.last) {
-    double sum = 0.0;
-    for (int j = 0; j < a.stage; ++j) sum += a.a[j] * a.k[j][row];
-    sum += a.a[a.stage] * kv;
-    a.zout[row] = yr + h * sum;
+  if (G == 1) {
+    double v = acc.reg;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (active && lane == 0) a.partial[it * kMaxGroupRows] = v;
   } else {
-    double sb = 0.0, sd = 0.0;
-    for (int j = 0; j < a.stage; ++j) {
-      const double kj = a.k[j][row];
-      sb += a.b[j] * kj;
-      sd += a.d[j] * kj;
+    __syncthreads();
+    if (active && lane < g.nrows) {
+      // row `lane` of the group: its slot in every lane, in lane order
+      const double* p = acc_lds[wave][lane];
+      double s = 0.0;
+      for (int l = 0; l < 64; ++l) s += p[l];
+      a.partial[it * kMaxGroupRows + lane] = s;
     }
-    sb += a.b[a.stage] * kv;
-    sd += a.d[a.stage] * kv;
-    a.ynew[row] = yr + h * sb;
-    a.lte[row] = h * sd;
   }
 }
 
-template <int TPR>
-static hipError_t launch_rows_t(const RowArgs& a, bool stage, hipStream_t s) {
-  constexpr int RPB = 256 / TPR;
-  const int64_t nb = (a.n_rows + RPB - 1) / RPB;
+hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s) {
+  const int64_t nb = (a.n_items + 3) / 4;
   if (nb == 0) return hipSuccess;
-  if (stage)
-    hipLaunchKernelGGL((k_rows<TPR, true>), dim3((unsigned)nb), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_rows<TPR, false>), dim3((unsigned)nb), dim3(256), 0, s, a);
+  switch (slots) {
+    case 1: hipLaunchKernelGGL(k_items<1>, dim3((unsigned)nb), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_items<8>, dim3((unsigned)nb), dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(k_items<16>, dim3((unsigned)nb), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_rows(const RowArgs& a, int tpr, bool stage, hipStream_t s) {
-  switch (tpr) {
-    case 16: return launch_rows_t<16>(a, stage, s);
-    case 32: return launch_rows_t<32>(a, stage, s);
-    case 64: return launch_rows_t<64>(a, stage, s);
-    case 128: return launch_rows_t<128>(a, stage, s);
-    case 256: return launch_rows_t<256>(a, stage, s);
-    default: return hipErrorInvalidValue;
+// One thread per row: the row's collision integral is minus the sum of its
+// group's item sums (in item order), then the plain or stage epilogue.
+template <bool STAGE>
+__global__ __launch_bounds__(256) void k_finish_rows(FinishArgs f) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= f.n_rows) return;
+  const int32_t gi = f.row_group[row];
+  const Group g = f.groups[gi];
+  if (STAGE && f.st[g.inst].done) return;
+  const int j = (int)(row - g.row0);
+  double tot = 0.0;
+  for (int64_t it = f.item_ptr[gi]; it < f.item_ptr[gi + 1]; ++it) tot += f.partial[it * kMaxGroupRows + j];
+  double kv = -tot;
+  if (!STAGE) {
+    f.out[row] = kv;
+    return;
   }
+  if (f.forcing && g.phonon) kv += f.forcing[row];
+  const double h = f.st[g.inst].h_use;
+  const double yr = f.y[row];
+  f.k[f.stage][row] = kv;
+  if (!f.last) {
+    double sum = 0.0;
+    for (int q = 0; q < f.stage; ++q) sum += f.a[q] * f.k[q][row];
+    sum += f.a[f.stage] * kv;
+    f.zout[row] = yr + h * sum;
+  } else {
+    double sb = 0.0, sd = 0.0;
+    for (int q = 0; q < f.stage; ++q) {
+      const double kq = f.k[q][row];
+      sb += f.b[q] * kq;
+      sd += f.d[q] * kq;
+    }
+    sb += f.b[f.stage] * kv;
+    sd += f.d[f.stage] * kv;
+    f.ynew[row] = yr + h * sb;
+    f.lte[row] = h * sd;
+  }
+}
+
+hipError_t launch_finish_rows(const FinishArgs& f, bool stage, hipStream_t s) {
+  if (f.n_rows == 0) return hipSuccess;
+  const unsigned nb = (unsigned)((f.n_rows + 255) / 256);
+  if (stage) hipLaunchKernelGGL(k_finish_rows<true>, dim3(nb), dim3(256), 0, s, f);
+  else hipLaunchKernelGGL(k_finish_rows<false>, dim3(nb), dim3(256), 0, s, f);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ WRMS norm
@@ -474,12 +532,13 @@ hipError_t launch_lincomb(double* out, const double* const* vecs, const double* 
 }
 
 // ------------------------------------------------ create-time channel preparation
-// One wavefront per destination row walks the row's raw entries in input
-// order, decides which channels are kept (energy mismatch within the
-// truncation, no phonon below the cutoff), and either counts them or writes
-// them with their weights prefactor * |M|^2 * delta(mismatch).  Positions
-// inside the row come from ballots, so the output order is the input order
-// (emission before absorption for one entry).
+// One wavefront per destination group walks the group's raw entries in their
+// merged visiting order, decides which channels are kept (energy mismatch
+// within the truncation, no phonon below the cutoff), and either counts them
+// or writes them, tagged with their row in the group, with their weights
+// prefactor * |M|^2 * delta(mismatch).  Positions come from ballots, so the
+// output order is the visiting order (emission before absorption for one
+// entry).
 __device__ __forceinline__ double gdelta(double x, double sigma) {
   const double u = x / sigma;
   return exp(-u * u) / (sigma * kSqrtPi);
@@ -487,10 +546,16 @@ __device__ __forceinline__ double gdelta(double x, double sigma) {
 
 struct Kept { bool em, ab; double wem, wab; int32_t o0; uint32_t o1; };
 
+// Destination row (instance-local) of a raw entry in the list being prepared.
+__device__ __forceinline__ int32_t dest_of(const PrepArgs& p, int64_t e) {
+  return p.kind == 1 ? p.i1[e] : p.row[e];
+}
+
 __device__ __forceinline__ Kept classify(const PrepArgs& p, int64_t j) {
   Kept k{false, false, 0.0, 0.0, 0, 0u};
   const int64_t e = p.perm ? p.perm[j] : j;
   const int32_t r = p.row[e], a = p.i0[e], b = p.i1[e];
+  const int32_t tag = (dest_of(p, e) % p.group_rows) << kTagShift;
   const double v = p.val[e];
   if (p.kind == 2) {  // ph-ph: row l, partners a, b
     const double w = p.hw[r], wa = p.hw[a], wb = p.hw[b];
@@ -502,7 +567,7 @@ __device__ __forceinline__ Kept classify(const PrepArgs& p, int64_t j) {
     if (k.em) k.wem = p.pre * v * gdelta(x_em, p.sigma);
     if (k.ab) k.wab = p.pre2 * v * gdelta(x_ab, p.sigma);
     const int64_t base = p.y_off + p.n_el;
-    k.o0 = (int32_t)(base + a);
+    k.o0 = (int32_t)(base + a) | tag;
     k.o1 = (uint32_t)(base + b);
     return k;
   }
@@ -516,12 +581,12 @@ __device__ __forceinline__ Kept classify(const PrepArgs& p, int64_t j) {
     k.ab = fabs(x_ab) <= p.cut;
     if (k.em) k.wem = p.pre * v * gdelta(x_em, p.sigma);
     if (k.ab) k.wab = p.pre * v * gdelta(x_ab, p.sigma);
-    k.o0 = (int32_t)(p.y_off + a);
+    k.o0 = (int32_t)(p.y_off + a) | tag;
     k.o1 = (uint32_t)(p.y_off + p.n_el + b);
   } else {  // ph-e: the absorption process seen from the phonon
     k.ab = fabs(x_ab) <= p.cut;
     if (k.ab) k.wab = p.pre * v * gdelta(x_ab, p.sigma);
-    k.o0 = (int32_t)(p.y_off + r);
+    k.o0 = (int32_t)(p.y_off + r) | tag;
     k.o1 = (uint32_t)(p.y_off + a);
   }
   return k;
@@ -529,10 +594,10 @@ __device__ __forceinline__ Kept classify(const PrepArgs& p, int64_t j) {
 
 __global__ __launch_bounds__(256) void k_prep(PrepArgs p, int fill) {
   const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (row >= p.n_dest) return;
-  const int64_t lo = p.raw_ptr[row], hi = p.raw_ptr[row + 1];
-  int64_t pos = fill ? p.base[row] : 0;
+  const int64_t grp = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (grp >= p.n_dest) return;
+  const int64_t lo = p.raw_ptr[grp], hi = p.raw_ptr[grp + 1];
+  int64_t pos = fill ? p.base[grp] : 0;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int64_t j0 = lo; j0 < hi; j0 += 64) {
     const int64_t j = j0 + lane;
@@ -546,7 +611,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs p, int fill) {
     }
     pos += __popcll(bem) + __popcll(bab);
   }
-  if (!fill && lane == 0) p.count[row] = pos;
+  if (!fill && lane == 0) p.count[grp] = pos;
 }
 
 hipError_t launch_prep_count(const PrepArgs& p, hipStream_t s) {

@@ -57,7 +57,8 @@ class Options(ctypes.Structure):
         ("eta_max_first", ctypes.c_double), ("eta_fail_min", ctypes.c_double),
         ("eta_fail_max", ctypes.c_double), ("eps_floor", ctypes.c_double),
         ("max_fails", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-        ("steps_per_poll", ctypes.c_int32), ("threads_per_row", ctypes.c_int32),
+        ("steps_per_poll", ctypes.c_int32), ("group_rows_el", ctypes.c_int32),
+        ("group_rows_ph", ctypes.c_int32), ("item_channels", ctypes.c_int64),
         ("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
     ]
 
@@ -109,7 +110,7 @@ def load():
     L.rtbte_step_multirate.argtypes = [_vp, _vp, _vp, _vp, dbl, dbl, i32, _vp]
     L.rtbte_reset.argtypes = [_vp]
     L.rtbte_get_stats.argtypes = [_vp, i32, ctypes.POINTER(Stats)]
-    L.rtbte_get_tuning.argtypes = [_vp, ctypes.POINTER(i32)]
+    L.rtbte_get_tuning.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.rtbte_get_state.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]
     L.rtbte_set_state.argtypes = [_vp, _vp, ctypes.c_size_t]
     L.rtbte_profile.argtypes = [_vp, i32]
@@ -238,10 +239,11 @@ class Context:
         self._check(load().rtbte_get_stats(self._h, inst, ctypes.byref(s)))
         return s.as_dict()
 
-    def tuning(self) -> int:
-        t = ctypes.c_int32()
-        self._check(load().rtbte_get_tuning(self._h, ctypes.byref(t)))
-        return t.value
+    def tuning(self):
+        """(electron rows per group, phonon rows per group, channels per item)."""
+        ge, gp, ic = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        self._check(load().rtbte_get_tuning(self._h, ctypes.byref(ge), ctypes.byref(gp), ctypes.byref(ic)))
+        return ge.value, gp.value, ic.value
 
     def profile(self, enable=True):
         self._check(load().rtbte_profile(self._h, int(bool(enable))))

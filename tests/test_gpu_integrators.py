@@ -221,7 +221,7 @@ def test_batched_instances_advance_independently():
         probs.append(Pr)
         ys.append(y0)
     say("[int] three instances, own steps")
-    multi = P.Context(probs, rtol=1e-6, threads_per_row=32)
+    multi = P.Context(probs, rtol=1e-6, group_rows_el=4, group_rows_ph=4, item_channels=512)
     y = to_dev(np.concatenate(ys))
     t = torch.zeros(3, dtype=torch.float64, device="cuda")
     h = torch.full((3,), 0.1, dtype=torch.float64, device="cuda")
@@ -230,7 +230,7 @@ def test_batched_instances_advance_independently():
     got = y.cpu().numpy()
     assert np.all(t.cpu().numpy() == 20.0)
     for i in range(3):
-        single = P.Context(probs[i], rtol=1e-6, threads_per_row=32)
+        single = P.Context(probs[i], rtol=1e-6, group_rows_el=4, group_rows_ph=4, item_channels=512)
         yi = to_dev(ys[i])
         ti = torch.zeros(1, dtype=torch.float64, device="cuda")
         hi = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")

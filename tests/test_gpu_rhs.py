@@ -67,21 +67,28 @@ def test_rhs_matches_oracle(name):
             assert_rows_close(out.cpu().numpy(), ref, A, TOL, f"{name} seed {seed} parts {parts}")
 
 
-@pytest.mark.parametrize("tpr", [16, 32, 64, 128, 256])
-def test_every_launch_shape(tpr):
+SHAPES = [(1, 1, 0), (2, 4, 0), (4, 8, 0), (8, 16, 0), (16, 12, 0), (12, 2, 0),
+          (8, 16, 1000), (16, 16, 333), (1, 16, 64), (4, 4, 10 ** 7)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("name", ["medium2d", "tiny3d"])
+def test_every_launch_shape(name, shape):
     torch = torch_cuda()
     import paper_2412_13402_amd as P
-    wl = workload("medium2d")
-    o = oracle_of("medium2d")
-    say(f"[rhs] medium2d tpr={tpr}")
-    ctx = P.Context(wl.problem_arrays(), threads_per_row=tpr)
-    assert ctx.tuning() == tpr
+    ge, gp, ic = shape
+    wl = workload(name)
+    o = oracle_of(name)
+    say(f"[rhs] {name} group_rows_el={ge} group_rows_ph={gp} item_channels={ic}")
+    ctx = P.Context(wl.problem_arrays(), group_rows_el=ge, group_rows_ph=gp, item_channels=ic)
+    assert ctx.tuning()[:2] == (ge, gp) and (ic == 0 or ctx.tuning()[2] == ic)
+    assert ctx.counts() == o.counts()
     y = random_state(wl, 5)
     out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
     ctx.rhs(to_dev(y), out, 7)
     torch.cuda.synchronize()
     ref, S, A = o.rhs(y, parts=7, scales=True)
-    assert_rows_close(out.cpu().numpy(), ref, A, TOL, f"tpr {tpr}")
+    assert_rows_close(out.cpu().numpy(), ref, A, TOL, f"shape {shape}")
 
 
 def test_empty_lists_give_zero():
@@ -132,7 +139,7 @@ def test_multi_instance_context_matches_single():
     names = ["toy2d", "tiny2d", "tiny3d"]
     probs = [workload(n).problem_arrays() for n in names]
     say("[rhs] three instances in one context")
-    multi = P.Context(probs, threads_per_row=32)
+    multi = P.Context(probs, group_rows_el=4, group_rows_ph=4, item_channels=512)
     ys = [random_state(workload(n), 9 + i) for i, n in enumerate(names)]
     y = np.concatenate(ys)
     assert multi.ny == len(y)
@@ -142,7 +149,7 @@ def test_multi_instance_context_matches_single():
     got = out.cpu().numpy()
     for i, n in enumerate(names):
         off, ne, nph = multi.layout(i)
-        single = P.Context(probs[i], threads_per_row=32)
+        single = P.Context(probs[i], group_rows_el=4, group_rows_ph=4, item_channels=512)
         o1 = torch.empty((ne + nph,), dtype=torch.float64, device="cuda")
         single.rhs(to_dev(ys[i]), o1, 7)
         torch.cuda.synchronize()
@@ -166,7 +173,7 @@ def test_rhs_is_deterministic():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("bad", ["row", "sigma", "tpr"])
+@pytest.mark.parametrize("bad", ["row", "sigma", "shape"])
 def test_invalid_create_is_rejected(bad):
     torch_cuda()
     import paper_2412_13402_amd as P
@@ -179,7 +186,7 @@ def test_invalid_create_is_rejected(bad):
     elif bad == "sigma":
         Pr["sigma_eph"] = -1.0
     else:
-        kw["threads_per_row"] = 48
+        kw["group_rows_el"] = 3
     with pytest.raises(P.RtbteError) as e:
         P.Context(Pr, **kw)
     assert e.value.code == P.rtbte.E_INVAL
