@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--item-channels", type=int, default=0, help="channels per work item (0: library choice)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (a known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -101,6 +103,13 @@ def main():
     from __graft_entry__ import _ensure_built
     _ensure_built()
 
+    if args.calibrate_copy:
+        src = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     over = {} if args.L is None else {"L": args.L}
     t0 = time.perf_counter()
     wl = synth.build(args.workload, **over)

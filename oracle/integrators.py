@@ -11,6 +11,10 @@ Plain numpy, FP64, one vector operation per formula term:
 * ``Adaptive``           the accept/reject loop of the ERK method;
 * ``mis_step``           one slow step of the MRI algorithm with the MIS coupling
                          Eq. (mis_coef) built from the Knoth-Wolke 3-stage ERK.
+
+``hnw_initial_step`` (the starting-step heuristic, not from the paper) is
+parity unpinned: nothing fixes its value independently; it is only compared
+with the GPU's starting step.
 """
 from __future__ import annotations
 

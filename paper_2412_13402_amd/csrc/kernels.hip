@@ -123,13 +123,15 @@ __device__ __forceinline__ void seg_sum(LaneAcc<G>& acc, const Channel* __restri
   }
 }
 
+// One wavefront per block, so the LDS a block needs is one wavefront's
+// accumulator slots and occupancy is not capped by whole 4-wave blocks.
 template <int G>
-__global__ __launch_bounds__(256) void k_items(RowArgs a) {
-  __shared__ double acc_lds[4][G][64];
-  __shared__ double rowv[4][kMaxGroupRows];
-  const int wave = threadIdx.x / 64;
+__global__ __launch_bounds__(64) void k_items(RowArgs a) {
+  __shared__ double acc_lds[1][G][64];
+  __shared__ double rowv[1][kMaxGroupRows];
+  const int wave = 0;
   const int lane = threadIdx.x & 63;
-  const int64_t ii = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t ii = blockIdx.x;
   bool active = ii < a.n_items;
   int64_t it = 0;
   Item item{};
@@ -175,12 +177,12 @@ __global__ __launch_bounds__(256) void k_items(RowArgs a) {
 }
 
 hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s) {
-  const int64_t nb = (a.n_items + 3) / 4;
+  const int64_t nb = a.n_items;
   if (nb == 0) return hipSuccess;
   switch (slots) {
-    case 1: hipLaunchKernelGGL(k_items<1>, dim3((unsigned)nb), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_items<8>, dim3((unsigned)nb), dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL(k_items<16>, dim3((unsigned)nb), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_items<1>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_items<8>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(k_items<16>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
