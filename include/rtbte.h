@@ -59,6 +59,17 @@ enum {
 };
 
 enum { RTBTE_FP64 = 0, RTBTE_MIXED = 1 };
+/* Weight storage of RTBTE_MIXED (Options.mixed_weights).  Every weight is
+   stored relative to the FP32 scale of its block of 512 consecutive channels
+   (the block's largest weight maps to 2^15):
+     RTBTE_W_F16X     FP16 with an 11-bit significand tail kept in bits of the
+                      8-byte index word that 24-bit state positions leave free:
+                      22 significant bits, relative rounding <= 2^-22 (default);
+     RTBTE_W_F16      FP16 only: relative rounding <= 2^-11;
+     RTBTE_W_BF16_EPH BF16 for the e-ph and ph-e weights (<= 2^-8), FP16 for
+                      the ph-ph weights (<= 2^-11).
+   The channel stream is 10 bytes per channel in all three. */
+enum { RTBTE_W_F16X = 0, RTBTE_W_F16 = 1, RTBTE_W_BF16_EPH = 2 };
 
 typedef struct rtbte_ctx rtbte_ctx;
 
@@ -106,7 +117,14 @@ typedef struct {
 
 /* Options; rtbte_default_options fills every field. */
 typedef struct {
-  int32_t precision;       /* RTBTE_FP64 (default) or RTBTE_MIXED                           */
+  int32_t precision;       /* RTBTE_FP64 (default) or RTBTE_MIXED: 16-bit weights relative
+                              to one FP32 scale per 512 channels (format: mixed_weights),
+                              populations gathered as FP32 pairs formed in FP64, per-lane
+                              compensated FP32 sums added in FP64; the state, the stages,
+                              the WRMS norm and the step control stay FP64.  RTBTE_MIXED
+                              holds at most 2^24 states per context (RTBTE_E_INVAL beyond) */
+  int32_t mixed_weights;   /* RTBTE_MIXED only: RTBTE_W_F16X (default), RTBTE_W_F16 or
+                              RTBTE_W_BF16_EPH                                             */
   int32_t device;          /* HIP device ordinal                                           */
   /* ERK error test (Eq. (wrms_weights)): w_i = 1/(rtol |y_i| + atol_i),
      atol_i = atol_el on electron components and atol_ph on phonon components */

@@ -68,7 +68,9 @@ def _lib():
         L.orc_free.argtypes = [ctypes.c_void_p]
         L.orc_counts.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_rhs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
-                              ctypes.c_void_p, ctypes.c_void_p]
+                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_max_weight.argtypes = [ctypes.c_void_p]
+        L.orc_max_weight.restype = ctypes.c_double
         L.orc_rhs_rows.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_brute_rhs.argtypes = ([ctypes.c_int] * 7 + [ctypes.c_void_p] * 5 +
@@ -127,14 +129,25 @@ class Oracle:
         _lib().orc_counts(self._h, _p(out))
         return tuple(int(x) for x in out)
 
-    def rhs(self, y, parts: int = PART_ALL, scales: bool = False):
+    def rhs(self, y, parts: int = PART_ALL, scales: bool = False, unweighted: bool = False):
+        """f(y) restricted to `parts`.  With scales=True also returns, per row,
+        S = sum |W F| and A = sum |W| (|gain| + |loss|); with unweighted=True
+        additionally M = sum (|gain| + |loss|) and Q = sum (W F)^2."""
         y = np.ascontiguousarray(y, dtype=np.float64)
         assert y.shape == (self.n_y,)
         out = np.empty(self.n_y)
         S = np.empty(self.n_y) if scales else None
         A = np.empty(self.n_y) if scales else None
-        _lib().orc_rhs(self._h, _p(y), _p(out), int(parts), _p(S), _p(A))
+        M = np.empty(self.n_y) if unweighted else None
+        Q = np.empty(self.n_y) if unweighted else None
+        _lib().orc_rhs(self._h, _p(y), _p(out), int(parts), _p(S), _p(A), _p(M), _p(Q))
+        if unweighted:
+            return out, S, A, M, Q
         return (out, S, A) if scales else out
+
+    def max_weight(self) -> float:
+        """Largest stored channel weight."""
+        return float(_lib().orc_max_weight(self._h))
 
     def rhs_rows(self, y, rows, parts: int = PART_ALL):
         y = np.ascontiguousarray(y, dtype=np.float64)

@@ -188,14 +188,17 @@ void orc_counts(const orc_lists *L, int64_t out[3]) {
 }
 
 /* Neumaier (improved Kahan-Babuska) compensated accumulation. */
-typedef struct { double s, c, mag, absw; } acc_t;
-static inline void acc_add(acc_t *a, double x, double mag) {
+typedef struct { double s, c, mag, absw, umag, sq; } acc_t;
+/* x = W * factor; m = |gain| + |loss| of the factor (unweighted). */
+static inline void acc_add(acc_t *a, double w, double x, double m) {
   double t = a->s + x;
   if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
   else a->c += (x - t) + a->s;
   a->s = t;
   a->absw += fabs(x);
-  a->mag += mag;
+  a->mag += fabs(w) * m;
+  a->umag += m;
+  a->sq += x * x;
 }
 
 /* Occupation factors, evaluated as printed (gain term minus loss term).
@@ -224,9 +227,9 @@ static inline double G_abs(double N, double Na, double Nb, double *m) {
 /* One destination row of y' (row < n_el: electron nk; else phonon nuq).
  * parts: 1 = I^{e-ph}, 2 = I^{ph-e}, 4 = I^{ph-ph}. */
 static double row_value(const orc_lists *L, const double *y, int64_t row, int parts, double *S,
-                        double *A) {
+                        double *A, double *M, double *Q) {
   const double *f = y, *N = y + L->n_el;
-  acc_t a = {0, 0, 0, 0};
+  acc_t a = {0, 0, 0, 0, 0, 0};
   double m;
   if (row < L->n_el) {
     if (parts & 1) {
@@ -234,8 +237,8 @@ static double row_value(const orc_lists *L, const double *y, int64_t row, int pa
       for (int64_t j = L->el_ptr[r]; j < L->el_ptr[r + 1]; ++j) {
         int64_t i = L->el_idx[j];
         double fr = f[r], fs = f[L->es[i]], Np = N[L->ep[i]];
-        if (L->w_em[i] != 0.0) { double F = F_em(fr, fs, Np, &m); acc_add(&a, L->w_em[i] * F, L->w_em[i] * m); }
-        if (L->w_abs[i] != 0.0) { double F = F_abs(fr, fs, Np, &m); acc_add(&a, L->w_abs[i] * F, L->w_abs[i] * m); }
+        if (L->w_em[i] != 0.0) { double F = F_em(fr, fs, Np, &m); acc_add(&a, L->w_em[i], L->w_em[i] * F, m); }
+        if (L->w_abs[i] != 0.0) { double F = F_abs(fr, fs, Np, &m); acc_add(&a, L->w_abs[i], L->w_abs[i] * F, m); }
       }
     }
   } else {
@@ -244,35 +247,51 @@ static double row_value(const orc_lists *L, const double *y, int64_t row, int pa
       for (int64_t j = L->phe_ptr[p]; j < L->phe_ptr[p + 1]; ++j) {
         int64_t i = L->phe_idx[j];
         double F = F_abs(f[L->er[i]], f[L->es[i]], N[p], &m);
-        acc_add(&a, L->w_phe[i] * F, L->w_phe[i] * m);
+        acc_add(&a, L->w_phe[i], L->w_phe[i] * F, m);
       }
     }
     if (parts & 4) {
       for (int64_t j = L->pp_ptr[p]; j < L->pp_ptr[p + 1]; ++j) {
         int64_t i = L->pp_idx[j];
         double Na = N[L->pa[i]], Nb = N[L->pb[i]];
-        if (L->v_em[i] != 0.0) { double G = G_em(N[p], Na, Nb, &m); acc_add(&a, L->v_em[i] * G, L->v_em[i] * m); }
-        if (L->v_abs[i] != 0.0) { double G = G_abs(N[p], Na, Nb, &m); acc_add(&a, L->v_abs[i] * G, L->v_abs[i] * m); }
+        if (L->v_em[i] != 0.0) { double G = G_em(N[p], Na, Nb, &m); acc_add(&a, L->v_em[i], L->v_em[i] * G, m); }
+        if (L->v_abs[i] != 0.0) { double G = G_abs(N[p], Na, Nb, &m); acc_add(&a, L->v_abs[i], L->v_abs[i] * G, m); }
       }
     }
   }
   if (S) *S = a.absw;
   if (A) *A = a.mag;
+  if (M) *M = a.umag;
+  if (Q) *Q = a.sq;
   return -(a.s + a.c);
 }
 
 /* Full right-hand side y' = [I^{e-ph}; I^{ph-e} + I^{ph-ph}] (Eq. (erk_rhs)),
- * restricted to the parts in `parts`.  S (optional) receives sum |W F| per row,
- * A (optional) sum |W| (|gain| + |loss|) per row. */
-void orc_rhs(const orc_lists *L, const double *y, double *ydot, int parts, double *S, double *A) {
+ * restricted to the parts in `parts`.  Optional per-row outputs: S = sum |W F|,
+ * A = sum |W| (|gain| + |loss|), M = sum (|gain| + |loss|), Q = sum (W F)^2. */
+void orc_rhs(const orc_lists *L, const double *y, double *ydot, int parts, double *S, double *A,
+             double *M, double *Q) {
   const int64_t ny = (int64_t)L->n_el + L->n_ph;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t row = 0; row < ny; ++row) {
-    double s, a;
-    ydot[row] = row_value(L, y, row, parts, &s, &a);
+    double s, a, m, q;
+    ydot[row] = row_value(L, y, row, parts, &s, &a, &m, &q);
     if (S) S[row] = s;
     if (A) A[row] = a;
+    if (M) M[row] = m;
+    if (Q) Q[row] = q;
   }
+}
+
+/* Largest stored channel weight. */
+double orc_max_weight(const orc_lists *L) {
+  double m = 0.0;
+  for (int64_t i = 0; i < L->n_eph; ++i) {
+    m = fmax(m, fmax(fabs(L->w_em[i]), fabs(L->w_abs[i])));
+    m = fmax(m, fabs(L->w_phe[i]));
+  }
+  for (int64_t i = 0; i < L->n_pp; ++i) m = fmax(m, fmax(fabs(L->v_em[i]), fabs(L->v_abs[i])));
+  return m;
 }
 
 /* Selected rows only (sampled parity at full size). */
@@ -281,7 +300,7 @@ void orc_rhs_rows(const orc_lists *L, const double *y, const int64_t *rows, int6
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t j = 0; j < nrows; ++j) {
     double s, a;
-    out[j] = row_value(L, y, rows[j], parts, &s, &a);
+    out[j] = row_value(L, y, rows[j], parts, &s, &a, NULL, NULL);
     if (S) S[j] = s;
     if (A) A[j] = a;
   }

@@ -111,6 +111,12 @@ struct rtbte_ctx {
   int64_t* item_ptr = nullptr;    // [n_groups + 1]
   int32_t* row_group = nullptr;   // [ny]
   double* partial_items = nullptr;
+  // mixed precision
+  bool mixed = false;
+  int2* mix_idx = nullptr;
+  uint16_t* mix_wq = nullptr;
+  float* mix_scale = nullptr;
+  float2* popf = nullptr;
   int32_t* row_inst = nullptr;
   InstInfo* info_d = nullptr;
   InstState* st = nullptr;       // main integrator
@@ -191,6 +197,7 @@ void rtbte_default_options(rtbte_options* o) {
   o->group_rows_el = 0;
   o->group_rows_ph = 0;
   o->item_channels = 0;
+  o->mixed_weights = RTBTE_W_F16X;
   o->tune = 0;
   o->tune_cache = nullptr;
 }
@@ -317,7 +324,7 @@ hipError_t upload(T** d, const T* h, size_t n) {
 void free_ctx(rtbte_ctx* c) {
   if (!c) return;
   void* ps[] = {c->ch, c->groups, c->items, c->order, c->item_ptr, c->row_group, c->partial_items,
-                c->row_inst, c->info_d, c->st, c->st_fast,
+                c->mix_idx, c->mix_wq, c->mix_scale, c->popf, c->row_inst, c->info_d, c->st, c->st_fast,
                 c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
                 c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
                 c->partial, c->tvec, c->summary_d};
@@ -343,8 +350,10 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
   rtbte_options o;
   if (opts) o = *opts;
   else rtbte_default_options(&o);
-  if (o.precision != RTBTE_FP64)
-    return fail(nullptr, RTBTE_E_UNSUPPORTED, "precision %d not available in this build", o.precision);
+  if (o.precision != RTBTE_FP64 && o.precision != RTBTE_MIXED)
+    return fail(nullptr, RTBTE_E_INVAL, "precision must be RTBTE_FP64 or RTBTE_MIXED");
+  if (o.mixed_weights < RTBTE_W_F16X || o.mixed_weights > RTBTE_W_BF16_EPH)
+    return fail(nullptr, RTBTE_E_INVAL, "mixed_weights must be RTBTE_W_F16X, RTBTE_W_F16 or RTBTE_W_BF16_EPH");
   if (o.group_rows_el == 0) o.group_rows_el = 8;
   if (o.group_rows_ph == 0) o.group_rows_ph = 16;
   if (!valid_group_rows(o.group_rows_el) || !valid_group_rows(o.group_rows_ph))
@@ -380,6 +389,11 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
   if (c->ny > (int64_t)kPosMask) {
     free_ctx(c);
     return fail(nullptr, RTBTE_E_INVAL, "state vector too long (%lld > %d)", (long long)off, kPosMask);
+  }
+  if (o.precision == RTBTE_MIXED && c->ny > (int64_t)kMixPosMask + 1) {
+    free_ctx(c);
+    return fail(nullptr, RTBTE_E_INVAL, "RTBTE_MIXED holds at most %d states (%lld given)", kMixPosMask + 1,
+                (long long)off);
   }
   c->counts.assign(3 * (size_t)n_inst, 0);
 
@@ -594,6 +608,26 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
   if (e == hipSuccess) e = upload(&c->item_ptr, iptr.data(), iptr.size());
   if (e == hipSuccess) e = upload(&c->row_group, rgroup.data(), rgroup.size());
   if (e == hipSuccess) c->partial_items = dalloc<double>((size_t)std::max<int64_t>(c->n_items, 1) * kMaxGroupRows, &e);
+  if (e == hipSuccess && o.precision == RTBTE_MIXED) {
+    // 16-bit weights with per-block FP32 scales; the FP64 channels are freed
+    const int64_t nblk = (c->n_ch + kMixBlock - 1) / kMixBlock;
+    c->mix_scale = dalloc<float>((size_t)std::max<int64_t>(nblk, 1), &e);
+    if (e == hipSuccess) c->mix_idx = dalloc<int2>((size_t)c->n_ch + 4, &e);
+    if (e == hipSuccess) c->mix_wq = dalloc<uint16_t>((size_t)c->n_ch + 8, &e);
+    if (e == hipSuccess) c->popf = dalloc<float2>((size_t)c->ny, &e);
+    if (e == hipSuccess) e = hipMemset(c->mix_idx, 0, ((size_t)c->n_ch + 4) * sizeof(int2));
+    if (e == hipSuccess) e = hipMemset(c->mix_wq, 0, ((size_t)c->n_ch + 8) * sizeof(uint16_t));
+    if (e == hipSuccess) e = launch_mix_scales(c->ch, c->n_ch, c->mix_scale, 0);
+    if (e == hipSuccess)
+      e = launch_mix_convert(c->ch, c->n_ch, c->groups, c->n_groups, c->mix_scale, o.mixed_weights,
+                             c->mix_idx, c->mix_wq, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) {
+      e = hipFree(c->ch);
+      c->ch = nullptr;
+    }
+    c->mixed = true;
+  }
   if (e == hipSuccess && n_inst > 1) {
     std::vector<int32_t> ri((size_t)c->ny);
     for (int i = 0; i < n_inst; ++i)
@@ -706,8 +740,11 @@ double launch_bytes(const rtbte_ctx* c, int parts) {
   for (int i = 0; i < c->n_inst; ++i)
     for (int k = 0; k < 3; ++k)
       if (parts & (1 << k)) ch += c->counts[3 * i + k];
-  return 16.0 * (double)ch + 8.0 * (double)c->ny + (double)sizeof(Group) * (double)c->n_groups +
-         (double)(sizeof(Item) + 4 + 8 * kMaxGroupRows) * (double)c->n_items;
+  const double tables = (double)sizeof(Group) * (double)c->n_groups +
+                        (double)(sizeof(Item) + 4 + 8 * kMaxGroupRows) * (double)c->n_items;
+  if (c->mixed)  // 8 B indices + 2 B weight per channel, a 4 B scale per block; population prep 8+8 B per state
+    return 10.0 * (double)ch + 4.0 * (double)ch / kMixBlock + 24.0 * (double)c->ny + tables;
+  return 16.0 * (double)ch + 8.0 * (double)c->ny + tables;
 }
 
 hipError_t harvest(rtbte_ctx* c) {
@@ -739,9 +776,29 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
   a.z = z;
   a.partial = c->partial_items;
   a.st = st;
+  MixArgs m{};
+  if (c->mixed) {
+    m.idx = c->mix_idx;
+    m.wq = c->mix_wq;
+    m.scale = c->mix_scale;
+    m.pop = c->popf;
+    m.groups = c->groups;
+    m.items = c->items;
+    m.order = c->order;
+    m.n_items = c->n_items;
+    m.parts = parts;
+    m.wfmt = c->opt.mixed_weights;
+    m.partial = c->partial_items;
+    m.st = st;
+  }
+  auto launch = [&]() {
+    if (!c->mixed) return launch_items(a, c->slots, s);
+    hipError_t e2 = launch_popf(c->popf, z, c->row_group, c->groups, c->ny, s);
+    return e2 == hipSuccess ? launch_items_mixed(m, c->slots, s) : e2;
+  };
   hipError_t e;
   if (!c->prof) {
-    e = launch_items(a, c->slots, s);
+    e = launch();
   } else {
     std::pair<hipEvent_t, hipEvent_t> ev;
     if (!c->pool.empty()) {
@@ -753,7 +810,7 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
       if (e != hipSuccess) return e;
     }
     e = hipEventRecord(ev.first, s);
-    if (e == hipSuccess) e = launch_items(a, c->slots, s);
+    if (e == hipSuccess) e = launch();
     if (e == hipSuccess) e = hipEventRecord(ev.second, s);
     c->pending.push_back({ev.first, ev.second, launch_bytes(c, parts)});
   }

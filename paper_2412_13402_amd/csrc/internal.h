@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "rtbte.h"
+
 namespace rtbte {
 
 constexpr double kHbarEvFs = 0.6582119569;          // eV fs
@@ -109,6 +111,38 @@ struct FinishArgs {
 // Launchers (kernels.hip)
 hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s);
 hipError_t launch_finish_rows(const FinishArgs& f, bool stage, hipStream_t s);
+
+// Mixed precision: channel indices (8 B), weights as 16-bit floats relative
+// to one FP32 scale per block of kMixBlock consecutive channels, populations
+// as FP32 pairs.  Index word: x = pos0 (bits 0..23) | tag (24..27) | tail
+// bits 0..3 (28..31); y = pos1 (0..23) | tail bits 4..10 (24..30) | em (31).
+// The 11-bit tail extends an FP16 weight's significand (weight format
+// RTBTE_W_F16X); it is zero in the other formats.
+constexpr int kMixBlock = 512;
+constexpr int32_t kMixPosMask = 0x00ffffff;
+constexpr int32_t kMixTagShift = 24;
+struct MixArgs {
+  const int2* idx;          // [n_ch] packed as above
+  const uint16_t* wq;       // [n_ch] weight / scale of its block, 16-bit head
+  const float* scale;       // [ceil(n_ch / kMixBlock)]
+  const float2* pop;        // [ny] electrons (f, 1-f), phonons (N, N+1)
+  const Group* groups;
+  const Item* items;
+  const int32_t* order;
+  int64_t n_items;
+  int32_t parts;
+  int32_t wfmt;             // RTBTE_W_* weight format
+  double* partial;
+  const InstState* st;
+};
+hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s);
+// pop[i] from z[i] (each factor formed in FP64, then rounded to FP32)
+hipError_t launch_popf(float2* pop, const double* z, const int32_t* row_group, const Group* groups,
+                       int64_t n, hipStream_t s);
+// create time: per-block scales, then the 16-bit weights and packed indices
+hipError_t launch_mix_scales(const Channel* ch, int64_t n_ch, float* scale, hipStream_t s);
+hipError_t launch_mix_convert(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                              const float* scale, int wfmt, int2* idx, uint16_t* wq, hipStream_t s);
 hipError_t launch_wrms(const double* v, const double* y, const InstInfo* info, const InstState* st,
                        double* partial, int n_inst, int nchunk, Ctl c, hipStream_t s);
 hipError_t launch_control(InstState* st, const double* partial, const InstInfo* info, int n_inst,

@@ -236,6 +236,245 @@ hipError_t launch_finish_rows(const FinishArgs& f, bool stage, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ mixed precision
+// Weights are stored relative to the FP32 scale of their 512-channel block as
+// FP16 heads, extended by an 11-bit significand tail held in the index word
+// (or FP16 alone, or BF16 for e-ph and ph-e, on request); the factors are
+// evaluated in FP32 from FP32 populations
+// (each pair formed in FP64 and rounded once); every lane keeps a Neumaier
+// compensated FP32 sum per row of the group, and the lanes' sums and
+// compensations are added in FP64.
+__device__ __forceinline__ float bf16_to_f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ float f16_to_f(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+}
+
+struct MixAcc {
+  float2* slot;  // this lane's (sum, compensation) of row j at slot[64 * j]
+  __device__ __forceinline__ void add(int tag, float x) {
+    float2 a = slot[64 * tag];
+    const float t = a.x + x;
+    if (fabsf(a.x) >= fabsf(x)) a.y += (a.x - t) + x;
+    else a.y += (x - t) + a.x;
+    a.x = t;
+    slot[64 * tag] = a;
+  }
+};
+
+template <int KIND>
+__device__ __forceinline__ float term_f(bool em, float w, float2 g0, float2 g1, float2 xr) {
+  if (KIND == K_EPH) {         // xr = (f_r, 1-f_r), g0 = (f_s, 1-f_s), g1 = (N_p, N_p+1)
+    const float gain = xr.x * g0.y * (em ? g1.y : g1.x);
+    const float loss = xr.y * g0.x * (em ? g1.x : g1.y);
+    return w * (gain - loss);
+  } else if (KIND == K_PHE) {  // xr = (N_p, N_p+1), g0 = (f_r, 1-f_r), g1 = (f_s, 1-f_s)
+    const float gain = g0.x * g1.y * xr.x;
+    const float loss = g0.y * g1.x * xr.y;
+    return w * (gain - loss);
+  } else {                     // xr = (N, N+1), g0 = (N_a, N_a+1), g1 = (N_b, N_b+1)
+    const float gain = xr.x * g0.y * (em ? g1.y : g1.x);
+    const float loss = xr.y * g0.x * (em ? g1.x : g1.y);
+    return w * (gain - loss);
+  }
+}
+
+// Channels [s, e) of one kind, four per lane per quad (quads are aligned to
+// 4 channels, so a quad never straddles a 512-channel scale block).
+template <int KIND>
+__device__ __forceinline__ void seg_sum_mixed(MixAcc& acc, const MixArgs& a, int64_t s, int64_t e, int lane,
+                                              const float2* rowv) {
+  if (s >= e) return;
+  typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+  const v4i* idx4 = reinterpret_cast<const v4i*>(a.idx);
+  const v2u* w4 = reinterpret_cast<const v2u*>(a.wq);
+  for (int64_t q = s / 4 + lane; q * 4 < e; q += 64) {
+    const v4i p0 = __builtin_nontemporal_load(idx4 + 2 * q);
+    const v4i p1 = __builtin_nontemporal_load(idx4 + 2 * q + 1);
+    const v2u wp = __builtin_nontemporal_load(w4 + q);
+    const float sc = a.scale[q / (kMixBlock / 4)];
+    const uint32_t i0[4] = {(uint32_t)p0.x, (uint32_t)p0.z, (uint32_t)p1.x, (uint32_t)p1.z};
+    const uint32_t i1[4] = {(uint32_t)p0.y, (uint32_t)p0.w, (uint32_t)p1.y, (uint32_t)p1.w};
+    const uint32_t wh[4] = {wp.x & 0xffffu, wp.x >> 16, wp.y & 0xffffu, wp.y >> 16};
+    float2 g0[4], g1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      g0[j] = a.pop[i0[j] & kMixPosMask];
+      g1[j] = a.pop[i1[j] & kMixPosMask];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = q * 4 + j;
+      if (c < s || c >= e) continue;
+      const int tag = (i0[j] >> kMixTagShift) & 15;
+      float w;
+      if (KIND != K_PP && a.wfmt == RTBTE_W_BF16_EPH) {
+        w = bf16_to_f(wh[j]);
+      } else {
+        // the tail fills FP32 significand bits 2..12, below the head's 10
+        const uint32_t tail = (i0[j] >> 28) | ((i1[j] >> 20) & 0x7f0u);
+        w = __uint_as_float(__float_as_uint(f16_to_f(wh[j])) | (tail << 2));
+      }
+      acc.add(tag, term_f<KIND>((int32_t)i1[j] < 0, w * sc, g0[j], g1[j], rowv[tag]));
+    }
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(64) void k_items_mixed(MixArgs a) {
+  __shared__ float2 acc_lds[G][64];
+  __shared__ float2 rowv[kMaxGroupRows];
+  const int lane = threadIdx.x & 63;
+  const int64_t ii = blockIdx.x;
+  bool active = ii < a.n_items;
+  int64_t it = 0;
+  Item item{};
+  Group g{};
+  if (active) {
+    it = a.order[ii];
+    item = a.items[it];
+    g = a.groups[item.group];
+    if (a.st && a.st[g.inst].done) active = false;
+  }
+#pragma unroll
+  for (int j = 0; j < G; ++j) acc_lds[j][lane] = make_float2(0.f, 0.f);
+  if (active && lane < g.nrows) rowv[lane] = a.pop[g.row0 + lane];
+  __syncthreads();
+  MixAcc acc{&acc_lds[0][lane]};
+  if (active) {
+    if (!g.phonon) {
+      if (a.parts & 1) seg_sum_mixed<K_EPH>(acc, a, item.lo, item.hi, lane, rowv);
+    } else {
+      const int64_t m = g.split;
+      if (a.parts & 2) seg_sum_mixed<K_PHE>(acc, a, item.lo, item.hi < m ? item.hi : m, lane, rowv);
+      if (a.parts & 4) seg_sum_mixed<K_PP>(acc, a, item.lo > m ? item.lo : m, item.hi, lane, rowv);
+    }
+  }
+  __syncthreads();
+  if (active && lane < g.nrows) {
+    double sum = 0.0, comp = 0.0;
+    for (int l = 0; l < 64; ++l) {
+      sum += (double)acc_lds[lane][l].x;
+      comp += (double)acc_lds[lane][l].y;
+    }
+    a.partial[it * kMaxGroupRows + lane] = sum + comp;
+  }
+}
+
+hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s) {
+  const int64_t nb = a.n_items;
+  if (nb == 0) return hipSuccess;
+  switch (slots) {
+    case 1: hipLaunchKernelGGL(k_items_mixed<1>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_items_mixed<8>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(k_items_mixed<16>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ void k_popf(float2* pop, const double* __restrict__ z, const int32_t* row_group,
+                       const Group* groups, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = z[i];
+  if (groups[row_group[i]].phonon) pop[i] = make_float2((float)v, (float)(v + 1.0));
+  else pop[i] = make_float2((float)v, (float)(1.0 - v));
+}
+
+hipError_t launch_popf(float2* pop, const double* z, const int32_t* row_group, const Group* groups,
+                       int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_popf, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pop, z, row_group, groups, n);
+  return hipGetLastError();
+}
+
+// Scale of each 512-channel block: its largest weight times 2^-15 (2^-15 if
+// all are 0), so stored values lie in [0, 2^15].  The 2^15 headroom keeps FP16
+// values of small weights out of FP16's subnormal range down to 2^-29 of the
+// block's largest weight; a power of two changes no rounding.
+__global__ __launch_bounds__(256) void k_mix_scales(const Channel* ch, int64_t n_ch, float* scale) {
+  __shared__ double red[4];
+  const int64_t b = blockIdx.x;
+  double m = 0.0;
+  for (int64_t c = b * kMixBlock + threadIdx.x; c < (b + 1) * kMixBlock && c < n_ch; c += 256)
+    m = fmax(m, fabs(ch[c].w));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    // round the scale up so every scaled weight is <= 2^15
+    float sf = (float)m;
+    if ((double)sf < m) sf = nextafterf(sf, INFINITY);
+    scale[b] = (m > 0.0 ? sf : 1.0f) * 0x1p-15f;
+  }
+}
+
+hipError_t launch_mix_scales(const Channel* ch, int64_t n_ch, float* scale, hipStream_t s) {
+  const int64_t nb = (n_ch + kMixBlock - 1) / kMixBlock;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mix_scales, dim3((unsigned)nb), dim3(256), 0, s, ch, n_ch, scale);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ uint16_t to_bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// r in [0, 2^15] (finite) to an FP16 head and an 11-bit tail: r rounded once,
+// to nearest even, to 22 significant bits.  Values below FP16's normal range
+// (2^-14) are plain FP16 (their tail is zero).
+__device__ __forceinline__ void to_f16x(double r, uint16_t* head, uint32_t* tail) {
+  const double m = fabs(r);
+  if (!(m >= 0x1p-14)) {
+    *head = __builtin_bit_cast(uint16_t, (_Float16)(float)r);
+    *tail = 0;
+    return;
+  }
+  int e = ilogb(m);                           // 2^e <= m < 2^(e+1)
+  double q = rint(ldexp(m, 21 - e));          // in [2^21, 2^22]
+  if (q >= 0x1p22) { q = 0x1p21; ++e; }
+  const uint32_t sig = (uint32_t)q;           // 22 bits, leading one at bit 21
+  const uint32_t sign = r < 0 ? 0x8000u : 0u;
+  *head = (uint16_t)(sign | ((uint32_t)(e + 15) << 10) | ((sig >> 11) & 0x3ffu));
+  *tail = sig & 0x7ffu;
+}
+
+__global__ void k_mix_convert(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                              const float* scale, int wfmt, int2* idx, uint16_t* wq) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_ch) return;
+  // the group holding channel c: last group with start <= c
+  int64_t lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (groups[mid].start <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const Group g = groups[lo];
+  const bool pp = g.phonon && c >= g.split;
+  const Channel x = ch[c];
+  const double r = x.w / (double)scale[c / kMixBlock];
+  uint32_t tail = 0;
+  if (!pp && wfmt == RTBTE_W_BF16_EPH) wq[c] = to_bf16_rne((float)r);
+  else if (wfmt == RTBTE_W_F16) wq[c] = __builtin_bit_cast(uint16_t, (_Float16)(float)r);
+  else to_f16x(r, &wq[c], &tail);
+  const uint32_t pos0 = (uint32_t)x.i0 & (uint32_t)kPosMask, pos1 = x.i1 & (uint32_t)kPosMask;
+  const uint32_t tag = ((uint32_t)x.i0 >> kTagShift) & 15u;
+  const uint32_t wx = pos0 | (tag << kMixTagShift) | ((tail & 15u) << 28);
+  const uint32_t wy = pos1 | ((tail >> 4) << 24) | (x.i1 & kEmBit);
+  idx[c] = make_int2((int)wx, (int)wy);
+}
+
+hipError_t launch_mix_convert(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                              const float* scale, int wfmt, int2* idx, uint16_t* wq, hipStream_t s) {
+  if (n_ch == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mix_convert, dim3((unsigned)((n_ch + 255) / 256)), dim3(256), 0, s, ch, n_ch, groups,
+                     n_groups, scale, wfmt, idx, wq);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ WRMS norm
 // Partial sums of (v_i w_i)^2, w_i = 1/(rtol |y_i| + atol_i) (Eq. (wrms_norm),
 // Eq. (wrms_weights)); grid (nchunk, n_inst), fixed summation order.

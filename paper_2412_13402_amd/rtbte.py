@@ -17,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 OK, E_INVAL, E_NOMEM, E_HIP, E_STEP, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 PART_EPH, PART_PHE, PART_PHPH, PART_ALL = 1, 2, 4, 7
 FP64, MIXED = 0, 1
+# weight formats of MIXED (rtbte.h): FP16 + 11-bit tail, FP16, BF16 for e-ph / FP16 for ph-ph
+W_F16X, W_F16, W_BF16_EPH = 0, 1, 2
 
 _STATUS = {E_INVAL: "invalid argument", E_NOMEM: "out of memory", E_HIP: "HIP error",
            E_STEP: "step failure", E_NONFINITE: "non-finite state", E_UNSUPPORTED: "unsupported"}
@@ -46,7 +48,7 @@ class Problem(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [
-        ("precision", ctypes.c_int32), ("device", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("mixed_weights", ctypes.c_int32), ("device", ctypes.c_int32),
         ("rtol", ctypes.c_double), ("atol_el", ctypes.c_double), ("atol_ph", ctypes.c_double),
         ("fast_mode", ctypes.c_int32), ("h_fast", ctypes.c_double),
         ("fast_rtol", ctypes.c_double), ("fast_atol_el", ctypes.c_double),

@@ -1,0 +1,99 @@
+"""Full-size parity on the graphene-like workload (120x120 k = q grid, 2 bands,
+6 branches: about 1.5e8 electron-side e-ph, 0.8e8 phonon-side e-ph and 5.0e8
+ph-ph stored channels), in the launch configuration the benchmark times
+(library-chosen rows per group and channels per item), against the FP64
+oracle on every row.
+
+FP64: |err_i| <= 1e-12 A_i on every row, A_i = sum |W| (|gain| + |loss|).
+Mixed (default weight format): the a priori bound of the mixed tests and a
+normwise relative error <= 1e-4; populations after 1 ps of RK4 (h = 4 fs, the
+same steps in both precisions) within 1e-6 of the FP64 path (parity unpinned:
+measured against the FP64 GPU path, itself checked against the oracle here).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rel_norm, say, to_dev, torch_cuda
+from tests.test_gpu_rhs import random_state
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U_F16X = 2.0 ** -21
+U_SUB = 2.0 ** -39
+
+
+@pytest.fixture(scope="module")
+def full():
+    say("[fullsize] generating graphene2d 120x120 and its oracle lists")
+    wl = synth.build("graphene2d")
+    o = oracle.Oracle(wl.problem_arrays())
+    say(f"[fullsize] counts {o.counts()}")
+    return wl, o
+
+
+def states(wl):
+    return (("y0", wl.y0), ("random", random_state(wl, 11)))
+
+
+def test_fp64_rhs_full_size(full):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl, o = full
+    ctx = P.Context(wl.problem_arrays())
+    assert ctx.counts() == o.counts()
+    for nm, y in states(wl):
+        say(f"[fullsize] fp64 rhs at {nm}")
+        out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.rhs(to_dev(y), out, P.PART_ALL)
+        torch.cuda.synchronize()
+        g = out.cpu().numpy()
+        ref, S, A = o.rhs(y, scales=True)
+        worst = np.max(np.abs(g - ref) / np.maximum(A, 1e-300))
+        say(f"    worst row error / magnitude {worst:.2e}, normwise {rel_norm(g, ref):.2e}")
+        assert np.all(np.abs(g - ref) <= 1e-12 * A + 1e-300), f"{nm}: {worst:.3e}"
+        assert rel_norm(g, ref) <= 1e-12
+
+
+def test_mixed_rhs_full_size(full):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl, o = full
+    ctx = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED)
+    wmax = o.max_weight()
+    for nm, y in states(wl):
+        for parts in (P.PART_ALL, P.PART_EPH, P.PART_PHE, P.PART_PHPH):
+            out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.rhs(to_dev(y), out, parts)
+            torch.cuda.synchronize()
+            g = out.cpu().numpy()
+            ref, S, A, M, Q = o.rhs(y, parts=parts, scales=True, unweighted=True)
+            bound = (U_F16X + 16 * U32) * A + U_SUB * wmax * M
+            assert np.all(np.isfinite(g))
+            assert np.all(np.abs(g - ref) <= bound + 1e-300), \
+                f"{nm} parts {parts}: worst {np.max(np.abs(g - ref) / np.maximum(A, 1e-300)):.3e}"
+            err = rel_norm(g, ref)
+            say(f"[fullsize] mixed {nm} parts {parts}: normwise {err:.2e}")
+            assert err <= 1e-4
+
+
+def test_mixed_populations_after_1ps_full_size(full):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl, _ = full
+    res = {}
+    for prec in (P.rtbte.FP64, P.rtbte.MIXED):
+        say(f"[fullsize] 1 ps of RK4 at 4 fs, precision {prec}")
+        ctx = P.Context(wl.problem_arrays(), precision=prec)
+        y = to_dev(wl.y0)
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.step_rk4(y, t, 4.0, 250)
+        torch.cuda.synchronize()
+        res[prec] = y.cpu().numpy()
+        del ctx
+    d = np.abs(res[P.rtbte.MIXED] - res[P.rtbte.FP64])
+    say(f"    max population difference {d.max():.2e}")
+    assert np.all(np.isfinite(res[P.rtbte.MIXED]))
+    assert d.max() <= 1e-6

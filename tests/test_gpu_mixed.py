@@ -1,0 +1,170 @@
+"""Mixed-precision right-hand side against the FP64 oracle: 16-bit weight
+heads with per-512-channel FP32 scales, FP32 populations formed in FP64,
+compensated FP32 lane sums added in FP64.
+
+Bounds: each row obeys the a priori bound
+    |err_i| <= (u_w + 16 u_32) A_i + 2^-39 w_max M_i,
+with u_32 = 2^-24, A_i = sum |W| (|gain| + |loss|) and M_i = sum (|gain| +
+|loss|) over the row's channels, w_max the largest weight, and u_w the weight
+format's relative rounding: 2^-21 for the default FP16 head + 11-bit tail
+(22 significant bits, rounded once: 2^-22, plus the FP32 product with the
+scale), 2^-11 for FP16 alone, 2^-8 for BF16 (e-ph and ph-e weights in the
+BF16 format).  The last term covers FP16 underflow: a block's largest weight
+is stored as 2^15, so a weight below 2^-29 of it is a subnormal FP16 value
+whose rounding error is at most 2^-25 * 2^-15 of the block scale.
+
+Normwise: the default format must give <= 1e-4 relative on every workload.
+FP16 alone and BF16 are reported only: their rounding (2^-11, 2^-8 per weight)
+does not average below 1e-4 on rows whose gain and loss nearly cancel (on the
+graphene-like workload FP16 alone gives about 1.1e-4 on the full right-hand
+side and 2.4e-4 on the ph-ph part).
+
+Populations after 1 ps of fixed RK4 steps (the same steps for both
+precisions) must agree with the FP64 path to 1e-6 absolute; that bound has no
+closed form behind it (parity unpinned), it is measured against the FP64 GPU
+path, itself parity-tested against the oracle.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rel_norm, say, to_dev, torch_cuda
+from tests.test_gpu_rhs import medium2d, random_state
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U_BF16 = 2.0 ** -8
+U_F16 = 2.0 ** -11
+U_F16X = 2.0 ** -21
+U_SUB = 2.0 ** -39
+
+
+@functools.lru_cache(maxsize=None)
+def wl_of(name):
+    return medium2d() if name == "medium2d" else synth.build(name)
+
+
+@functools.lru_cache(maxsize=None)
+def orc(name):
+    return oracle.Oracle(wl_of(name).problem_arrays())
+
+
+def check_bounds(o, y, g, parts, uw, label):
+    """A priori componentwise bound; returns the normwise error (or None when
+    the reference is cancellation noise)."""
+    ref, S, A, M, Q = o.rhs(y, parts=parts, scales=True, unweighted=True)
+    assert np.all(np.isfinite(g)), label
+    bound = (uw + 16 * U32) * A + U_SUB * o.max_weight() * M
+    assert np.all(np.abs(g - ref) <= bound + 1e-300), \
+        f"{label}: worst {np.max(np.abs(g - ref) / np.maximum(A, 1e-300)):.3e}"
+    if np.linalg.norm(ref) > 1e-3 * np.linalg.norm(A):
+        return rel_norm(g, ref)
+    return None
+
+
+@pytest.mark.parametrize("name", ["toy2d", "tiny2d", "tiny3d", "medium2d"])
+def test_mixed_rhs_within_bounds(name):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of(name)
+    o = orc(name)
+    say(f"[mixed] rhs {name}")
+    ctx = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED)
+    assert ctx.counts() == o.counts()
+    for seed, y in ((0, wl.y0), (1, random_state(wl, 1))):
+        for parts in (7, 3, 4, 1, 2):
+            out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.rhs(to_dev(y), out, parts)
+            torch.cuda.synchronize()
+            err = check_bounds(o, y, out.cpu().numpy(), parts, U_F16X, f"{name} seed {seed} parts {parts}")
+            if err is not None:
+                say(f"    seed {seed} parts {parts}: normwise {err:.2e}")
+                assert err <= 1e-4, f"{name} seed {seed} parts {parts}: {err:.3e}"
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16_eph"])
+@pytest.mark.parametrize("name", ["toy2d", "medium2d"])
+def test_16bit_weight_formats_within_bound(name, fmt):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of(name)
+    o = orc(name)
+    code, uw = {"f16": (P.rtbte.W_F16, U_F16), "bf16_eph": (P.rtbte.W_BF16_EPH, U_BF16)}[fmt]
+    say(f"[mixed] {fmt} weights {name}")
+    ctx = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED, mixed_weights=code)
+    for seed, y in ((0, wl.y0), (2, random_state(wl, 2))):
+        for parts in (7, 1, 2, 4):
+            out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+            ctx.rhs(to_dev(y), out, parts)
+            torch.cuda.synchronize()
+            err = check_bounds(o, y, out.cpu().numpy(), parts, uw, f"{name} {fmt} seed {seed} parts {parts}")
+            if err is not None:
+                say(f"    seed {seed} parts {parts}: normwise {err:.2e} (reported)")
+
+
+def test_mixed_rejects_bad_weight_format():
+    torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of("toy2d")
+    with pytest.raises(P.RtbteError):
+        P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED, mixed_weights=7)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 0), (8, 16, 0), (4, 12, 333), (16, 2, 64)])
+def test_mixed_launch_shapes(shape):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of("medium2d")
+    o = orc("medium2d")
+    ge, gp, ic = shape
+    say(f"[mixed] shape {shape}")
+    ctx = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED, group_rows_el=ge, group_rows_ph=gp,
+                    item_channels=ic)
+    y = random_state(wl, 3)
+    out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+    ctx.rhs(to_dev(y), out, 7)
+    torch.cuda.synchronize()
+    err = check_bounds(o, y, out.cpu().numpy(), 7, U_F16X, f"shape {shape}")
+    assert err is not None and err <= 1e-4
+
+
+def test_mixed_populations_after_1ps():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of("medium2d")
+    say("[mixed] 1 ps of RK4, mixed vs FP64")
+    res = {}
+    for prec in (P.rtbte.FP64, P.rtbte.MIXED):
+        ctx = P.Context(wl.problem_arrays(), precision=prec)
+        y = to_dev(wl.y0)
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.step_rk4(y, t, 1.0, 1000)
+        torch.cuda.synchronize()
+        res[prec] = y.cpu().numpy()
+        assert abs(t.item() - 1000.0) < 1e-9
+    d = np.abs(res[P.rtbte.MIXED] - res[P.rtbte.FP64])
+    assert np.all(np.isfinite(res[P.rtbte.MIXED]))
+    assert d.max() <= 1e-6, f"max population difference {d.max():.3e}"
+
+
+def test_mixed_adaptive_run_tracks_fp64():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of("medium2d")
+    say("[mixed] adaptive ERK 200 fs, mixed vs FP64")
+    res = {}
+    for prec in (P.rtbte.FP64, P.rtbte.MIXED):
+        ctx = P.Context(wl.problem_arrays(), precision=prec, rtol=1e-6, atol_el=1e-9, atol_ph=1e-12)
+        y = to_dev(wl.y0)
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        h = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.step_adaptive(y, t, h, 200.0)
+        torch.cuda.synchronize()
+        res[prec] = y.cpu().numpy()
+    # both runs are within tolerance of the exact solution; their distance is
+    # tolerance-sized
+    assert np.max(np.abs(res[P.rtbte.MIXED] - res[P.rtbte.FP64])) <= 1e-4
