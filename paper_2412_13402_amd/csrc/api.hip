@@ -116,7 +116,7 @@ struct rtbte_ctx {
   int2* mix_idx = nullptr;
   uint16_t* mix_wq = nullptr;
   float* mix_scale = nullptr;
-  float2* popf = nullptr;
+  float* popf = nullptr;
   int32_t* row_inst = nullptr;
   InstInfo* info_d = nullptr;
   InstState* st = nullptr;       // main integrator
@@ -614,7 +614,7 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
     c->mix_scale = dalloc<float>((size_t)std::max<int64_t>(nblk, 1), &e);
     if (e == hipSuccess) c->mix_idx = dalloc<int2>((size_t)c->n_ch + 4, &e);
     if (e == hipSuccess) c->mix_wq = dalloc<uint16_t>((size_t)c->n_ch + 8, &e);
-    if (e == hipSuccess) c->popf = dalloc<float2>((size_t)c->ny, &e);
+    if (e == hipSuccess) c->popf = dalloc<float>((size_t)c->ny, &e);
     if (e == hipSuccess) e = hipMemset(c->mix_idx, 0, ((size_t)c->n_ch + 4) * sizeof(int2));
     if (e == hipSuccess) e = hipMemset(c->mix_wq, 0, ((size_t)c->n_ch + 8) * sizeof(uint16_t));
     if (e == hipSuccess) e = launch_mix_scales(c->ch, c->n_ch, c->mix_scale, 0);
@@ -733,8 +733,9 @@ extern "C" int rtbte_get_tuning(const rtbte_ctx* c, int32_t* group_rows_el, int3
 namespace {
 
 // Algorithmic bytes of one collision-kernel launch: every stored channel of
-// the selected parts once (16 B), the populations once (8 B per state), the
-// group and item tables, and the item row sums written.
+// the selected parts once (16 B; mixed: 10 B and a 4 B scale per 512), the
+// populations once (8 B per state; mixed: 4 B), the group and item tables,
+// and the item row sums written.
 double launch_bytes(const rtbte_ctx* c, int parts) {
   int64_t ch = 0;
   for (int i = 0; i < c->n_inst; ++i)
@@ -742,8 +743,8 @@ double launch_bytes(const rtbte_ctx* c, int parts) {
       if (parts & (1 << k)) ch += c->counts[3 * i + k];
   const double tables = (double)sizeof(Group) * (double)c->n_groups +
                         (double)(sizeof(Item) + 4 + 8 * kMaxGroupRows) * (double)c->n_items;
-  if (c->mixed)  // 8 B indices + 2 B weight per channel, a 4 B scale per block; population prep 8+8 B per state
-    return 10.0 * (double)ch + 4.0 * (double)ch / kMixBlock + 24.0 * (double)c->ny + tables;
+  if (c->mixed)
+    return 10.0 * (double)ch + 4.0 * (double)ch / kMixBlock + 4.0 * (double)c->ny + tables;
   return 16.0 * (double)ch + 8.0 * (double)c->ny + tables;
 }
 
@@ -781,6 +782,7 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
     m.idx = c->mix_idx;
     m.wq = c->mix_wq;
     m.scale = c->mix_scale;
+    m.n_scale = (c->n_ch + kMixBlock - 1) / kMixBlock;
     m.pop = c->popf;
     m.groups = c->groups;
     m.items = c->items;

@@ -124,8 +124,9 @@ constexpr int32_t kMixTagShift = 24;
 struct MixArgs {
   const int2* idx;          // [n_ch] packed as above
   const uint16_t* wq;       // [n_ch] weight / scale of its block, 16-bit head
-  const float* scale;       // [ceil(n_ch / kMixBlock)]
-  const float2* pop;        // [ny] electrons (f, 1-f), phonons (N, N+1)
+  const float* scale;       // [n_scale] = [ceil(n_ch / kMixBlock)]
+  int64_t n_scale;
+  const float* pop;         // [ny] one coded FP32 word per state (k_popf)
   const Group* groups;
   const Item* items;
   const int32_t* order;
@@ -137,7 +138,7 @@ struct MixArgs {
 };
 hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s);
 // pop[i] from z[i] (each factor formed in FP64, then rounded to FP32)
-hipError_t launch_popf(float2* pop, const double* z, const int32_t* row_group, const Group* groups,
+hipError_t launch_popf(float* pop, const double* z, const int32_t* row_group, const Group* groups,
                        int64_t n, hipStream_t s);
 // create time: per-block scales, then the 16-bit weights and packed indices
 hipError_t launch_mix_scales(const Channel* ch, int64_t n_ch, float* scale, hipStream_t s);

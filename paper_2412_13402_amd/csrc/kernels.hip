@@ -237,17 +237,33 @@ hipError_t launch_finish_rows(const FinishArgs& f, bool stage, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ mixed precision
+#ifndef MIX_PAIRS
+#define MIX_PAIRS 2
+#endif
 // Weights are stored relative to the FP32 scale of their 512-channel block as
 // FP16 heads, extended by an 11-bit significand tail held in the index word
 // (or FP16 alone, or BF16 for e-ph and ph-e, on request); the factors are
-// evaluated in FP32 from FP32 populations
-// (each pair formed in FP64 and rounded once); every lane keeps a Neumaier
-// compensated FP32 sum per row of the group, and the lanes' sums and
-// compensations are added in FP64.
+// evaluated in FP32 from one FP32 word per state (4-byte gathers):
+//   phonon:   N; N + 1 is formed in FP32 (relative error <= 2u for N >= 0);
+//   electron: c = f if f <= 1/2, else c = 1 - f (formed in FP64), rounded to
+//             FP32 with the significand's lowest bit replaced by the choice;
+//             the other factor is 1 - c in FP32.  Both f and 1 - f come back
+//             within 4u relative for 0 <= f <= 1 (u = 2^-24), however close
+//             f is to 0 or 1, and the code is unambiguous for any real f.
+// Every lane keeps a Neumaier compensated FP32 sum per row of the group, and
+// the lanes' sums and compensations are added in FP64.
 __device__ __forceinline__ float bf16_to_f(uint32_t h) { return __uint_as_float(h << 16); }
 __device__ __forceinline__ float f16_to_f(uint32_t h) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
 }
+
+__device__ __forceinline__ float2 el_pair(float v) {   // (f, 1 - f)
+  const uint32_t b = __float_as_uint(v);
+  const float c = __uint_as_float(b & ~1u);            // flag cleared: f = 1 stays exact
+  const float o = 1.0f - c;
+  return (b & 1u) ? make_float2(o, c) : make_float2(c, o);
+}
+__device__ __forceinline__ float2 ph_pair(float v) { return make_float2(v, v + 1.0f); }   // (N, N + 1)
 
 struct MixAcc {
   float2* slot;  // this lane's (sum, compensation) of row j at slot[64 * j]
@@ -262,7 +278,9 @@ struct MixAcc {
 };
 
 template <int KIND>
-__device__ __forceinline__ float term_f(bool em, float w, float2 g0, float2 g1, float2 xr) {
+__device__ __forceinline__ float term_f(bool em, float w, float v0, float v1, float2 xr) {
+  const float2 g0 = KIND == K_PP ? ph_pair(v0) : el_pair(v0);
+  const float2 g1 = KIND == K_PHE ? el_pair(v1) : ph_pair(v1);
   if (KIND == K_EPH) {         // xr = (f_r, 1-f_r), g0 = (f_s, 1-f_s), g1 = (N_p, N_p+1)
     const float gain = xr.x * g0.y * (em ? g1.y : g1.x);
     const float loss = xr.y * g0.x * (em ? g1.x : g1.y);
@@ -278,44 +296,93 @@ __device__ __forceinline__ float term_f(bool em, float w, float2 g0, float2 g1, 
   }
 }
 
-// Channels [s, e) of one kind, four per lane per quad (quads are aligned to
-// 4 channels, so a quad never straddles a 512-channel scale block).
+// One channel of the mixed stream: decode the weight (head and tail, or BF16),
+// form w * factor in FP32 and add it to its row's compensated lane slot.
+template <int KIND>
+__device__ __forceinline__ void chan_mixed(MixAcc& acc, const MixArgs& a, uint32_t ix, uint32_t iy,
+                                           uint32_t head, float sc, float g0, float g1, const float2* rowv) {
+  const int tag = (ix >> kMixTagShift) & 15;
+  float w;
+  if (KIND != K_PP && a.wfmt == RTBTE_W_BF16_EPH) {
+    w = bf16_to_f(head);
+  } else {
+    // the tail fills FP32 significand bits 2..12, below the head's 10
+    const uint32_t tail = (ix >> 28) | ((iy >> 20) & 0x7f0u);
+    w = __uint_as_float(__float_as_uint(f16_to_f(head)) | (tail << 2));
+  }
+  acc.add(tag, term_f<KIND>((int32_t)iy < 0, w * sc, g0, g1, rowv[tag]));
+}
+
+// Channels [s, e) of one kind.  The stream is read as channel pairs (16 B of
+// index words and 4 B of weight heads per pair), lanes on consecutive pairs,
+// kMixPairs pairs 64 apart per lane per batch, so every load instruction
+// reads whole contiguous lines.  Two-stage pipeline as in the FP64 kernel:
+// the gathers of batch k are issued before the stream loads of batch k+1.
+// A batch (at most 512 channels) spans at most two 512-channel scale blocks,
+// whose scales are read once per batch with scalar loads.
+constexpr int kMixPairs = MIX_PAIRS;
 template <int KIND>
 __device__ __forceinline__ void seg_sum_mixed(MixAcc& acc, const MixArgs& a, int64_t s, int64_t e, int lane,
                                               const float2* rowv) {
   if (s >= e) return;
-  typedef unsigned int v2u __attribute__((ext_vector_type(2)));
-  const v4i* idx4 = reinterpret_cast<const v4i*>(a.idx);
-  const v2u* w4 = reinterpret_cast<const v2u*>(a.wq);
-  for (int64_t q = s / 4 + lane; q * 4 < e; q += 64) {
-    const v4i p0 = __builtin_nontemporal_load(idx4 + 2 * q);
-    const v4i p1 = __builtin_nontemporal_load(idx4 + 2 * q + 1);
-    const v2u wp = __builtin_nontemporal_load(w4 + q);
-    const float sc = a.scale[q / (kMixBlock / 4)];
-    const uint32_t i0[4] = {(uint32_t)p0.x, (uint32_t)p0.z, (uint32_t)p1.x, (uint32_t)p1.z};
-    const uint32_t i1[4] = {(uint32_t)p0.y, (uint32_t)p0.w, (uint32_t)p1.y, (uint32_t)p1.w};
-    const uint32_t wh[4] = {wp.x & 0xffffu, wp.x >> 16, wp.y & 0xffffu, wp.y >> 16};
-    float2 g0[4], g1[4];
+  constexpr int NP = kMixPairs;
+  const v4i* idx2 = reinterpret_cast<const v4i*>(a.idx);
+  const uint32_t* w2 = reinterpret_cast<const uint32_t*>(a.wq);
+  const int64_t p_end = (e + 1) / 2;          // pairs [s / 2, p_end)
+  int64_t pb = s / 2;                          // first pair of the batch (wave-uniform)
+  v4i c[NP];
+  uint32_t h[NP];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      g0[j] = a.pop[i0[j] & kMixPosMask];
-      g1[j] = a.pop[i1[j] & kMixPosMask];
+  for (int j = 0; j < NP; ++j) {
+    const int64_t q = pb + lane + 64 * j;
+    c[j] = v4i{0, 0, 0, 0};
+    h[j] = 0;
+    if (q < p_end) { c[j] = __builtin_nontemporal_load(idx2 + q); h[j] = __builtin_nontemporal_load(w2 + q); }
+  }
+  for (;;) {
+    float g0[2 * NP], g1[2 * NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      g0[2 * j] = a.pop[(uint32_t)c[j].x & kMixPosMask];
+      g1[2 * j] = a.pop[(uint32_t)c[j].y & kMixPosMask];
+      g0[2 * j + 1] = a.pop[(uint32_t)c[j].z & kMixPosMask];
+      g1[2 * j + 1] = a.pop[(uint32_t)c[j].w & kMixPosMask];
     }
+    const int64_t blk = __builtin_amdgcn_readfirstlane((int)(pb / (kMixBlock / 2)));
+    const float s_lo = a.scale[blk];
+    const float s_hi = a.scale[blk + 1 < a.n_scale ? blk + 1 : blk];
+    const int64_t nb = pb + 64 * NP;
+    const bool more = nb < p_end;
+    v4i n[NP];
+    uint32_t m[NP];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t c = q * 4 + j;
-      if (c < s || c >= e) continue;
-      const int tag = (i0[j] >> kMixTagShift) & 15;
-      float w;
-      if (KIND != K_PP && a.wfmt == RTBTE_W_BF16_EPH) {
-        w = bf16_to_f(wh[j]);
-      } else {
-        // the tail fills FP32 significand bits 2..12, below the head's 10
-        const uint32_t tail = (i0[j] >> 28) | ((i1[j] >> 20) & 0x7f0u);
-        w = __uint_as_float(__float_as_uint(f16_to_f(wh[j])) | (tail << 2));
+    for (int j = 0; j < NP; ++j) {
+      n[j] = v4i{0, 0, 0, 0};
+      m[j] = 0;
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        const int64_t q = nb + lane + 64 * j;
+        if (q < p_end) { n[j] = __builtin_nontemporal_load(idx2 + q); m[j] = __builtin_nontemporal_load(w2 + q); }
       }
-      acc.add(tag, term_f<KIND>((int32_t)i1[j] < 0, w * sc, g0[j], g1[j], rowv[tag]));
     }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int64_t q = pb + lane + 64 * j;
+      const float sc = q / (kMixBlock / 2) == blk ? s_lo : s_hi;
+      const int64_t ca = 2 * q;
+      if (ca >= s && ca < e) chan_mixed<KIND>(acc, a, c[j].x, c[j].y, h[j] & 0xffffu, sc, g0[2 * j], g1[2 * j], rowv);
+      if (ca + 1 >= s && ca + 1 < e)
+        chan_mixed<KIND>(acc, a, c[j].z, c[j].w, h[j] >> 16, sc, g0[2 * j + 1], g1[2 * j + 1], rowv);
+    }
+    if (!more) break;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      c[j] = n[j];
+      h[j] = m[j];
+    }
+    pb = nb;
   }
 }
 
@@ -337,7 +404,10 @@ __global__ __launch_bounds__(64) void k_items_mixed(MixArgs a) {
   }
 #pragma unroll
   for (int j = 0; j < G; ++j) acc_lds[j][lane] = make_float2(0.f, 0.f);
-  if (active && lane < g.nrows) rowv[lane] = a.pop[g.row0 + lane];
+  if (active && lane < g.nrows) {
+    const float v = a.pop[g.row0 + lane];
+    rowv[lane] = g.phonon ? ph_pair(v) : el_pair(v);
+  }
   __syncthreads();
   MixAcc acc{&acc_lds[0][lane]};
   if (active) {
@@ -372,16 +442,22 @@ hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void k_popf(float2* pop, const double* __restrict__ z, const int32_t* row_group,
+// One FP32 word per state, coded as described above for the mixed gathers.
+__global__ void k_popf(float* pop, const double* __restrict__ z, const int32_t* row_group,
                        const Group* groups, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double v = z[i];
-  if (groups[row_group[i]].phonon) pop[i] = make_float2((float)v, (float)(v + 1.0));
-  else pop[i] = make_float2((float)v, (float)(1.0 - v));
+  if (groups[row_group[i]].phonon) {
+    pop[i] = (float)v;
+  } else {
+    const bool hi = v > 0.5;
+    const float c = (float)(hi ? 1.0 - v : v);
+    pop[i] = __uint_as_float((__float_as_uint(c) & ~1u) | (hi ? 1u : 0u));
+  }
 }
 
-hipError_t launch_popf(float2* pop, const double* z, const int32_t* row_group, const Group* groups,
+hipError_t launch_popf(float* pop, const double* z, const int32_t* row_group, const Group* groups,
                        int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_popf, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pop, z, row_group, groups, n);
