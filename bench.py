@@ -9,7 +9,11 @@ fused stage updates, the WRMS error norm and the device-side PID control.
 
 Prints one JSON line: channels/s (the metric), the roofline of the collision
 kernel (algorithmic bytes per launch over its HIP-event-timed duration), the
-simulated ps/s, and the FP64 oracle timed on this host's cores.
+simulated ps/s, and the FP64 oracle timed on this host's cores.  A second leg
+runs the same workload and steps in mixed precision ("mixed": its channels/s,
+simulated ps/s and their speedup over FP64, its kernel roofline, the RHS error
+against the oracle after each of its first steps, and the population error
+after 1 ps of RK4 against the FP64 path).
 """
 import argparse
 import hashlib
@@ -36,17 +40,19 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, per_launch_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the collision kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source;
+    else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    e = d.get(precision)
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return e.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(wl, seconds):
@@ -88,6 +94,9 @@ def main():
     ap.add_argument("--item-channels", type=int, default=0, help="channels per work item (0: library choice)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--err-steps", type=int, default=5, help="mixed steps with a per-step RHS error report")
+    ap.add_argument("--no-errors", action="store_true", help="skip the mixed accuracy pass (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -126,7 +135,90 @@ def main():
     C = sum(counts)
     log(f"[bench] create {create_s:.1f} s; channels e-ph {counts[0]}, ph-e {counts[1]}, "
         f"ph-ph {counts[2]} (total {C}); rows per group (el, ph), channels per item {ctx.tuning()}")
+    leg = timed_steps(ctx, wl, args, C, "fp64")
+    k = leg["kernel"]
+    traffic = measured_traffic(args.workload if args.L is None else f"{args.workload}_L{args.L}", "fp64")
+    rec = {
+        "metric": "RHS scattering channels/s & % HBM peak; simulated ps/s at fixed error",
+        "value": leg["value"],
+        "unit": "channels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": leg["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded graphene-like band/phonon model and channel lists; no first-principles data)",
+        "config": {
+            "workload": f"{args.workload}: {'x'.join([str(wl.grid['L'])] * 2)} k=q grid, 2 bands, 6 branches, "
+                        f"FP64, adaptive Zonneveld ERK rtol {args.rtol:g}",
+            "channels_eph": counts[0], "channels_phe": counts[1], "channels_phph": counts[2],
+            "n_y": wl.n_y, "rhs_per_step": leg["rhs_per_step"],
+            "rows_per_group_el": ctx.tuning()[0], "rows_per_group_ph": ctx.tuning()[1],
+            "channels_per_item": ctx.tuning()[2],
+        },
+        "sim_ps_per_s": leg["sim_ps_per_s"],
+        "hbm_frac": k["achieved"] / HBM_PEAK_GBS,
+        "roofline": dict(k, traffic=traffic),
+        "create_s": create_s,
+        "generate_s": gen_s,
+    }
 
+    ctx_m = None
+    if not args.no_mixed:
+        t0 = time.perf_counter()
+        ctx_m = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED, rtol=args.rtol, atol_el=1e-9,
+                          atol_ph=1e-12, group_rows_el=args.group_rows_el, group_rows_ph=args.group_rows_ph,
+                          item_channels=args.item_channels)
+        torch.cuda.synchronize()
+        create_m = time.perf_counter() - t0
+        leg_m = timed_steps(ctx_m, wl, args, C, "mixed", start=leg["start"])
+        km = leg_m["kernel"]
+        tm = measured_traffic(args.workload if args.L is None else f"{args.workload}_L{args.L}", "mixed")
+        rec["mixed"] = {
+            "value": leg_m["value"], "unit": "channels/s", "ms_per_step": leg_m["ms_per_step"],
+            "sim_ps_per_s": leg_m["sim_ps_per_s"],
+            "speedup_sim_ps_per_s_vs_fp64": leg_m["sim_ps_per_s"] / leg["sim_ps_per_s"],
+            "speedup_rhs_kernel_vs_fp64": k["avg_launch_ms"] / km["avg_launch_ms"],
+            "rhs_per_step": leg_m["rhs_per_step"],
+            "t_span_fs": leg_m["t_span"], "fp64_t_span_fs": leg["t_span"],
+            "dtype": "weights FP16 head + 11-bit tail (22 significant bits) with per-512 FP32 scales; "
+                     "FP32 population codes, products and compensated lane sums; FP64 state, stages, "
+                     "WRMS and control",
+            "roofline": dict(km, traffic=tm),
+            "create_s": create_m,
+        }
+
+    o = None
+    if not args.no_cpu_baseline:
+        log("[bench] oracle baseline on host cores ...")
+        o, cb = cpu_baseline(wl, args.cpu_seconds)
+        rec["cpu_baseline"] = cb
+        # parity of the GPU right-hand side at the final state, every row
+        yf = leg["y"].cpu().numpy()
+        out = torch.empty_like(leg["y"])
+        ctx.rhs(leg["y"], out, P.PART_ALL)
+        torch.cuda.synchronize()
+        ref, S, A = o.rhs(yf, scales=True)
+        g = out.cpu().numpy()
+        rec["rhs_err_vs_oracle"] = {
+            "max_row_err_over_magnitude": float(np.max(np.abs(g - ref) / np.maximum(A, 1e-300))),
+            "normwise": float(np.linalg.norm(g - ref) / np.linalg.norm(ref)),
+        }
+    if ctx_m is not None and not args.no_errors:
+        rec["mixed"].update(mixed_errors(P, torch, np, ctx, ctx_m, wl, o, args))
+    print(json.dumps(rec), flush=True)
+
+
+def timed_steps(ctx, wl, args, C, label, start=None):
+    """Warm-up steps from the initial state, then exactly `steps` accepted
+    adaptive ERK steps, with the collision kernel timed by HIP events on its
+    stream.  With `start` (another leg's state after its warm-up: y, t, h and
+    the controller state), the timed steps resume from that state instead, so
+    two legs advance from the same point with the same step-size history."""
+    import torch
     dev = torch.device("cuda:0")
     y = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
     t = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -134,8 +226,15 @@ def main():
     for i in range(args.warmup):
         ctx.step_adaptive(y, t, h, 1e12, one_step=True)
     torch.cuda.synchronize()
-    log(f"[bench] warmup done: t = {t.item():.4g} fs, h = {h.item():.4g} fs")
-
+    log(f"[bench] {label} warmup done: t = {t.item():.4g} fs, h = {h.item():.4g} fs")
+    if start is None:
+        snap = (y.clone(), t.clone(), h.clone(), ctx.get_state())
+    else:
+        y.copy_(start[0]); t.copy_(start[1]); h.copy_(start[2])
+        ctx.set_state(start[3])
+        torch.cuda.synchronize()
+        snap = start
+        log(f"[bench] {label} resumes the first leg's state: t = {t.item():.4g} fs, h = {h.item():.4g} fs")
     s0 = ctx.stats()
     t_start = t.item()
     ctx.profile(True)
@@ -152,61 +251,58 @@ def main():
     wall = w1 - w0
     evals = s1["n_rhs_eph"] - s0["n_rhs_eph"]
     attempts = (s1["n_accept"] + s1["n_reject"]) - (s0["n_accept"] + s0["n_reject"])
-    value = evals * C / wall
-    log(f"[bench] {args.steps} steps ({attempts} attempts, {evals} RHS) in {wall * 1e3:.1f} ms; "
+    log(f"[bench] {label}: {args.steps} steps ({attempts} attempts, {evals} RHS) in {wall * 1e3:.1f} ms; "
         f"t {t_start:.4g} -> {t_end:.4g} fs")
     avg_ms = k_ms / max(k_n, 1)
     per_launch = k_bytes / max(k_n, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload if args.L is None else f"{args.workload}_L{args.L}", per_launch)
-    rec = {
-        "metric": "RHS scattering channels/s & % HBM peak; simulated ps/s at fixed error",
-        "value": value,
-        "unit": "channels/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded graphene-like band/phonon model and channel lists; no first-principles data)",
-        "config": {
-            "workload": f"{args.workload}: {'x'.join([str(wl.grid['L'])] * 2)} k=q grid, 2 bands, 6 branches, "
-                        f"FP64, adaptive Zonneveld ERK rtol {args.rtol:g}",
-            "channels_eph": counts[0], "channels_phe": counts[1], "channels_phph": counts[2],
-            "n_y": wl.n_y, "rhs_per_step": evals / args.steps,
-            "rows_per_group_el": ctx.tuning()[0], "rows_per_group_ph": ctx.tuning()[1],
-            "channels_per_item": ctx.tuning()[2],
-        },
-        "sim_ps_per_s": (t_end - t_start) * 1e-3 / wall,
-        "hbm_frac": achieved / HBM_PEAK_GBS,
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_items (collision integrals: per-item row sums)",
-            "launches": k_n, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch,
-        },
-        "create_s": create_s,
-        "generate_s": gen_s,
+    kernel = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "kernel": ("k_items" if label == "fp64" else "k_items_mixed") + " (collision integrals: per-item row sums)",
+        "launches": k_n, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch,
     }
-    if not args.no_cpu_baseline:
-        log("[bench] oracle baseline on host cores ...")
-        o, cb = cpu_baseline(wl, args.cpu_seconds)
-        rec["cpu_baseline"] = cb
-        # parity of the GPU right-hand side at the final state, every row
-        yf = y.cpu().numpy()
-        out = torch.empty_like(y)
-        ctx.rhs(y, out, P.PART_ALL)
+    return dict(value=evals * C / wall, ms_per_step=wall * 1e3 / args.steps, rhs_per_step=evals / args.steps,
+                sim_ps_per_s=(t_end - t_start) * 1e-3 / wall, kernel=kernel, y=y, start=snap,
+                t_span=(t_start, t_end))
+
+
+def mixed_errors(P, torch, np, ctx64, ctx_m, wl, o, args):
+    """Accuracy of the mixed path (untimed): the right-hand-side error after
+    each of the first steps of a mixed adaptive run (against the oracle, or the
+    FP64 GPU path when the oracle is not built), and the largest population
+    difference after 1 ps of RK4 with the same 4 fs steps in both precisions."""
+    dev = torch.device("cuda:0")
+    y = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    h = torch.zeros(1, dtype=torch.float64, device=dev)
+    out = torch.empty_like(y)
+    ref_d = torch.empty_like(y)
+    errs = []
+    for i in range(args.err_steps):
+        ctx_m.step_adaptive(y, t, h, 1e12, one_step=True)
+        ctx_m.rhs(y, out, P.PART_ALL)
         torch.cuda.synchronize()
-        ref, S, A = o.rhs(yf, scales=True)
         g = out.cpu().numpy()
-        rec["rhs_err_vs_oracle"] = {
-            "max_row_err_over_magnitude": float(np.max(np.abs(g - ref) / np.maximum(A, 1e-300))),
-            "normwise": float(np.linalg.norm(g - ref) / np.linalg.norm(ref)),
-        }
-    print(json.dumps(rec), flush=True)
+        if o is not None:
+            ref = o.rhs(y.cpu().numpy())
+        else:
+            ctx64.rhs(y, ref_d, P.PART_ALL)
+            torch.cuda.synchronize()
+            ref = ref_d.cpu().numpy()
+        errs.append({"t_fs": t.item(), "normwise": float(np.linalg.norm(g - ref) / np.linalg.norm(ref))})
+    log(f"[bench] mixed RHS error per step: {[round(e['normwise'], 9) for e in errs]}")
+    res = {}
+    for name, c in (("fp64", ctx64), ("mixed", ctx_m)):
+        yy = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
+        tt = torch.zeros(1, dtype=torch.float64, device=dev)
+        c.step_rk4(yy, tt, 4.0, 250)
+        torch.cuda.synchronize()
+        res[name] = yy.cpu().numpy()
+    d = float(np.max(np.abs(res["mixed"] - res["fp64"])))
+    log(f"[bench] mixed vs FP64 populations after 1 ps of RK4 (4 fs): {d:.3e}")
+    return {"rhs_err_per_step": errs, "rhs_err_reference": "oracle" if o is not None else "FP64 GPU path",
+            "pop_err_after_1ps_rk4_4fs": d}
 
 
 if __name__ == "__main__":

@@ -119,8 +119,9 @@ typedef struct {
 typedef struct {
   int32_t precision;       /* RTBTE_FP64 (default) or RTBTE_MIXED: 16-bit weights relative
                               to one FP32 scale per 512 channels (format: mixed_weights),
-                              populations gathered as FP32 pairs formed in FP64, per-lane
-                              compensated FP32 sums added in FP64; the state, the stages,
+                              populations gathered as one FP32 code per state (formed in
+                              FP64), factors and products in FP32, per-lane compensated
+                              FP32 sums added in FP64; the state, the stages,
                               the WRMS norm and the step control stay FP64.  RTBTE_MIXED
                               holds at most 2^24 states per context (RTBTE_E_INVAL beyond) */
   int32_t mixed_weights;   /* RTBTE_MIXED only: RTBTE_W_F16X (default), RTBTE_W_F16 or
@@ -143,15 +144,27 @@ typedef struct {
   int32_t pid_order, pid_alt_sign;
   double safety, eta_max, eta_max_first, eta_fail_min, eta_fail_max, eps_floor;
   int32_t max_fails;
-  int32_t use_graph;        /* replay each step through a captured HIP graph (1) or launch (0) */
+  int32_t use_graph;        /* 1: the steps between two host checks of the done flags are
+                               captured once into a HIP graph (per argument set: y, t/h
+                               buffers, tableau, controller) on a stream of the context, and
+                               replayed on the caller's stream; 0: launched one by one.  The
+                               results are identical.  Profiling (rtbte_profile) launches
+                               eagerly, since it times individual launches.                  */
   int32_t steps_per_poll;   /* steps enqueued between host checks of the done flags           */
   int32_t group_rows_el;    /* consecutive electron rows sharing one merged channel stream:
                                1, 2, 4, 8, 12 or 16 (0: 8)                                     */
   int32_t group_rows_ph;    /* the same for phonon rows (0: 16)                                 */
   int64_t item_channels;    /* channels per work item of the collision kernel (0: sized so
                                that there are ~40k items, within [2048, 65536])                */
-  int32_t tune;             /* 1: time the launch shapes at create and keep the fastest      */
-  const char *tune_cache;   /* file caching tuning results (NULL: env RTBTE_TUNE_CACHE)       */
+  int32_t tune;             /* 1: autotune the launch shape at create: for up to four row-group
+                               layouts (the given or default one; 4 and 16 electron rows; 8
+                               phonon rows) and three item sizes each (the given or default
+                               one, half, double), time full right-hand sides and keep the
+                               fastest.  Any shape gives the same results to rounding order.
+                               Costs up to four layout builds; a cache hit costs one.        */
+  const char *tune_cache;   /* text file of tuned shapes, one line per problem signature
+                               (device, precision, sizes); read before tuning, appended
+                               after.  NULL: env RTBTE_TUNE_CACHE; neither: no cache.         */
 } rtbte_options;
 
 typedef struct {
@@ -221,6 +234,11 @@ int rtbte_get_stats(const rtbte_ctx *ctx, int32_t inst, rtbte_stats *out);
 /* Launch shape in use: electron and phonon rows per group, channels per item. */
 int rtbte_get_tuning(const rtbte_ctx *ctx, int32_t *group_rows_el, int32_t *group_rows_ph,
                      int64_t *item_channels);
+/* Where the shape came from: *source = 0 given or default, 1 tuned at create
+ * (then *rhs_ms is the measured time of one right-hand side), 2 tune cache. */
+int rtbte_get_tuning_source(const rtbte_ctx *ctx, int32_t *source, double *rhs_ms);
+/* Number of HIP graph launches made by the stepping calls (use_graph). */
+int64_t rtbte_graph_launches(const rtbte_ctx *ctx);
 
 /* Checkpoint of the integrator state kept in the context (PID histories,
  * step sizes, counters; not y, which the caller owns).  With buf == NULL,

@@ -145,6 +145,21 @@ struct rtbte_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   double prof_ms = 0.0, prof_bytes = 0.0;
   int64_t prof_n = 0;
+  // host copy of the group table (work items are cut from it)
+  std::vector<Group> groups_h;
+  // captured step sequences, replayed through HIP graphs (use_graph)
+  struct GraphKey {
+    const double* y; const double* forcing; const InstState* st;
+    int tb_stages, parts, steps;   // the tableau is identified by its stage count (RK4 4, Zonneveld 5)
+    Ctl ctl;
+  };
+  struct GraphEntry { GraphKey key; hipGraph_t g; hipGraphExec_t exec; };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap = nullptr;       // capture stream (default priority)
+  int64_t graph_launches = 0;
+  // launch-shape tuning: source of the shape and the time it measured
+  int tuned = 0;                   // 0 given/default, 1 measured at create, 2 from the cache
+  double tuned_ms = 0.0;
 };
 
 static int fail(rtbte_ctx* c, int code, const char* fmt, ...) {
@@ -330,6 +345,11 @@ void free_ctx(rtbte_ctx* c) {
                 c->partial, c->tvec, c->summary_d};
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  for (auto& g : c->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.g);
+  }
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   for (auto& p : c->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (auto& p : c->pool) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
   if (c->summary_h) (void)hipHostFree(c->summary_h);
@@ -339,11 +359,57 @@ void free_ctx(rtbte_ctx* c) {
 
 bool valid_group_rows(int g) { return g == 1 || g == 2 || g == 4 || g == 8 || g == 12 || g == 16; }
 
+// Default channels per work item: about 40k items, within [2048, 65536].
+int64_t auto_item_channels(int64_t n_ch) { return std::min<int64_t>(65536, std::max<int64_t>(2048, n_ch / 40960)); }
+
+// (Re)build the work items: each group's channels cut into near-equal pieces
+// of at most `ich` channels; processing order longest first (stable).
+hipError_t build_items(rtbte_ctx* c, int64_t ich) {
+  if (ich <= 0) ich = auto_item_channels(c->n_ch);
+  void* old[] = {c->items, c->order, c->item_ptr, c->partial_items};
+  for (void* p : old)
+    if (p) (void)hipFree(p);
+  c->items = nullptr; c->order = nullptr; c->item_ptr = nullptr; c->partial_items = nullptr;
+  c->item_channels = ich;
+  std::vector<Item> items;
+  std::vector<int64_t> iptr((size_t)c->n_groups + 1, 0);
+  for (int64_t gi = 0; gi < c->n_groups; ++gi) {
+    const Group& gr = c->groups_h[gi];
+    const int64_t len = gr.end - gr.start;
+    const int64_t n = len ? (len + ich - 1) / ich : 0;
+    for (int64_t q = 0; q < n; ++q) {
+      Item it{};
+      it.lo = gr.start + len * q / n;
+      it.hi = gr.start + len * (q + 1) / n;
+      it.group = (int32_t)gi;
+      items.push_back(it);
+    }
+    iptr[gi + 1] = (int64_t)items.size();
+  }
+  c->n_items = (int64_t)items.size();
+  std::vector<int32_t> order((size_t)c->n_items);
+  for (int64_t i = 0; i < c->n_items; ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return items[x].hi - items[x].lo > items[y].hi - items[y].lo;
+  });
+  hipError_t e = upload(&c->items, items.data(), items.size());
+  if (e == hipSuccess) e = upload(&c->order, order.data(), order.size());
+  if (e == hipSuccess) e = upload(&c->item_ptr, iptr.data(), iptr.size());
+  if (e == hipSuccess)
+    c->partial_items = dalloc<double>((size_t)std::max<int64_t>(c->n_items, 1) * kMaxGroupRows, &e);
+  for (auto& g : c->graphs) {  // captured launches hold the old tables
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.g);
+  }
+  c->graphs.clear();
+  return e;
+}
+
 }  // namespace
 
-extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const rtbte_options* opts,
-                            rtbte_ctx** out) {
-  g_create_error.clear();
+// Build a context with the launch shape in `opts` (no tuning).
+static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbte_options* opts,
+                       rtbte_ctx** out) {
   if (!out) return fail(nullptr, RTBTE_E_INVAL, "out is NULL");
   *out = nullptr;
   if (!problems || n_inst < 1) return fail(nullptr, RTBTE_E_INVAL, "need n_inst >= 1 problems");
@@ -574,40 +640,13 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
     d.release();
   }
 
-  // Work items: each group's channels cut into pieces of at most
-  // item_channels; processing order longest first (stable).
-  int64_t ich = o.item_channels;
-  if (ich == 0) ich = std::min<int64_t>(65536, std::max<int64_t>(2048, c->n_ch / 40960));
-  c->item_channels = ich;
-  std::vector<Item> items;
-  std::vector<int64_t> iptr((size_t)c->n_groups + 1, 0);
   std::vector<int32_t> rgroup((size_t)c->ny, 0);
-  for (int64_t gi = 0; gi < c->n_groups; ++gi) {
-    const Group& gr = groups[gi];
-    for (int32_t j = 0; j < gr.nrows; ++j) rgroup[(size_t)gr.row0 + j] = (int32_t)gi;
-    const int64_t len = gr.end - gr.start;
-    const int64_t n = len ? (len + ich - 1) / ich : 0;
-    for (int64_t q = 0; q < n; ++q) {
-      Item it{};
-      it.lo = gr.start + len * q / n;
-      it.hi = gr.start + len * (q + 1) / n;
-      it.group = (int32_t)gi;
-      items.push_back(it);
-    }
-    iptr[gi + 1] = (int64_t)items.size();
-  }
-  c->n_items = (int64_t)items.size();
-  std::vector<int32_t> order((size_t)c->n_items);
-  for (int64_t j = 0; j < c->n_items; ++j) order[j] = (int32_t)j;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    return items[x].hi - items[x].lo > items[y].hi - items[y].lo;
-  });
+  for (int64_t gi = 0; gi < c->n_groups; ++gi)
+    for (int32_t j = 0; j < groups[gi].nrows; ++j) rgroup[(size_t)groups[gi].row0 + j] = (int32_t)gi;
   e = upload(&c->groups, groups.data(), groups.size());
-  if (e == hipSuccess) e = upload(&c->items, items.data(), items.size());
-  if (e == hipSuccess) e = upload(&c->order, order.data(), order.size());
-  if (e == hipSuccess) e = upload(&c->item_ptr, iptr.data(), iptr.size());
   if (e == hipSuccess) e = upload(&c->row_group, rgroup.data(), rgroup.size());
-  if (e == hipSuccess) c->partial_items = dalloc<double>((size_t)std::max<int64_t>(c->n_items, 1) * kMaxGroupRows, &e);
+  c->groups_h = std::move(groups);
+  if (e == hipSuccess) e = build_items(c, o.item_channels);
   if (e == hipSuccess && o.precision == RTBTE_MIXED) {
     // 16-bit weights with per-block FP32 scales; the FP64 channels are freed
     const int64_t nblk = (c->n_ch + kMixBlock - 1) / kMixBlock;
@@ -728,6 +767,15 @@ extern "C" int rtbte_get_tuning(const rtbte_ctx* c, int32_t* group_rows_el, int3
   if (item_channels) *item_channels = c->item_channels;
   return RTBTE_OK;
 }
+
+extern "C" int rtbte_get_tuning_source(const rtbte_ctx* c, int32_t* source, double* rhs_ms) {
+  if (!c) return RTBTE_E_INVAL;
+  if (source) *source = c->tuned;
+  if (rhs_ms) *rhs_ms = c->tuned_ms;
+  return RTBTE_OK;
+}
+
+extern "C" int64_t rtbte_graph_launches(const rtbte_ctx* c) { return c ? c->graph_launches : -1; }
 
 // ------------------------------------------------------------ right-hand side
 namespace {
@@ -929,6 +977,57 @@ int enqueue_h0(rtbte_ctx* c, double* y, int parts, const double* forcing, InstSt
   return RTBTE_OK;
 }
 
+bool same_ctl(const Ctl& a, const Ctl& b) {
+  return a.k1 == b.k1 && a.k2 == b.k2 && a.k3 == b.k3 && a.order == b.order && a.safety == b.safety &&
+         a.eta_max == b.eta_max && a.eta_max_first == b.eta_max_first && a.eta_fail_min == b.eta_fail_min &&
+         a.eta_fail_max == b.eta_fail_max && a.eps_floor == b.eps_floor && a.rtol == b.rtol &&
+         a.atol_el == b.atol_el && a.atol_ph == b.atol_ph && a.max_fails == b.max_fails &&
+         a.alt_sign == b.alt_sign && a.fixed == b.fixed && a.stages == b.stages;
+}
+
+// The executable graph of `steps` attempted steps with these arguments,
+// captured on the context's own stream the first time it is asked for.  The
+// captured region holds kernel launches only.
+int step_graph(rtbte_ctx* c, double* y, int parts, const double* forcing, InstState* st, const Ctl& ctl,
+               const Tableau& tb, int steps, hipGraphExec_t* out) {
+  for (auto& g : c->graphs) {
+    const auto& k = g.key;
+    if (k.y == y && k.forcing == forcing && k.st == st && k.tb_stages == tb.S && k.parts == parts &&
+        k.steps == steps && same_ctl(k.ctl, ctl)) {
+      *out = g.exec;
+      return RTBTE_OK;
+    }
+  }
+  if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  if (c->graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    (void)hipGraphDestroy(c->graphs.front().g);
+    c->graphs.erase(c->graphs.begin());
+  }
+  HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  int rc = RTBTE_OK;
+  for (int m = 0; m < steps && rc == RTBTE_OK; ++m) rc = enqueue_step(c, y, parts, forcing, st, ctl, tb, c->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (rc != RTBTE_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != RTBTE_OK ? rc : fail(c, RTBTE_E_HIP, "step capture: %s", hipGetErrorString(e));
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(c, RTBTE_E_HIP, "graph instantiate: %s", hipGetErrorString(e2));
+  }
+  rtbte_ctx::GraphEntry ent{};
+  ent.key = {y, forcing, st, tb.S, parts, steps, ctl};
+  ent.g = g;
+  ent.exec = ex;
+  c->graphs.push_back(ent);
+  *out = ex;
+  return RTBTE_OK;
+}
+
 int poll(rtbte_ctx* c, InstState* st, double* t, double* h, hipStream_t s, bool* all_done, int* worst) {
   HIPCHK(c, launch_finish(st, t, h, c->n_inst, c->summary_d, s));
   HIPCHK(c, hipMemcpyAsync(c->summary_h, c->summary_d, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -958,10 +1057,21 @@ int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_ste
   const int per_poll = one_step ? 1 : c->opt.steps_per_poll;
   bool done = false;
   int worst = 0;
+  // Graph replay: the same launches as the loop below, captured once per
+  // argument set (profiling times individual launches, so it stays eager).
+  const bool graph = c->opt.use_graph && !c->prof;
   while (!done) {
-    for (int m = 0; m < per_poll; ++m) {
-      int rc = enqueue_step(c, y, parts, forcing, st, ctl, tb, s);
+    if (graph) {
+      hipGraphExec_t ex = nullptr;
+      int rc = step_graph(c, y, parts, forcing, st, ctl, tb, per_poll, &ex);
       if (rc) return rc;
+      HIPCHK(c, hipGraphLaunch(ex, s));
+      c->graph_launches++;
+    } else {
+      for (int m = 0; m < per_poll; ++m) {
+        int rc = enqueue_step(c, y, parts, forcing, st, ctl, tb, s);
+        if (rc) return rc;
+      }
     }
     int rc = poll(c, st, t, h, s, &done, &worst);
     if (rc) return rc;
@@ -1158,4 +1268,216 @@ extern "C" int rtbte_profile_read(rtbte_ctx* c, double* total_ms, int64_t* launc
   if (launches) *launches = c->prof_n;
   if (bytes) *bytes = c->prof_bytes;
   return RTBTE_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+// Cache key: device, precision and weight format, and the sizes and
+// parameters of every instance.  A collision can only cost speed: every
+// launch shape gives the same results to rounding order.
+std::string tune_key(const rtbte_problem* P, int n, const rtbte_options& o) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, o.device);
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, &n, sizeof n);
+  for (int i = 0; i < n; ++i) {
+    const rtbte_problem& p = P[i];
+    const int64_t v[6] = {p.n_el, p.n_ph, p.n_k_total, p.n_q_total, p.n_eph, p.n_pp};
+    const double d[4] = {p.sigma_eph, p.sigma_pp, p.nsigma, p.hw_cut};
+    h = fnv1a(h, v, sizeof v);
+    h = fnv1a(h, d, sizeof d);
+  }
+  const int32_t f[2] = {o.precision, o.precision == RTBTE_MIXED ? o.mixed_weights : 0};
+  h = fnv1a(h, f, sizeof f);
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s-cu%d-%016llx", prop.gcnArchName, prop.multiProcessorCount,
+           (unsigned long long)h);
+  for (char* q = buf; *q; ++q)
+    if (*q == ' ' || *q == ':') *q = '_';
+  return buf;
+}
+
+// Cache file: one line per entry, "key rows_el rows_ph item_channels ms";
+// the last line with the key wins.
+bool cache_lookup(const char* path, const std::string& key, int* ge, int* gp, int64_t* ich) {
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char k[200];
+  int a, b;
+  long long ic;
+  double ms;
+  bool hit = false;
+  while (fscanf(f, "%199s %d %d %lld %lf", k, &a, &b, &ic, &ms) == 5)
+    if (key == k && valid_group_rows(a) && valid_group_rows(b) && ic > 0) {
+      *ge = a; *gp = b; *ich = ic; hit = true;
+    }
+  fclose(f);
+  return hit;
+}
+
+void cache_store(const char* path, const std::string& key, int ge, int gp, int64_t ich, double ms) {
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d %lld %.6f\n", key.c_str(), ge, gp, (long long)ich, ms);
+  fclose(f);
+}
+
+// Mean time of one full right-hand side (collision kernel and row fix-up)
+// over `reps` launches after two untimed ones, on a stream of its own.
+int time_rhs(rtbte_ctx* c, const double* y, double* ydot, int reps, double* ms) {
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  FinishArgs f{};
+  f.out = ydot;
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = rhs_launch(c, y, RTBTE_PART_ALL, nullptr, f, false, s);
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = rhs_launch(c, y, RTBTE_PART_ALL, nullptr, f, false, s);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(s);
+  if (e != hipSuccess) return fail(c, RTBTE_E_HIP, "tuning: %s", hipGetErrorString(e));
+  *ms = (double)t / reps;
+  return RTBTE_OK;
+}
+
+// Coordinate search over launch shapes: rows per group (each candidate is a
+// full channel layout) and, for each layout, channels per work item (only the
+// item table is rebuilt).  The fastest context is kept; the shape goes to the
+// cache file.
+int tune_create(const rtbte_problem* P, int n, rtbte_options o, rtbte_ctx** out) {
+  const char* path = o.tune_cache ? o.tune_cache : getenv("RTBTE_TUNE_CACHE");
+  if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, RTBTE_E_HIP, "hipSetDevice failed");
+  const std::string key = tune_key(P, n, o);
+  o.tune = 0;
+  int ge = 0, gp = 0;
+  int64_t ich = 0;
+  if (cache_lookup(path, key, &ge, &gp, &ich)) {
+    o.group_rows_el = ge;
+    o.group_rows_ph = gp;
+    o.item_channels = ich;
+    const int rc = create_impl(P, n, &o, out);
+    if (rc == RTBTE_OK) (*out)->tuned = 2;
+    return rc;
+  }
+  const int ge0 = o.group_rows_el ? o.group_rows_el : 8, gp0 = o.group_rows_ph ? o.group_rows_ph : 16;
+  std::vector<std::pair<int, int>> layouts = {{ge0, gp0}, {4, gp0}, {16, gp0}, {ge0, 8}};
+  rtbte_ctx* best = nullptr;
+  double best_ms = INFINITY;
+  int64_t best_ich = 0;
+  double* y = nullptr;
+  double* yd = nullptr;
+  std::vector<std::pair<int, int>> seen;
+  int rc = RTBTE_OK;
+  for (auto lay : layouts) {
+    if (std::find(seen.begin(), seen.end(), lay) != seen.end()) continue;
+    seen.push_back(lay);
+    rtbte_options oc = o;
+    oc.group_rows_el = lay.first;
+    oc.group_rows_ph = lay.second;
+    oc.item_channels = 0;
+    rtbte_ctx* c = nullptr;
+    rc = create_impl(P, n, &oc, &c);
+    if (rc == RTBTE_E_NOMEM && best) {  // a second layout does not fit beside the best one
+      rc = RTBTE_OK;
+      continue;
+    }
+    if (rc != RTBTE_OK) break;
+    if (!y) {
+      hipError_t e = hipMalloc((void**)&y, (size_t)std::max<int64_t>(c->ny, 1) * sizeof(double));
+      if (e == hipSuccess) e = hipMalloc((void**)&yd, (size_t)std::max<int64_t>(c->ny, 1) * sizeof(double));
+      if (e == hipSuccess) e = hipMemset(y, 0, (size_t)std::max<int64_t>(c->ny, 1) * sizeof(double));
+      if (e != hipSuccess) {
+        rtbte_destroy(c);
+        rc = fail(nullptr, RTBTE_E_NOMEM, "tuning buffers: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+    const int64_t base = o.item_channels > 0 ? o.item_channels : c->item_channels;
+    std::vector<int64_t> cand = {base, std::max<int64_t>(512, base / 2), std::min<int64_t>(1 << 20, base * 2)};
+    double c_best = INFINITY;
+    int64_t c_ich = 0;
+    std::vector<int64_t> tried;
+    for (int64_t ic : cand) {
+      if (std::find(tried.begin(), tried.end(), ic) != tried.end()) continue;
+      tried.push_back(ic);
+      if (ic != c->item_channels && build_items(c, ic) != hipSuccess) {
+        rc = fail(nullptr, RTBTE_E_NOMEM, "tuning: work items");
+        break;
+      }
+      double ms = 0.0;
+      rc = time_rhs(c, y, yd, 5, &ms);
+      if (rc != RTBTE_OK) {
+        g_create_error = c->err;
+        break;
+      }
+      if (ms < c_best) { c_best = ms; c_ich = ic; }
+    }
+    if (rc != RTBTE_OK) {
+      rtbte_destroy(c);
+      break;
+    }
+    if (c_best < best_ms) {
+      if (c->item_channels != c_ich && build_items(c, c_ich) != hipSuccess) {
+        rtbte_destroy(c);
+        rc = fail(nullptr, RTBTE_E_NOMEM, "tuning: work items");
+        break;
+      }
+      if (best) rtbte_destroy(best);
+      best = c;
+      best_ms = c_best;
+      best_ich = c_ich;
+    } else {
+      rtbte_destroy(c);
+    }
+  }
+  if (y) (void)hipFree(y);
+  if (yd) (void)hipFree(yd);
+  if (rc != RTBTE_OK) {
+    if (best) rtbte_destroy(best);
+    return rc;
+  }
+  best->tuned = 1;
+  best->tuned_ms = best_ms;
+  best->opt.tune = 1;
+  if (rtbte_reset(best) != RTBTE_OK) {
+    const std::string msg = best->err;
+    rtbte_destroy(best);
+    return fail(nullptr, RTBTE_E_HIP, "%s", msg.c_str());
+  }
+  cache_store(path, key, best->group_rows_el, best->group_rows_ph, best_ich, best_ms);
+  *out = best;
+  return RTBTE_OK;
+}
+
+}  // namespace
+
+extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const rtbte_options* opts,
+                            rtbte_ctx** out) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, RTBTE_E_INVAL, "out is NULL");
+  *out = nullptr;
+  rtbte_options o;
+  if (opts) o = *opts;
+  else rtbte_default_options(&o);
+  if (o.tune) {
+    // the candidate contexts check every argument themselves
+    return tune_create(problems, n_inst, o, out);
+  }
+  return create_impl(problems, n_inst, &o, out);
 }

@@ -113,6 +113,9 @@ def load():
     L.rtbte_reset.argtypes = [_vp]
     L.rtbte_get_stats.argtypes = [_vp, i32, ctypes.POINTER(Stats)]
     L.rtbte_get_tuning.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.rtbte_get_tuning_source.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    L.rtbte_graph_launches.argtypes = [_vp]
+    L.rtbte_graph_launches.restype = i64
     L.rtbte_get_state.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]
     L.rtbte_set_state.argtypes = [_vp, _vp, ctypes.c_size_t]
     L.rtbte_profile.argtypes = [_vp, i32]
@@ -246,6 +249,15 @@ class Context:
         ge, gp, ic = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         self._check(load().rtbte_get_tuning(self._h, ctypes.byref(ge), ctypes.byref(gp), ctypes.byref(ic)))
         return ge.value, gp.value, ic.value
+
+    def tuning_source(self):
+        """(0 given/default, 1 tuned at create, 2 from the tune cache; measured ms per RHS)."""
+        src, ms = ctypes.c_int32(), ctypes.c_double()
+        self._check(load().rtbte_get_tuning_source(self._h, ctypes.byref(src), ctypes.byref(ms)))
+        return src.value, ms.value
+
+    def graph_launches(self) -> int:
+        return int(load().rtbte_graph_launches(self._h))
 
     def profile(self, enable=True):
         self._check(load().rtbte_profile(self._h, int(bool(enable))))

@@ -1,0 +1,78 @@
+"""The C ABI without a GPU: the built library loads, exports every function
+that include/rtbte.h declares, the ctypes structures of the binding follow the
+header's field order, the defaults are the documented ones, and the binding
+fails loudly when the library is missing (no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rtbte.h")
+
+
+def header_text():
+    with open(HEADER) as f:
+        s = f.read()
+    s = re.sub(r"/\*.*?\*/", " ", s, flags=re.S)
+    return re.sub(r"//[^\n]*", " ", s)
+
+
+def declared_functions():
+    names = re.findall(r"\b(rtbte_\w+)\s*\(", header_text())
+    return sorted(set(names))
+
+
+def struct_fields(name):
+    m = re.search(r"typedef\s+struct\s*\{([^{}]*)\}\s*" + name + r"\s*;", header_text())
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        # "const int32_t *a, *b" -> a, b
+        first, *rest = decl.split(",")
+        fields.append(re.findall(r"(\w+)\s*$", first.strip())[0])
+        fields += [r.strip().lstrip("*").strip() for r in rest]
+    return fields
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2412_13402_amd import rtbte
+    if not os.path.exists(rtbte.lib_path()):
+        pytest.fail("librtbte.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(rtbte.lib_path())
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert "rtbte_create" in names and "rtbte_step_multirate" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_structs_follow_the_header():
+    from paper_2412_13402_amd import rtbte
+    for cname, py in (("rtbte_problem", rtbte.Problem), ("rtbte_options", rtbte.Options),
+                      ("rtbte_stats", rtbte.Stats)):
+        assert [f for f, _ in py._fields_] == struct_fields(cname), cname
+
+
+def test_default_options():
+    from paper_2412_13402_amd import rtbte
+    o = rtbte.default_options()
+    assert o.precision == rtbte.FP64 and o.mixed_weights == rtbte.W_F16X
+    assert (o.rtol, o.atol_el, o.atol_ph) == (1e-6, 1e-9, 1e-12)
+    assert o.use_graph == 0 and o.tune == 0 and o.steps_per_poll == 8
+    assert o.max_fails == 7 and o.safety == 0.96
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    from paper_2412_13402_amd import rtbte
+    monkeypatch.setattr(rtbte, "_LIB", None)
+    monkeypatch.setattr(rtbte, "lib_path", lambda: str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        rtbte.load()
