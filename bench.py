@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--err-steps", type=int, default=5, help="mixed steps with a per-step RHS error report")
     ap.add_argument("--no-errors", action="store_true", help="skip the mixed accuracy pass (profiling runs)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--batch", type=int, default=64, help="instances of the batched leg")
+    ap.add_argument("--batch-t-end", type=float, default=200.0, help="simulated fs of the batched leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -209,7 +212,114 @@ def main():
         }
     if ctx_m is not None and not args.no_errors:
         rec["mixed"].update(mixed_errors(P, torch, np, ctx, ctx_m, wl, o, args))
+    if not args.no_batched:
+        del ctx, ctx_m, o, leg
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        rec["batched"] = batched_leg(P, torch, np, args)
     print(json.dumps(rec), flush=True)
+
+
+def batched_leg(P, torch, np, args):
+    """Many independent graphene-like instances (grid sides uniform in
+    24..72, initial electron temperatures uniform in 500..3000 K, phonons at
+    300 K), each with its own adaptive step (rtol as above), advanced from
+    their initial states to the same end time: all in one mixed-precision
+    context whose step sequence is replayed through HIP graphs, against the
+    same instances run one by one in plain FP64 contexts.  Simulated time is
+    counted per instance (instance-ps per wall second)."""
+    import synth
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    ws = synth.build_batch(args.batch, (24, 72), (500.0, 3000.0))
+    gen_s = time.perf_counter() - t0
+    n = len(ws)
+    y0 = np.concatenate([w.y0 for w in ws])
+    probs = [w.problem_arrays() for w in ws]
+    tol = dict(rtol=args.rtol, atol_el=1e-9, atol_ph=1e-12)
+    t0 = time.perf_counter()
+    ctx = P.Context(probs, precision=P.rtbte.MIXED, use_graph=1, **tol)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    counts = ctx.counts()
+    C = sum(counts)
+    log(f"[bench] batched: {n} instances, {C} channels ({counts}), generated {gen_s:.1f} s, "
+        f"created {create_s:.1f} s, shape {ctx.tuning()}")
+    y = torch.tensor(y0, dtype=torch.float64, device=dev)
+    t = torch.zeros(n, dtype=torch.float64, device=dev)
+    h = torch.zeros(n, dtype=torch.float64, device=dev)
+    ctx.step_adaptive(y, t, h, 2.0)          # warm-up (first launches, graph capture)
+    torch.cuda.synchronize()
+    y.copy_(torch.tensor(y0, dtype=torch.float64, device=dev))
+    t.zero_()
+    h.zero_()
+    ctx.reset()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ctx.step_adaptive(y, t, h, args.batch_t_end)
+    torch.cuda.synchronize()
+    wall_m = time.perf_counter() - w0
+    steps_m = sum(ctx.stats(i)["n_accept"] + ctx.stats(i)["n_reject"] for i in range(n))
+    ym = y.cpu().numpy()
+    # the batched collision kernel alone, HIP-event timed
+    out = torch.empty_like(y)
+    ctx.profile(True)
+    for _ in range(5):
+        ctx.rhs(y, out, P.PART_ALL)
+    k_ms, k_n, k_bytes = ctx.profile_read()
+    ctx.profile(False)
+    kms = k_ms / max(k_n, 1)
+    achieved = k_bytes / max(k_n, 1) / (kms * 1e-3) / 1e9
+    layouts = [ctx.layout(i) for i in range(n)]
+    del ctx, y, out
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"[bench] batched mixed: {n} x {args.batch_t_end:g} fs in {wall_m * 1e3:.1f} ms ({steps_m} attempts)")
+    # plain FP64, one instance at a time
+    wall_f = 0.0
+    steps_f = 0
+    diff = 0.0
+    for i, w in enumerate(ws):
+        c = P.Context(w.problem_arrays(), **tol)
+        yi = torch.tensor(w.y0, dtype=torch.float64, device=dev)
+        ti = torch.zeros(1, dtype=torch.float64, device=dev)
+        hi = torch.zeros(1, dtype=torch.float64, device=dev)
+        if i == 0:                                  # warm-up once (first launches)
+            c.step_adaptive(yi, ti, hi, 2.0)
+            torch.cuda.synchronize()
+            yi.copy_(torch.tensor(w.y0, dtype=torch.float64, device=dev))
+            ti.zero_()
+            hi.zero_()
+            c.reset()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        c.step_adaptive(yi, ti, hi, args.batch_t_end)
+        torch.cuda.synchronize()
+        wall_f += time.perf_counter() - w0
+        st = c.stats()
+        steps_f += st["n_accept"] + st["n_reject"]
+        off, ne, nph = layouts[i]
+        diff = max(diff, float(np.max(np.abs(ym[off:off + ne + nph] - yi.cpu().numpy()))))
+        del c
+    log(f"[bench] plain FP64: {n} x {args.batch_t_end:g} fs in {wall_f * 1e3:.1f} ms ({steps_f} attempts); "
+        f"max |y_batched_mixed - y_plain_fp64| = {diff:.2e}")
+    inst_ps = n * args.batch_t_end * 1e-3
+    return {
+        "workload": f"{n} graphene-like instances, sides uniform in 24..72, T_el uniform in 500..3000 K, "
+                    f"adaptive Zonneveld ERK rtol {args.rtol:g}, each from its initial state to "
+                    f"{args.batch_t_end:g} fs",
+        "channels": C, "channels_eph": counts[0], "channels_phe": counts[1], "channels_phph": counts[2],
+        "mixed_graph_wall_s": wall_m, "plain_fp64_wall_s": wall_f,
+        "sim_instance_ps_per_s_mixed_batched": inst_ps / wall_m,
+        "sim_instance_ps_per_s_plain_fp64": inst_ps / wall_f,
+        "speedup_sim_ps_per_s": wall_f / wall_m,
+        "attempts_mixed": steps_m, "attempts_plain_fp64": steps_f,
+        "max_abs_pop_diff_at_t_end": diff,
+        "roofline_batched_mixed_kernel": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                          "avg_launch_ms": kms, "algorithmic_bytes_per_launch": k_bytes / max(k_n, 1)},
+        "generate_s": gen_s, "create_s": create_s,
+    }
 
 
 def timed_steps(ctx, wl, args, C, label, start=None):

@@ -567,6 +567,11 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   {
     int64_t pos = 0;
     for (int i = 0; i < n_inst; ++i) {
+      // every instance starts on a 512-channel boundary (the slots between
+      // instances are never read), so mixed-precision scale blocks never
+      // straddle two instances: an instance is stored, and computes, exactly
+      // as it would alone
+      pos = (pos + kMixBlock - 1) / kMixBlock * kMixBlock;
       const InstInfo& in = c->info[i];
       const int32_t nge = (int32_t)cnt_e[i].size(), ngp = (int32_t)cnt_pe[i].size();
       base_e[i].resize(nge);

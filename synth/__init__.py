@@ -290,3 +290,18 @@ def build(name: str, seed: int | None = None, dense: bool = False, **overrides):
     if seed is None:
         seed = MASTER_SEED + r.get("seed_offset", 0)
     return generate(grid, problem, init, seed, name=name, dense=dense)
+
+
+def build_batch(n: int = 64, L_range=(24, 72), T_range=(500.0, 3000.0), recipe: str = "graphene2d",
+                seed: int | None = None, **overrides):
+    """Independent instances of a recipe for batched runs: instance i has grid
+    side L_i drawn uniformly from the integers in L_range and initial electron
+    temperature T_i uniformly from T_range (phonons as in the recipe), and its
+    own generator seed.  Returns the list of Workloads."""
+    if seed is None:
+        seed = MASTER_SEED + 5
+    rng = np.random.default_rng(seed)
+    Ls = rng.integers(L_range[0], L_range[1] + 1, size=n)
+    Ts = rng.uniform(T_range[0], T_range[1], size=n)
+    return [build(recipe, seed=seed * 1000 + i, L=int(L), T_el=float(T), **overrides)
+            for i, (L, T) in enumerate(zip(Ls, Ts))]

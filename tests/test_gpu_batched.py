@@ -1,0 +1,95 @@
+"""Batched instances (independent graphene-like grids of different sizes and
+initial electron temperatures) in one context.
+
+Every instance starts its channels on a 512-channel boundary and owns its
+groups, items, step size and controller history, so in either precision an
+instance in a batch must compute bitwise what it computes alone: right-hand
+sides, and whole adaptive runs with the step sequence captured in HIP graphs.
+The mixed right-hand sides are also held to the a priori bound against the
+oracle (see the mixed tests for its derivation)."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rel_norm, say, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U_F16X = 2.0 ** -21
+U_SUB = 2.0 ** -39
+
+
+@functools.lru_cache(maxsize=None)
+def batch():
+    return synth.build_batch(6, (8, 16))
+
+
+def stack(ws):
+    return np.concatenate([w.y0 for w in ws])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_rhs_is_bitwise_alone(prec):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    ws = batch()
+    p = P.rtbte.FP64 if prec == "fp64" else P.rtbte.MIXED
+    kw = dict(precision=p, group_rows_el=8, group_rows_ph=16, item_channels=2048)
+    say(f"[batched] {prec} rhs of 6 instances")
+    multi = P.Context([w.problem_arrays() for w in ws], **kw)
+    y = np.concatenate([np.random.default_rng(7 + i).uniform(0, 1, w.n_y) for i, w in enumerate(ws)])
+    out = torch.empty((len(y),), dtype=torch.float64, device="cuda")
+    multi.rhs(to_dev(y), out, P.PART_ALL)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    for i, w in enumerate(ws):
+        off, ne, nph = multi.layout(i)
+        yi = y[off:off + ne + nph]
+        single = P.Context(w.problem_arrays(), **kw)
+        oi = torch.empty((w.n_y,), dtype=torch.float64, device="cuda")
+        single.rhs(to_dev(yi), oi, P.PART_ALL)
+        torch.cuda.synchronize()
+        assert np.array_equal(g[off:off + ne + nph], oi.cpu().numpy()), i
+        o = oracle.Oracle(w.problem_arrays())
+        ref, S, A, M, Q = o.rhs(yi, scales=True, unweighted=True)
+        gi = g[off:off + ne + nph]
+        if prec == "fp64":
+            assert np.all(np.abs(gi - ref) <= 1e-12 * A + 1e-300), i
+        else:
+            bound = (U_F16X + 24 * U32) * A + U_SUB * o.max_weight() * M
+            assert np.all(np.abs(gi - ref) <= bound + 1e-300), i
+            assert rel_norm(gi, ref) <= 1e-4
+
+
+def test_batched_mixed_graph_run_is_bitwise_alone():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    ws = batch()
+    n = len(ws)
+    kw = dict(precision=P.rtbte.MIXED, rtol=1e-6, atol_el=1e-9, atol_ph=1e-12, group_rows_el=8,
+              group_rows_ph=16, item_channels=2048)
+    say("[batched] mixed adaptive run of 6 instances to 40 fs, graph replay")
+    multi = P.Context([w.problem_arrays() for w in ws], use_graph=1, **kw)
+    y = to_dev(stack(ws))
+    t = torch.zeros(n, dtype=torch.float64, device="cuda")
+    h = torch.zeros(n, dtype=torch.float64, device="cuda")
+    multi.step_adaptive(y, t, h, 40.0)
+    torch.cuda.synchronize()
+    assert multi.graph_launches() > 0
+    assert np.all(t.cpu().numpy() == 40.0)
+    got = y.cpu().numpy()
+    for i, w in enumerate(ws):
+        single = P.Context(w.problem_arrays(), **kw)
+        yi = to_dev(w.y0)
+        ti = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hi = torch.zeros(1, dtype=torch.float64, device="cuda")
+        single.step_adaptive(yi, ti, hi, 40.0)
+        torch.cuda.synchronize()
+        off, ne, nph = multi.layout(i)
+        assert np.array_equal(got[off:off + ne + nph], yi.cpu().numpy()), i
+        assert multi.stats(i)["n_accept"] == single.stats(0)["n_accept"]
+        assert multi.stats(i)["n_reject"] == single.stats(0)["n_reject"]
