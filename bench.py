@@ -100,6 +100,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched leg")
     ap.add_argument("--batch-t-end", type=float, default=200.0, help="simulated fs of the batched leg")
+    ap.add_argument("--si3d", action="store_true",
+                    help="add the silicon-like 3D leg (40^3, ~2.5e9 channels; minutes): MIS vs ERK")
+    ap.add_argument("--si-L", type=int, default=40)
+    ap.add_argument("--si-t-end", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -217,7 +221,94 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         rec["batched"] = batched_leg(P, torch, np, args)
+    if args.si3d:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        rec["si3d"] = si3d_leg(P, torch, np, args)
     print(json.dumps(rec), flush=True)
+
+
+def kernel_roofline(ctx, torch, y, parts, reps=3):
+    out = torch.empty_like(y)
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.rhs(y, out, parts)
+    k_ms, k_n, k_bytes = ctx.profile_read()
+    ctx.profile(False)
+    ms = k_ms / max(k_n, 1)
+    by = k_bytes / max(k_n, 1)
+    ach = by / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "avg_launch_ms": ms, "algorithmic_bytes_per_launch": by}
+
+
+def si3d_leg(P, torch, np, args):
+    """Silicon-like 3D bulk (4 conduction bands, 6 branches): the third-order
+    MIS multirate method (slow ph-ph steps of 50 fs, fixed 1 fs RK4 steps for
+    the fast e-ph part) against the adaptive ERK on the whole right-hand side,
+    both from the initial state to the same end time, in FP64; MIS also in
+    mixed precision."""
+    import synth
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    wl = synth.build("si3d", L=args.si_L)
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] si3d {args.si_L}^3: n_el {wl.n_el} n_ph {wl.n_ph} entries {len(wl.eph_row)} e-ph + "
+        f"{len(wl.pp_row)} ph-ph, generated in {gen_s:.1f} s")
+    res = {"workload": f"si3d: {args.si_L}^3 k = q grid, 4 conduction bands, 6 branches, from the initial "
+                       f"state to {args.si_t_end:g} fs",
+           "generate_s": gen_s}
+    y0 = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
+    hs, hf = 50.0, 1.0
+    for prec, name in ((P.rtbte.FP64, "fp64"), (P.rtbte.MIXED, "mixed")):
+        t0 = time.perf_counter()
+        ctx = P.Context(wl.problem_arrays(), precision=prec, rtol=args.rtol, atol_el=1e-9, atol_ph=1e-12,
+                        fast_mode=1, h_fast=hf)
+        torch.cuda.synchronize()
+        cs = time.perf_counter() - t0
+        counts = ctx.counts()
+        log(f"[bench] si3d {name}: create {cs:.1f} s, channels {counts}")
+        leg = {"create_s": cs, "channels_eph": counts[0], "channels_phe": counts[1], "channels_phph": counts[2],
+               "roofline_slow_rhs": kernel_roofline(ctx, torch, y0, P.PART_PHPH),
+               "roofline_fast_rhs": kernel_roofline(ctx, torch, y0, P.PART_EPH | P.PART_PHE)}
+        runs = {}
+        for method in (("mis", "erk") if prec == P.rtbte.FP64 else ("mis",)):
+            y = y0.clone()
+            t = torch.zeros(1, dtype=torch.float64, device=dev)
+            h = torch.zeros(1, dtype=torch.float64, device=dev)
+            ctx.reset()
+            if method == "mis":   # warm-up on a copy (first launches)
+                yw, tw, hw_ = y0.clone(), torch.zeros_like(t), torch.zeros_like(h)
+                ctx.step_multirate(yw, tw, hw_, hs, hs)
+                ctx.reset()
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            if method == "mis":
+                ctx.step_multirate(y, t, h, args.si_t_end, hs)
+            else:
+                ctx.step_adaptive(y, t, h, args.si_t_end)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - w0
+            st = ctx.stats()
+            runs[method] = y.cpu().numpy()
+            leg[method] = {"wall_s": wall, "sim_ps_per_s": args.si_t_end * 1e-3 / wall,
+                           "rhs_eph": st["n_rhs_eph"], "rhs_phph": st["n_rhs_phph"],
+                           "steps": st["n_accept"], "rejected": st["n_reject"]}
+            log(f"[bench] si3d {name} {method}: {args.si_t_end:g} fs in {wall * 1e3:.1f} ms "
+                f"({st['n_rhs_eph']} fast-part and {st['n_rhs_phph']} ph-ph evaluations)")
+        if "erk" in runs:
+            leg["speedup_mis_vs_erk"] = leg["erk"]["wall_s"] / leg["mis"]["wall_s"]
+            leg["max_abs_diff_mis_vs_erk"] = float(np.max(np.abs(runs["mis"] - runs["erk"])))
+            res["_mis_fp64_y"] = runs["mis"]
+        else:
+            leg["max_abs_diff_vs_fp64_mis"] = float(np.max(np.abs(runs["mis"] - res["_mis_fp64_y"])))
+            leg["speedup_vs_fp64_mis"] = res["fp64"]["mis"]["wall_s"] / leg["mis"]["wall_s"]
+        res[name] = leg
+        del ctx
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    res.pop("_mis_fp64_y")
+    return res
 
 
 def batched_leg(P, torch, np, args):

@@ -1197,7 +1197,7 @@ extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* ou
       hipMemcpy(&f, c->st_fast + inst, sizeof f, hipMemcpyDeviceToHost) != hipSuccess)
     return RTBTE_E_HIP;
   std::memset(out, 0, sizeof *out);
-  out->n_accept = s.n_accept;
+  out->n_accept = s.n_accept + c->slow_steps;   // ERK steps, plus MIS slow steps (single instance)
   out->n_reject = s.n_reject;
   out->n_fast_accept = f.n_accept;
   out->n_fast_reject = f.n_reject;

@@ -75,7 +75,7 @@ class Params(ctypes.Structure):
         ("keep_eph", ctypes.c_double), ("keep_pp", ctypes.c_double),
         ("g2_mu", ctypes.c_double), ("g2_sig", ctypes.c_double),
         ("v2_mu", ctypes.c_double), ("v2_sig", ctypes.c_double),
-        ("seed", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64), ("keep_pp_q", ctypes.c_double),
     ]
 
 
@@ -101,6 +101,19 @@ def fermi_dirac(eps, T, mu=0.0):
     """Fermi-Dirac occupation at temperature T (K) and chemical potential mu (eV)."""
     x = (np.asarray(eps, dtype=np.float64) - mu) / (KB_EV_PER_K * T)
     return 0.5 * (1.0 - np.tanh(0.5 * x))
+
+
+def solve_mu(eps, T, density, n_k_total):
+    """Chemical potential (eV) at which the windowed states hold `density`
+    carriers per cell at temperature T (bisection; the count rises with mu)."""
+    lo, hi = float(np.min(eps)) - 5.0, float(np.max(eps)) + 5.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if fermi_dirac(eps, T, mid).sum() / n_k_total < density:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
 
 
 def bose_einstein(hw, T):
@@ -166,6 +179,24 @@ RECIPES = {
         init=dict(T_el=2000.0, T_ph=300.0, mu=0.3),
         seed_offset=12,
     ),
+    # Silicon-like 3D bulk: 40^3 simple-cubic-indexed k = q grid, 4 conduction
+    # bands (offset cosine bands) in a window 0.4 eV above the band minimum,
+    # 6 branches (acoustic TA1/TA2/LA with sin dispersions to 25/27/60 meV,
+    # optical near 62-64 meV), sigma 5 meV (e-ph) / 1.1 meV (ph-ph), cutoff
+    # 0.2 meV (Methods, silicon grids).  q-point triplets are thinned to ~3%
+    # (~2e9 ph-ph channels).  |g|^2 is scaled for an e-ph spectral radius of
+    # ~0.5/fs (fast steps of ~1 fs), |V3|^2 for a mean 300 K phonon decay rate
+    # of ~1/ps.  Carriers at 2000 K with 0.0184 electrons per cell, phonons at
+    # 300 K.
+    "si3d": dict(
+        grid=dict(dim=3, L=40, lattice=2, n_bands=4, n_modes=6, t_hop=0.5,
+                  win_lo=-1.0, win_hi=0.4, with_eph=1, with_pp=1,
+                  shell_eph=0.030, shell_pp=0.0066, keep_eph=1.0, keep_pp=1.0, keep_pp_q=0.03,
+                  g2_mu=-6.2, g2_sig=1.0, v2_mu=-15.0, v2_sig=1.0),
+        problem=dict(sigma_eph=0.005, sigma_pp=0.0011, nsigma=6.0, hw_cut=0.0002),
+        init=dict(T_el=2000.0, T_ph=300.0, density=0.0184),
+        seed_offset=3,
+    ),
     # Integer-lattice toy: every energy is a multiple of 25 meV and only exactly
     # energy-conserving channels are stored (the shell and the n*sigma
     # truncation are both below one quantum).
@@ -227,7 +258,7 @@ class Workload:
 
 def make_params(grid: dict, seed: int) -> Params:
     p = Params()
-    defaults = dict(quantize=0, quantum=0.025)
+    defaults = dict(quantize=0, quantum=0.025, keep_pp_q=1.0)
     for k, v in {**defaults, **grid}.items():
         setattr(p, k, v)
     p.seed = seed
@@ -263,7 +294,10 @@ def generate(grid: dict, problem: dict, init: dict, seed: int, name: str = "cust
                           v2=v2d.reshape(n_ph, N, nm, nm))
     finally:
         L.synth_destroy(h)
-    f0 = fermi_dirac(eps, init.get("T_el", 300.0), init.get("mu", 0.0))
+    mu = init.get("mu", 0.0)
+    if "density" in init:   # carriers per cell: sum_window f / N_k = density
+        mu = solve_mu(eps, init.get("T_el", 300.0), init["density"], N)
+    f0 = fermi_dirac(eps, init.get("T_el", 300.0), mu)
     n0 = bose_einstein(hw, init.get("T_ph", 300.0))
     wl = Workload(name=name, params=dict(grid=grid, problem=problem, init=init, seed=seed),
                   n_el=n_el, n_ph=n_ph, n_k_total=N, n_q_total=N, eps=eps, hw=hw,

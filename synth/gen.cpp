@@ -100,6 +100,8 @@ typedef struct {
   double g2_mu, g2_sig;            // ln|g|^2 ~ N(mu, sig), |g|^2 in eV^2
   double v2_mu, v2_sig;            // ln|V3|^2 ~ N(mu, sig), eV^2
   uint64_t seed;
+  double keep_pp_q;                // symmetric thinning of q-point triplets (q, q', q''),
+                                   // decided before any branch: 1 keeps all
 } synth_params;
 
 void synth_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
@@ -245,11 +247,23 @@ inline bool pair_channel(const Model &m, int f_lo, int f_hi, int nu, int q_lo_to
   return true;
 }
 
+// Is the q-point triplet (q0, q1, q2), q0 + q1 + q2 = 0, kept by the
+// q-level thinning?  Decided on the sorted ids: the same for every ordering.
+inline bool qtriplet_kept(const Model &m, int q0, int q1, int q2) {
+  if (!(m.p.keep_pp_q < 1.0)) return true;
+  int id[3] = {q0, q1, q2};
+  std::sort(id, id + 3);
+  uint64_t packed = (uint64_t)id[0] | ((uint64_t)id[1] << 21) | ((uint64_t)id[2] << 42) | (1ull << 62);
+  return keep_u01(packed, m.p.seed) < m.p.keep_pp_q;
+}
+
 // Is the unordered phonon triplet stored, and with which |V3|^2?  The shell
 // test uses the sorted frequencies, the hash the sorted ids: both are
 // invariant under permutation of the three phonons.
 inline bool triplet_channel(const Model &m, int l0, int l1, int l2, double *v2) {
   const synth_params &p = m.p;
+  const int nm = p.n_modes;
+  if (!qtriplet_kept(m, l0 / nm, l1 / nm, l2 / nm)) return false;
   const double wa = m.hw[l0], wb = m.hw[l1], wc = m.hw[l2];
   const double hi = std::max(std::max(wa, wb), wc), lo = std::min(std::min(wa, wb), wc);
   const double mid = std::max(std::min(wa, wb), std::min(std::max(wa, wb), wc));
@@ -300,6 +314,7 @@ void pp_row(const Model &m, int lam, F &&emit) {
   const double w0 = m.hw[lam];
   for (int q1 = 0; q1 < m.g.N; ++q1) {
     int q2 = m.g.add(mq, m.g.neg(q1));
+    if (!qtriplet_kept(m, q, q1, q2)) continue;   // the same decision triplet_channel takes
     const double *w1 = &m.hw[(size_t)q1 * nm], *w2 = &m.hw[(size_t)q2 * nm];
     // branch-free shell test of all (n1, n2) first (same selection as
     // triplet_channel), then the full decision for the few that pass

@@ -42,3 +42,27 @@ def assert_rows_close(gpu, ref, A, tol=1e-12, what=""):
     # and the componentwise test above is the criterion).
     if np.linalg.norm(ref) > 1e-3 * np.linalg.norm(A):
         assert rel_norm(gpu, ref) <= tol, f"{what}: normwise {rel_norm(gpu, ref):.3e}"
+
+
+def row_subset_problem(prob, rows_el, rows_ph):
+    """The entries of `prob` that feed the sampled destination rows: e-ph
+    entries of the sampled electron rows (electron side) or of the sampled
+    phonons (their ph-e channels come from these), and ph-ph entries of the
+    sampled phonon rows.  The oracle over this subset gives exactly the
+    sampled rows' right-hand side (every other row is incomplete), at a
+    fraction of the full lists' memory.  Indices are unchanged."""
+    import numpy as np
+    rows_el = np.asarray(rows_el, np.int64)
+    rows_ph = np.asarray(rows_ph, np.int64)
+    me = np.zeros(prob["n_el"], bool)
+    me[rows_el] = True
+    mp = np.zeros(prob["n_ph"], bool)
+    mp[rows_ph] = True
+    ke = me[prob["eph_row"]] | mp[prob["eph_phonon"]]
+    kp = mp[prob["pp_row"]]
+    out = dict(prob)
+    for k in ("eph_row", "eph_partner", "eph_phonon", "eph_g2"):
+        out[k] = np.ascontiguousarray(prob[k][ke])
+    for k in ("pp_row", "pp_a", "pp_b", "pp_v2"):
+        out[k] = np.ascontiguousarray(prob[k][kp])
+    return out

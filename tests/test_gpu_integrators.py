@@ -184,6 +184,7 @@ def test_multirate_fixed_fast_matches_oracle():
     assert close(y.cpu().numpy(), yr)
     st = ctx.stats()
     assert st["n_rhs_phph"] == 4 * 3
+    assert st["n_accept"] == 4
 
 
 def test_multirate_adaptive_fast_matches_oracle():

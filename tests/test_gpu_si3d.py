@@ -1,0 +1,116 @@
+"""Silicon-like 3D workload (4 conduction bands, 6 branches, MIS multirate
+with fast e-ph and slow ph-ph parts).
+
+Default: the si3d recipe on a 24^3 grid (~1.4e8 channels): FP64 right-hand
+side against the oracle on every row (1e-12 of each row's magnitude sum),
+mixed within its a priori bound, and a multirate run with fixed 1 fs RK4 fast
+steps against the oracle's MIS on every row (1e-12).
+Full size (40^3, ~2.5e9 channels) with RTBTE_FULL_SI3D=1: the FP64 and mixed
+right-hand sides on 2000 sampled rows against the oracle built on the
+entries of those rows alone."""
+import functools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import integrators as I
+from tests.gpu_util import rel_norm, row_subset_problem, say, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U_F16X = 2.0 ** -21
+U_SUB = 2.0 ** -39
+
+
+@functools.lru_cache(maxsize=None)
+def si(L):
+    return synth.build("si3d", L=L)
+
+
+def random_state(wl, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.uniform(0.0, 1.0, wl.n_el), rng.uniform(0.0, 2.0, wl.n_ph)])
+
+
+def test_si3d_24_rhs_fp64_and_mixed():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = si(24)
+    say(f"[si3d] 24^3: n_el {wl.n_el} n_ph {wl.n_ph} entries {len(wl.eph_row)} + {len(wl.pp_row)}")
+    o = oracle.Oracle(wl.problem_arrays())
+    c64 = P.Context(wl.problem_arrays())
+    cmx = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED)
+    assert c64.counts() == o.counts()
+    for y in (wl.y0, random_state(wl, 3)):
+        ref, S, A, M, Q = o.rhs(y, scales=True, unweighted=True)
+        for ctx, prec in ((c64, "fp64"), (cmx, "mixed")):
+            out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+            ctx.rhs(to_dev(y), out, P.PART_ALL)
+            torch.cuda.synchronize()
+            g = out.cpu().numpy()
+            if prec == "fp64":
+                assert np.all(np.abs(g - ref) <= 1e-12 * A + 1e-300)
+            else:
+                bound = (U_F16X + 24 * U32) * A + U_SUB * o.max_weight() * M
+                assert np.all(np.abs(g - ref) <= bound + 1e-300)
+                assert rel_norm(g, ref) <= 1e-4
+            say(f"    {prec}: normwise {rel_norm(g, ref):.2e}")
+
+
+def test_si3d_24_multirate_matches_oracle():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = si(24)
+    hs, hf, n = 50.0, 1.0, 2
+    say("[si3d] 24^3 MIS, slow 50 fs, fast RK4 1 fs, 2 slow steps")
+    ctx = P.Context(wl.problem_arrays(), fast_mode=1, h_fast=hf)
+    y = to_dev(wl.y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hfd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.step_multirate(y, t, hfd, n * hs, hs)
+    torch.cuda.synchronize()
+    o = oracle.Oracle(wl.problem_arrays())
+    fast = lambda v: o.rhs(v, parts=3)
+    slow = lambda v: o.rhs(v, parts=4)
+    yr = wl.y0.copy()
+    for _ in range(n):
+        yr = I.mis_step(fast, slow, yr, hs, I.rk4_fixed_solver(hf))
+    g = y.cpu().numpy()
+    assert t.item() == n * hs
+    assert float(np.max(np.abs(g - yr))) <= 1e-12 * max(1.0, float(np.max(np.abs(yr))))
+
+
+@pytest.mark.skipif(os.environ.get("RTBTE_FULL_SI3D") != "1",
+                    reason="full 40^3 silicon-like grid (~2.5e9 channels, minutes to generate): "
+                           "set RTBTE_FULL_SI3D=1")
+def test_si3d_full_size_sampled_rows():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = si(40)
+    say(f"[si3d] 40^3: n_el {wl.n_el} n_ph {wl.n_ph} entries {len(wl.eph_row)} + {len(wl.pp_row)}")
+    rng = np.random.default_rng(1)
+    rows_el = rng.choice(wl.n_el, 500, replace=False)
+    rows_ph = rng.choice(wl.n_ph, 1500, replace=False)
+    sub = oracle.Oracle(row_subset_problem(wl.problem_arrays(), rows_el, rows_ph))
+    idx = np.concatenate([rows_el, wl.n_el + rows_ph])
+    for prec in (P.rtbte.FP64, P.rtbte.MIXED):
+        ctx = P.Context(wl.problem_arrays(), precision=prec)
+        say(f"    precision {prec}: {sum(ctx.counts())} channels")
+        for y in (wl.y0, random_state(wl, 4)):
+            out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+            ctx.rhs(to_dev(y), out, P.PART_ALL)
+            torch.cuda.synchronize()
+            g = out.cpu().numpy()[idx]
+            ref, S, A, M, Q = sub.rhs(y, scales=True, unweighted=True)
+            ref, A, M = ref[idx], A[idx], M[idx]
+            if prec == P.rtbte.FP64:
+                assert np.all(np.abs(g - ref) <= 1e-12 * A + 1e-300)
+            else:
+                bound = (U_F16X + 24 * U32) * A + U_SUB * sub.max_weight() * M
+                assert np.all(np.abs(g - ref) <= bound + 1e-300)
+            say(f"    sampled normwise {rel_norm(g, ref):.2e}")
+        del ctx
