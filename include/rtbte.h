@@ -227,6 +227,15 @@ int rtbte_step_rk4(rtbte_ctx *ctx, double *y, double *t, double h_step, int64_t 
 int rtbte_step_multirate(rtbte_ctx *ctx, double *y, double *t, double *h_fast, double t_out,
                          double h_slow, int32_t one_step, void *stream);
 
+/* First-order operator splitting (the alternative the paper compares MIS
+ * with, Results, Fig. 3): each step of h_slow advances the fast part
+ * I^{e-ph} + I^{ph-e} over the step by RK4 substeps of h_fast (the last one
+ * cut to land), then the slow part I^{ph-ph} over the same interval by one
+ * RK4 step.  Advances *t (device) to t_out, the last step shortened to land.
+ * Only n_inst == 1 contexts support it (RTBTE_E_UNSUPPORTED otherwise). */
+int rtbte_step_split(rtbte_ctx *ctx, double *y, double *t, double h_fast, double h_slow, double t_out,
+                     void *stream);
+
 /* Clear the integrator state kept between calls (PID histories, counters). */
 int rtbte_reset(rtbte_ctx *ctx);
 int rtbte_get_stats(const rtbte_ctx *ctx, int32_t inst, rtbte_stats *out);

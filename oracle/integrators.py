@@ -274,6 +274,15 @@ def rk4_fixed_solver(h_fast):
     return solve
 
 
+def split_step(fast_rhs, slow_rhs, y, h_s, h_f):
+    """One step of the first-order operator splitting the paper compares
+    against (Results, discussion of Fig. 3): the fast part advanced over
+    [t, t + h_s] by RK4 with steps h_f (the last cut to land), then the slow
+    part advanced over the same interval by one RK4 step of h_s."""
+    y = rk4_fixed_solver(h_f)(y, 0.0, h_s, fast_rhs)
+    return rk4_step(slow_rhs, y, h_s)
+
+
 class AdaptiveFastSolver:
     """Fast solver: adaptive Zonneveld ERK whose step size and error history
     carry over from one stage interval to the next, capped by the interval."""

@@ -137,6 +137,7 @@ struct rtbte_ctx {
   // host tallies of right-hand-side evaluations outside the predicated step loop
   int64_t extra_rhs[3] = {0, 0, 0};
   int64_t slow_steps = 0;
+  int64_t split_slow_evals = 0;  // ph-ph evaluations of operator-splitting steps (run on st_fast)
   int last_status = 0;
   // timing of the collision-kernel launches with HIP events on their stream
   bool prof = false;
@@ -740,6 +741,7 @@ extern "C" int rtbte_reset(rtbte_ctx* c) {
   HIPCHK(c, hipMemcpy(c->st_fast, s.data(), s.size() * sizeof(InstState), hipMemcpyHostToDevice));
   c->extra_rhs[0] = c->extra_rhs[1] = c->extra_rhs[2] = 0;
   c->slow_steps = 0;
+  c->split_slow_evals = 0;
   c->last_status = 0;
   return RTBTE_OK;
 }
@@ -1110,6 +1112,35 @@ extern "C" int rtbte_step_rk4(rtbte_ctx* c, double* y, double* t, double h_step,
              (hipStream_t)stream);
 }
 
+namespace {
+
+// Fixed RK4 substeps of h over [t0, t1] on `parts` (plus `forcing` on the
+// phonon rows, if given), the last substep cut to land on t1; runs on the
+// fast-integrator state with the device scalar t_in as its clock.
+int rk4_segment(rtbte_ctx* c, double* y, double* t_in, int parts, const double* forcing, const Ctl& ctl,
+                double t0, double t1, double h, hipStream_t s) {
+  const Tableau tb = rk4();
+  int64_t nfull = 0;
+  double tt = t0;
+  while (tt < t1) {
+    if (tt + h >= t1) break;
+    tt += h;
+    ++nfull;
+  }
+  c->scal_h[2] = t0;
+  HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 2, sizeof(double), hipMemcpyHostToDevice, s));
+  int rc = RTBTE_OK;
+  if (nfull > 0) rc = run(c, y, t_in, nullptr, 0.0, 0, parts, forcing, c->st_fast, ctl, tb, 0.0, nfull, h, s);
+  if (rc == RTBTE_OK && t1 - tt > 0) {
+    c->scal_h[3] = tt;
+    HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 3, sizeof(double), hipMemcpyHostToDevice, s));
+    rc = run(c, y, t_in, nullptr, 0.0, 0, parts, forcing, c->st_fast, ctl, tb, 0.0, 1, t1 - tt, s);
+  }
+  return rc;
+}
+
+}  // namespace
+
 extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* h_fast, double t_out,
                                     double h_slow, int32_t one_step, void* stream) {
   if (!c) return RTBTE_E_INVAL;
@@ -1152,24 +1183,7 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
         rc = run(c, y, t_in, h_in, t1, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl, tb,
                  t1 - t0, 0, 0.0, s);
       } else {
-        // fixed RK4 substeps of h_fast, the last one cut to land on t1
-        int64_t nfull = 0;
-        double tt = t0;
-        while (tt < t1) {
-          if (tt + c->opt.h_fast >= t1) break;
-          tt += c->opt.h_fast;
-          ++nfull;
-        }
-        rc = RTBTE_OK;
-        if (nfull > 0)
-          rc = run(c, y, t_in, nullptr, 0.0, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl,
-                   tb, 0.0, nfull, c->opt.h_fast, s);
-        if (rc == RTBTE_OK && t1 - tt > 0) {
-          c->scal_h[3] = tt;
-          HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 3, sizeof(double), hipMemcpyHostToDevice, s));
-          rc = run(c, y, t_in, nullptr, 0.0, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl,
-                   tb, 0.0, 1, t1 - tt, s);
-        }
+        rc = rk4_segment(c, y, t_in, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, ctl, t0, t1, c->opt.h_fast, s);
       }
       if (rc) return rc;
       if (i < 3) {
@@ -1189,6 +1203,37 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
   return RTBTE_OK;
 }
 
+extern "C" int rtbte_step_split(rtbte_ctx* c, double* y, double* t, double h_fast, double h_slow, double t_out,
+                                void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (c->n_inst != 1) return fail(c, RTBTE_E_UNSUPPORTED, "split stepping needs a single instance");
+  if (!y || !t || !(h_fast > 0) || !(h_slow > 0) || !std::isfinite(t_out))
+    return fail(c, RTBTE_E_INVAL, "step_split: bad arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const Ctl ctl = make_ctl(c->opt, true, true);
+  HIPCHK(c, hipMemcpyAsync(c->scal_h, t, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  double tc = c->scal_h[0];
+  double* t_in = c->tvec;
+  while (tc < t_out) {
+    double hs = h_slow;
+    const bool last = tc + hs >= t_out;
+    if (last) hs = t_out - tc;
+    // fast part over the step, then the slow part over the same interval
+    int rc = rk4_segment(c, y, t_in, RTBTE_PART_EPH | RTBTE_PART_PHE, nullptr, ctl, 0.0, hs, h_fast, s);
+    if (rc == RTBTE_OK) rc = rk4_segment(c, y, t_in, RTBTE_PART_PHPH, nullptr, ctl, 0.0, hs, hs, s);
+    if (rc) return rc;
+    c->split_slow_evals += 4;
+    tc = last ? t_out : tc + hs;
+    c->slow_steps++;
+  }
+  c->scal_h[4] = tc;
+  HIPCHK(c, hipMemcpyAsync(t, c->scal_h + 4, sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return RTBTE_OK;
+}
+
 extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* out) {
   if (!c || !out || inst < 0 || inst >= c->n_inst) return RTBTE_E_INVAL;
   InstState s, f;
@@ -1202,9 +1247,10 @@ extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* ou
   out->n_fast_accept = f.n_accept;
   out->n_fast_reject = f.n_reject;
   const int64_t main_evals = s.n_evals, fast_evals = f.n_evals;
-  out->n_rhs_eph = main_evals + fast_evals + c->extra_rhs[0];
-  out->n_rhs_phe = main_evals + fast_evals + c->extra_rhs[1];
-  out->n_rhs_phph = main_evals + c->extra_rhs[2];
+  // the fast state also ran the slow sub-flows of splitting steps
+  out->n_rhs_eph = main_evals + fast_evals - c->split_slow_evals + c->extra_rhs[0];
+  out->n_rhs_phe = main_evals + fast_evals - c->split_slow_evals + c->extra_rhs[1];
+  out->n_rhs_phph = main_evals + c->split_slow_evals + c->extra_rhs[2];
   out->t = s.t;
   out->h_last = s.h;
   out->h_min = s.h_min;
@@ -1216,7 +1262,7 @@ extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* ou
 
 extern "C" int rtbte_get_state(const rtbte_ctx* c, void* buf, size_t* len) {
   if (!c || !len) return RTBTE_E_INVAL;
-  const size_t need = 2 * (size_t)c->n_inst * sizeof(InstState) + 4 * sizeof(int64_t);
+  const size_t need = 2 * (size_t)c->n_inst * sizeof(InstState) + 5 * sizeof(int64_t);
   if (!buf) {
     *len = need;
     return RTBTE_OK;
@@ -1228,7 +1274,7 @@ extern "C" int rtbte_get_state(const rtbte_ctx* c, void* buf, size_t* len) {
       hipMemcpy(p + c->n_inst * sizeof(InstState), c->st_fast, c->n_inst * sizeof(InstState),
                 hipMemcpyDeviceToHost) != hipSuccess)
     return RTBTE_E_HIP;
-  int64_t tail[4] = {c->extra_rhs[0], c->extra_rhs[1], c->extra_rhs[2], c->slow_steps};
+  int64_t tail[5] = {c->extra_rhs[0], c->extra_rhs[1], c->extra_rhs[2], c->slow_steps, c->split_slow_evals};
   std::memcpy(p + 2 * c->n_inst * sizeof(InstState), tail, sizeof tail);
   *len = need;
   return RTBTE_OK;
@@ -1236,19 +1282,20 @@ extern "C" int rtbte_get_state(const rtbte_ctx* c, void* buf, size_t* len) {
 
 extern "C" int rtbte_set_state(rtbte_ctx* c, const void* buf, size_t len) {
   if (!c || !buf) return RTBTE_E_INVAL;
-  const size_t need = 2 * (size_t)c->n_inst * sizeof(InstState) + 4 * sizeof(int64_t);
+  const size_t need = 2 * (size_t)c->n_inst * sizeof(InstState) + 5 * sizeof(int64_t);
   if (len != need) return fail(c, RTBTE_E_INVAL, "state size %zu, expected %zu", len, need);
   const char* p = (const char*)buf;
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipMemcpy(c->st, p, c->n_inst * sizeof(InstState), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->st_fast, p + c->n_inst * sizeof(InstState), c->n_inst * sizeof(InstState),
                       hipMemcpyHostToDevice));
-  int64_t tail[4];
+  int64_t tail[5];
   std::memcpy(tail, p + 2 * c->n_inst * sizeof(InstState), sizeof tail);
   c->extra_rhs[0] = tail[0];
   c->extra_rhs[1] = tail[1];
   c->extra_rhs[2] = tail[2];
   c->slow_steps = tail[3];
+  c->split_slow_evals = tail[4];
   return RTBTE_OK;
 }
 

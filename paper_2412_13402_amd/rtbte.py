@@ -110,6 +110,7 @@ def load():
     L.rtbte_step_adaptive.argtypes = [_vp, _vp, _vp, _vp, dbl, i32, _vp]
     L.rtbte_step_rk4.argtypes = [_vp, _vp, _vp, dbl, i64, _vp]
     L.rtbte_step_multirate.argtypes = [_vp, _vp, _vp, _vp, dbl, dbl, i32, _vp]
+    L.rtbte_step_split.argtypes = [_vp, _vp, _vp, dbl, dbl, dbl, _vp]
     L.rtbte_reset.argtypes = [_vp]
     L.rtbte_get_stats.argtypes = [_vp, i32, ctypes.POINTER(Stats)]
     L.rtbte_get_tuning.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
@@ -235,6 +236,10 @@ class Context:
         self._check(load().rtbte_step_multirate(self._h, _dptr(y, self.ny, "y"), _dptr(t, 1, "t"),
                                                 _dptr(h_fast, 1, "h_fast"), float(t_out), float(h_slow),
                                                 int(bool(one_step)), _stream(stream)))
+
+    def step_split(self, y, t, h_fast, h_slow, t_out, stream=None):
+        self._check(load().rtbte_step_split(self._h, _dptr(y, self.ny, "y"), _dptr(t, 1, "t"), float(h_fast),
+                                            float(h_slow), float(t_out), _stream(stream)))
 
     def reset(self):
         self._check(load().rtbte_reset(self._h))

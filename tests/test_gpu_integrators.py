@@ -297,3 +297,27 @@ def test_checkpoint_resume_is_bitwise():
     ctx.step_adaptive(ys, ts, hs, 25.0)
     torch.cuda.synchronize()
     assert np.array_equal(ya, ys.cpu().numpy()) and ts.item() == 25.0
+
+
+def test_operator_splitting_matches_oracle():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    hs, hf = 5.0, 0.7
+    say("[int] operator splitting, RK4 fast 0.7 fs / slow 5 fs")
+    ctx = P.Context(Pr)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.step_split(y, t, hf, hs, 23.0)
+    torch.cuda.synchronize()
+    o = oracle.Oracle(Pr)
+    fast = lambda v: o.rhs(v, parts=3)
+    slow = lambda v: o.rhs(v, parts=4)
+    yr = y0.copy()
+    for H in (5.0, 5.0, 5.0, 5.0, 3.0):
+        yr = I.split_step(fast, slow, yr, H, hf)
+    assert t.item() == 23.0
+    assert close(y.cpu().numpy(), yr)
+    st = ctx.stats()
+    assert st["n_accept"] == 5 and st["n_rhs_phph"] == 5 * 4
+    assert st["n_rhs_eph"] == 4 * (8 * 4 + 5)   # 7 full + 1 cut substeps per 5 fs step; 4 + 1 in the last

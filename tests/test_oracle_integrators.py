@@ -310,3 +310,41 @@ def test_too_many_failures_raise():
     a = I.Adaptive(rhs=o.rhs, atol_vec=atol, c=I.Controls(rtol=1e-15, max_fails=1), h=5.0)
     with pytest.raises(I.StepFailure):
         a.advance(wl.y0.copy(), 0.0, 10.0)
+
+
+def test_split_step_special_cases():
+    """Operator splitting: without a slow part it is the fast RK4 substeps;
+    without a fast part it is one RK4 step of the slow part."""
+    wl, o = _coupled_problem()
+    fast = lambda v: o.rhs(v, parts=3)
+    slow = lambda v: o.rhs(v, parts=4)
+    zero = lambda v: np.zeros_like(v)
+    hs, hf = 3.0, 0.7
+    y = I.split_step(fast, zero, wl.y0.copy(), hs, hf)
+    v = wl.y0.copy()
+    for h in (0.7, 0.7, 0.7, 0.7, 0.2):
+        v = I.rk4_step(fast, v, h)
+    assert np.allclose(y, v, rtol=0, atol=1e-15)
+    y = I.split_step(zero, slow, wl.y0.copy(), hs, hf)
+    assert np.array_equal(y, I.rk4_step(slow, wl.y0.copy(), hs))
+
+
+def test_split_step_is_first_order():
+    """Lie splitting of coupled parts converges at first order in h_s (fast
+    substeps small enough that RK4's own error does not show)."""
+    wl, o = _coupled_problem()
+    fast = lambda v: o.rhs(v, parts=3)
+    slow = lambda v: o.rhs(v, parts=4)
+    full = lambda v: o.rhs(v, parts=7)
+    T = 40.0
+    yref = wl.y0.copy()
+    for _ in range(3200):
+        yref = I.rk4_step(full, yref, T / 3200)
+    errs = []
+    for m in (8, 16, 32):
+        y = wl.y0.copy()
+        for _ in range(m):
+            y = I.split_step(fast, slow, y, T / m, T / m / 32)
+        errs.append(np.linalg.norm(y - yref))
+    p = np.log2(errs[1] / errs[2])
+    assert 0.8 < p < 1.3, errs
