@@ -60,16 +60,25 @@ enum {
 
 enum { RTBTE_FP64 = 0, RTBTE_MIXED = 1 };
 /* Weight storage of RTBTE_MIXED (Options.mixed_weights).  Every weight is
-   stored relative to the FP32 scale of its block of 512 consecutive channels
-   (the block's largest weight maps to 2^15):
-     RTBTE_W_F16X     FP16 with an 11-bit significand tail kept in bits of the
-                      8-byte index word that 24-bit state positions leave free:
-                      22 significant bits, relative rounding <= 2^-22 (default);
-     RTBTE_W_F16      FP16 only: relative rounding <= 2^-11;
-     RTBTE_W_BF16_EPH BF16 for the e-ph and ph-e weights (<= 2^-8), FP16 for
-                      the ph-ph weights (<= 2^-11).
-   The channel stream is 10 bytes per channel in all three. */
-enum { RTBTE_W_F16X = 0, RTBTE_W_F16 = 1, RTBTE_W_BF16_EPH = 2 };
+   stored relative to the FP32 scale of its block of 512 consecutive channels.
+     RTBTE_W_PACK8    8 bytes per channel: both partner positions (P bits each,
+                      relative to the instance; P = bits of the largest
+                      instance's state count), the row tag, the emission bit
+                      and the weight as a small float (6 exponent bits, M =
+                      min(53 - 2P, 23) mantissa bits; relative rounding
+                      <= 2^-(M+1), e.g. 2^-20 for 115 200 states) in one
+                      64-bit word.
+                      Needs P <= 20 (instances of at most 2^20 states).
+     RTBTE_W_F16X     10 bytes: 8-byte index word (24-bit positions) and an
+                      FP16 head whose 11-bit significand tail sits in the index
+                      word: 22 significant bits, relative rounding <= 2^-22;
+     RTBTE_W_F16      10 bytes, FP16 only: relative rounding <= 2^-11;
+     RTBTE_W_BF16_EPH 10 bytes, BF16 for the e-ph and ph-e weights (<= 2^-8),
+                      FP16 for the ph-ph weights (<= 2^-11);
+     RTBTE_W_AUTO     RTBTE_W_PACK8 when its mantissa has at least 12 bits
+                      (instances of at most 2^20 states), else RTBTE_W_F16X.
+   rtbte_get_weight_format reports the format chosen and its rounding. */
+enum { RTBTE_W_AUTO = 0, RTBTE_W_PACK8 = 1, RTBTE_W_F16X = 2, RTBTE_W_F16 = 3, RTBTE_W_BF16_EPH = 4 };
 
 typedef struct rtbte_ctx rtbte_ctx;
 
@@ -124,8 +133,8 @@ typedef struct {
                               FP32 sums added in FP64; the state, the stages,
                               the WRMS norm and the step control stay FP64.  RTBTE_MIXED
                               holds at most 2^24 states per context (RTBTE_E_INVAL beyond) */
-  int32_t mixed_weights;   /* RTBTE_MIXED only: RTBTE_W_F16X (default), RTBTE_W_F16 or
-                              RTBTE_W_BF16_EPH                                             */
+  int32_t mixed_weights;   /* RTBTE_MIXED only: RTBTE_W_AUTO (default), RTBTE_W_PACK8,
+                              RTBTE_W_F16X, RTBTE_W_F16 or RTBTE_W_BF16_EPH               */
   int32_t device;          /* HIP device ordinal                                           */
   /* ERK error test (Eq. (wrms_weights)): w_i = 1/(rtol |y_i| + atol_i),
      atol_i = atol_el on electron components and atol_ph on phonon components */
@@ -243,6 +252,12 @@ int rtbte_get_stats(const rtbte_ctx *ctx, int32_t inst, rtbte_stats *out);
 /* Launch shape in use: electron and phonon rows per group, channels per item. */
 int rtbte_get_tuning(const rtbte_ctx *ctx, int32_t *group_rows_el, int32_t *group_rows_ph,
                      int64_t *item_channels);
+/* Weight storage in use (RTBTE_MIXED; FP64 contexts report format -1, 16
+ * bytes and 0): the RTBTE_W_* format, bytes per stored channel, and the
+ * bound on the relative rounding of a stored weight (before the FP32
+ * product with its block scale). */
+int rtbte_get_weight_format(const rtbte_ctx *ctx, int32_t *format, int32_t *bytes_per_channel,
+                            double *weight_rounding);
 /* Where the shape came from: *source = 0 given or default, 1 tuned at create
  * (then *rhs_ms is the measured time of one right-hand side), 2 tune cache. */
 int rtbte_get_tuning_source(const rtbte_ctx *ctx, int32_t *source, double *rhs_ms);

@@ -113,6 +113,8 @@ struct rtbte_ctx {
   double* partial_items = nullptr;
   // mixed precision
   bool mixed = false;
+  int wfmt = -1;                  // weight format in use (RTBTE_W_*), -1 in FP64
+  int pack_p = 0, pack_m = 0;     // RTBTE_W_PACK8: position and mantissa bits
   int2* mix_idx = nullptr;
   uint16_t* mix_wq = nullptr;
   float* mix_scale = nullptr;
@@ -213,7 +215,7 @@ void rtbte_default_options(rtbte_options* o) {
   o->group_rows_el = 0;
   o->group_rows_ph = 0;
   o->item_channels = 0;
-  o->mixed_weights = RTBTE_W_F16X;
+  o->mixed_weights = RTBTE_W_AUTO;
   o->tune = 0;
   o->tune_cache = nullptr;
 }
@@ -419,8 +421,8 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   else rtbte_default_options(&o);
   if (o.precision != RTBTE_FP64 && o.precision != RTBTE_MIXED)
     return fail(nullptr, RTBTE_E_INVAL, "precision must be RTBTE_FP64 or RTBTE_MIXED");
-  if (o.mixed_weights < RTBTE_W_F16X || o.mixed_weights > RTBTE_W_BF16_EPH)
-    return fail(nullptr, RTBTE_E_INVAL, "mixed_weights must be RTBTE_W_F16X, RTBTE_W_F16 or RTBTE_W_BF16_EPH");
+  if (o.mixed_weights < RTBTE_W_AUTO || o.mixed_weights > RTBTE_W_BF16_EPH)
+    return fail(nullptr, RTBTE_E_INVAL, "mixed_weights must be one of RTBTE_W_AUTO .. RTBTE_W_BF16_EPH");
   if (o.group_rows_el == 0) o.group_rows_el = 8;
   if (o.group_rows_ph == 0) o.group_rows_ph = 16;
   if (!valid_group_rows(o.group_rows_el) || !valid_group_rows(o.group_rows_ph))
@@ -457,10 +459,28 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     free_ctx(c);
     return fail(nullptr, RTBTE_E_INVAL, "state vector too long (%lld > %d)", (long long)off, kPosMask);
   }
-  if (o.precision == RTBTE_MIXED && c->ny > (int64_t)kMixPosMask + 1) {
-    free_ctx(c);
-    return fail(nullptr, RTBTE_E_INVAL, "RTBTE_MIXED holds at most %d states (%lld given)", kMixPosMask + 1,
-                (long long)off);
+  if (o.precision == RTBTE_MIXED) {
+    // weight format: the packed 8-byte words need P-bit positions relative to
+    // the instance with P <= 20 (mantissa M = min(53 - 2P, 23) >= 13 bits)
+    int64_t big = 1;
+    for (int i = 0; i < n_inst; ++i) big = std::max<int64_t>(big, (int64_t)problems[i].n_el + problems[i].n_ph);
+    int P = 1;
+    while (((int64_t)1 << P) < big) ++P;
+    int w = o.mixed_weights;
+    if (w == RTBTE_W_AUTO) w = P <= 20 ? RTBTE_W_PACK8 : RTBTE_W_F16X;
+    if (w == RTBTE_W_PACK8 && P > 20) {
+      free_ctx(c);
+      return fail(nullptr, RTBTE_E_INVAL, "RTBTE_W_PACK8 needs instances of at most 2^20 states (%lld given)",
+                  (long long)big);
+    }
+    if (w != RTBTE_W_PACK8 && c->ny > (int64_t)kMixPosMask + 1) {
+      free_ctx(c);
+      return fail(nullptr, RTBTE_E_INVAL, "the 10-byte mixed formats hold at most %d states (%lld given)",
+                  kMixPosMask + 1, (long long)off);
+    }
+    c->wfmt = w;
+    c->pack_p = P;
+    c->pack_m = std::min(53 - 2 * P, 23);   // at most FP32's 23 mantissa bits; spare high bits stay 0
   }
   c->counts.assign(3 * (size_t)n_inst, 0);
 
@@ -653,19 +673,24 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   if (e == hipSuccess) e = upload(&c->row_group, rgroup.data(), rgroup.size());
   c->groups_h = std::move(groups);
   if (e == hipSuccess) e = build_items(c, o.item_channels);
+  if (e == hipSuccess) e = upload(&c->info_d, c->info.data(), c->info.size());
   if (e == hipSuccess && o.precision == RTBTE_MIXED) {
-    // 16-bit weights with per-block FP32 scales; the FP64 channels are freed
+    // compact weights with per-block FP32 scales; the FP64 channels are freed
+    const bool pack = c->wfmt == RTBTE_W_PACK8;
     const int64_t nblk = (c->n_ch + kMixBlock - 1) / kMixBlock;
     c->mix_scale = dalloc<float>((size_t)std::max<int64_t>(nblk, 1), &e);
     if (e == hipSuccess) c->mix_idx = dalloc<int2>((size_t)c->n_ch + 4, &e);
-    if (e == hipSuccess) c->mix_wq = dalloc<uint16_t>((size_t)c->n_ch + 8, &e);
+    if (e == hipSuccess && !pack) c->mix_wq = dalloc<uint16_t>((size_t)c->n_ch + 8, &e);
     if (e == hipSuccess) c->popf = dalloc<float>((size_t)c->ny, &e);
     if (e == hipSuccess) e = hipMemset(c->mix_idx, 0, ((size_t)c->n_ch + 4) * sizeof(int2));
-    if (e == hipSuccess) e = hipMemset(c->mix_wq, 0, ((size_t)c->n_ch + 8) * sizeof(uint16_t));
-    if (e == hipSuccess) e = launch_mix_scales(c->ch, c->n_ch, c->mix_scale, 0);
-    if (e == hipSuccess)
-      e = launch_mix_convert(c->ch, c->n_ch, c->groups, c->n_groups, c->mix_scale, o.mixed_weights,
-                             c->mix_idx, c->mix_wq, 0);
+    if (e == hipSuccess && !pack) e = hipMemset(c->mix_wq, 0, ((size_t)c->n_ch + 8) * sizeof(uint16_t));
+    if (e == hipSuccess) e = launch_mix_scales(c->ch, c->n_ch, pack ? 1.0f : 0x1p-15f, c->mix_scale, 0);
+    if (e == hipSuccess && pack)
+      e = launch_mix_pack8(c->ch, c->n_ch, c->groups, c->n_groups, c->info_d, c->mix_scale, c->pack_p,
+                           c->pack_m, c->mix_idx, 0);
+    if (e == hipSuccess && !pack)
+      e = launch_mix_convert(c->ch, c->n_ch, c->groups, c->n_groups, c->mix_scale, c->wfmt, c->mix_idx,
+                             c->mix_wq, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) {
       e = hipFree(c->ch);
@@ -679,7 +704,6 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
       for (int64_t j = 0; j < (int64_t)c->info[i].n_el + c->info[i].n_ph; ++j) ri[c->info[i].off + j] = i;
     e = upload(&c->row_inst, ri.data(), ri.size());
   }
-  if (e == hipSuccess) e = upload(&c->info_d, c->info.data(), c->info.size());
   // integrator state and work vectors
   int64_t maxrows = 1;
   for (auto& in : c->info) maxrows = std::max<int64_t>(maxrows, (int64_t)in.n_el + in.n_ph);
@@ -784,6 +808,24 @@ extern "C" int rtbte_get_tuning_source(const rtbte_ctx* c, int32_t* source, doub
 
 extern "C" int64_t rtbte_graph_launches(const rtbte_ctx* c) { return c ? c->graph_launches : -1; }
 
+extern "C" int rtbte_get_weight_format(const rtbte_ctx* c, int32_t* format, int32_t* bytes_per_channel,
+                                       double* weight_rounding) {
+  if (!c) return RTBTE_E_INVAL;
+  int32_t f = c->mixed ? c->wfmt : -1, b = 16;
+  double u = 0.0;
+  if (c->mixed) {
+    b = f == RTBTE_W_PACK8 ? 8 : 10;
+    u = f == RTBTE_W_PACK8 ? std::ldexp(1.0, -(c->pack_m + 1))
+        : f == RTBTE_W_F16X ? std::ldexp(1.0, -22)
+        : f == RTBTE_W_F16  ? std::ldexp(1.0, -11)
+                            : std::ldexp(1.0, -8);
+  }
+  if (format) *format = f;
+  if (bytes_per_channel) *bytes_per_channel = b;
+  if (weight_rounding) *weight_rounding = u;
+  return RTBTE_OK;
+}
+
 // ------------------------------------------------------------ right-hand side
 namespace {
 
@@ -799,7 +841,8 @@ double launch_bytes(const rtbte_ctx* c, int parts) {
   const double tables = (double)sizeof(Group) * (double)c->n_groups +
                         (double)(sizeof(Item) + 4 + 8 * kMaxGroupRows) * (double)c->n_items;
   if (c->mixed)
-    return 10.0 * (double)ch + 4.0 * (double)ch / kMixBlock + 4.0 * (double)c->ny + tables;
+    return (c->wfmt == RTBTE_W_PACK8 ? 8.0 : 10.0) * (double)ch + 4.0 * (double)ch / kMixBlock +
+           4.0 * (double)c->ny + tables;
   return 16.0 * (double)ch + 8.0 * (double)c->ny + tables;
 }
 
@@ -844,7 +887,10 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
     m.order = c->order;
     m.n_items = c->n_items;
     m.parts = parts;
-    m.wfmt = c->opt.mixed_weights;
+    m.wfmt = c->wfmt;
+    m.pack_p = c->pack_p;
+    m.pack_m = c->pack_m;
+    m.info = c->info_d;
     m.partial = c->partial_items;
     m.st = st;
   }

@@ -112,12 +112,17 @@ struct FinishArgs {
 hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s);
 hipError_t launch_finish_rows(const FinishArgs& f, bool stage, hipStream_t s);
 
-// Mixed precision: channel indices (8 B), weights as 16-bit floats relative
-// to one FP32 scale per block of kMixBlock consecutive channels, populations
-// as FP32 pairs.  Index word: x = pos0 (bits 0..23) | tag (24..27) | tail
-// bits 0..3 (28..31); y = pos1 (0..23) | tail bits 4..10 (24..30) | em (31).
-// The 11-bit tail extends an FP16 weight's significand (weight format
-// RTBTE_W_F16X); it is zero in the other formats.
+// Mixed precision: weights relative to one FP32 scale per block of kMixBlock
+// consecutive channels, populations as 4-byte codes.
+// 10-byte formats: index word x = pos0 (bits 0..23) | tag (24..27) | tail
+// bits 0..3 (28..31); y = pos1 (0..23) | tail bits 4..10 (24..30) | em (31),
+// plus a 16-bit weight head; the 11-bit tail extends an FP16 weight's
+// significand (RTBTE_W_F16X), it is zero in the other 10-byte formats.
+// 8-byte format (RTBTE_W_PACK8), P-bit positions relative to the instance:
+// x = pos0 (0..P-1) | tag (P..P+3) | weight bits 0..27-P (P+4..31);
+// y = pos1 (0..P-1) | weight bits 28-P.. (P..30) | em (31); the weight is a
+// small float of 6 exponent bits over M = min(53 - 2P, 23) mantissa bits
+// (the field's spare high bits are zero).
 constexpr int kMixBlock = 512;
 constexpr int32_t kMixPosMask = 0x00ffffff;
 constexpr int32_t kMixTagShift = 24;
@@ -132,7 +137,9 @@ struct MixArgs {
   const int32_t* order;
   int64_t n_items;
   int32_t parts;
-  int32_t wfmt;             // RTBTE_W_* weight format
+  int32_t wfmt;             // RTBTE_W_* weight format (never RTBTE_W_AUTO here)
+  int32_t pack_p, pack_m;   // RTBTE_W_PACK8: position bits P, mantissa bits M
+  const InstInfo* info;     // RTBTE_W_PACK8: instance offsets
   double* partial;
   const InstState* st;
 };
@@ -141,9 +148,12 @@ hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s);
 hipError_t launch_popf(float* pop, const double* z, const int32_t* row_group, const Group* groups,
                        int64_t n, hipStream_t s);
 // create time: per-block scales, then the 16-bit weights and packed indices
-hipError_t launch_mix_scales(const Channel* ch, int64_t n_ch, float* scale, hipStream_t s);
+hipError_t launch_mix_scales(const Channel* ch, int64_t n_ch, float headroom, float* scale, hipStream_t s);
 hipError_t launch_mix_convert(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
                               const float* scale, int wfmt, int2* idx, uint16_t* wq, hipStream_t s);
+hipError_t launch_mix_pack8(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                            const InstInfo* info, const float* scale, int p_bits, int m_bits, int2* words,
+                            hipStream_t s);
 hipError_t launch_wrms(const double* v, const double* y, const InstInfo* info, const InstState* st,
                        double* partial, int n_inst, int nchunk, Ctl c, hipStream_t s);
 hipError_t launch_control(InstState* st, const double* partial, const InstInfo* info, int n_inst,

@@ -16,6 +16,8 @@
 // so long groups never straggle at the end of the grid.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace rtbte {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -296,36 +298,54 @@ __device__ __forceinline__ float term_f(bool em, float w, float v0, float v1, fl
   }
 }
 
-// One channel of the mixed stream: decode the weight (head and tail, or BF16),
-// form w * factor in FP32 and add it to its row's compensated lane slot.
-template <int KIND>
+// State position of a channel's partner word: 24 bits in the 10-byte
+// formats; P bits relative to the instance's offset `off` when packed.
+template <bool PACK>
+__device__ __forceinline__ uint32_t mix_pos(uint32_t v, uint32_t pmask, uint32_t off) {
+  return PACK ? (v & pmask) + off : v & (uint32_t)kMixPosMask;
+}
+
+// One channel of the mixed stream: decode the weight (packed small float;
+// FP16 head and tail; or BF16), form w * factor in FP32 and add it to its
+// row's compensated lane slot.
+template <int KIND, bool PACK>
 __device__ __forceinline__ void chan_mixed(MixAcc& acc, const MixArgs& a, uint32_t ix, uint32_t iy,
                                            uint32_t head, float sc, float g0, float g1, const float2* rowv) {
-  const int tag = (ix >> kMixTagShift) & 15;
+  int tag;
   float w;
-  if (KIND != K_PP && a.wfmt == RTBTE_W_BF16_EPH) {
-    w = bf16_to_f(head);
+  if constexpr (PACK) {
+    const int P = a.pack_p, M = a.pack_m;
+    tag = (ix >> P) & 15;
+    const uint32_t wb = (ix >> (P + 4)) | (((iy & 0x7fffffffu) >> P) << (28 - P));
+    const uint32_t E = wb >> M, m = wb & ((1u << M) - 1u);
+    w = E ? __uint_as_float(((E + 64u) << 23) | (m << (23 - M))) : 0.0f;
   } else {
-    // the tail fills FP32 significand bits 2..12, below the head's 10
-    const uint32_t tail = (ix >> 28) | ((iy >> 20) & 0x7f0u);
-    w = __uint_as_float(__float_as_uint(f16_to_f(head)) | (tail << 2));
+    tag = (ix >> kMixTagShift) & 15;
+    if (KIND != K_PP && a.wfmt == RTBTE_W_BF16_EPH) {
+      w = bf16_to_f(head);
+    } else {
+      // the tail fills FP32 significand bits 2..12, below the head's 10
+      const uint32_t tail = (ix >> 28) | ((iy >> 20) & 0x7f0u);
+      w = __uint_as_float(__float_as_uint(f16_to_f(head)) | (tail << 2));
+    }
   }
   acc.add(tag, term_f<KIND>((int32_t)iy < 0, w * sc, g0, g1, rowv[tag]));
 }
 
 // Channels [s, e) of one kind.  The stream is read as channel pairs (16 B of
-// index words and 4 B of weight heads per pair), lanes on consecutive pairs,
+// words, plus 4 B of weight heads in the 10-byte formats), lanes on consecutive pairs,
 // kMixPairs pairs 64 apart per lane per batch, so every load instruction
 // reads whole contiguous lines.  Two-stage pipeline as in the FP64 kernel:
 // the gathers of batch k are issued before the stream loads of batch k+1.
 // A batch (at most 512 channels) spans at most two 512-channel scale blocks,
 // whose scales are read once per batch with scalar loads.
 constexpr int kMixPairs = MIX_PAIRS;
-template <int KIND>
+template <int KIND, bool PACK>
 __device__ __forceinline__ void seg_sum_mixed(MixAcc& acc, const MixArgs& a, int64_t s, int64_t e, int lane,
-                                              const float2* rowv) {
+                                              const float2* rowv, uint32_t off) {
   if (s >= e) return;
   constexpr int NP = kMixPairs;
+  const uint32_t pmask = PACK ? (1u << a.pack_p) - 1u : 0u;
   const v4i* idx2 = reinterpret_cast<const v4i*>(a.idx);
   const uint32_t* w2 = reinterpret_cast<const uint32_t*>(a.wq);
   const int64_t p_end = (e + 1) / 2;          // pairs [s / 2, p_end)
@@ -337,16 +357,19 @@ __device__ __forceinline__ void seg_sum_mixed(MixAcc& acc, const MixArgs& a, int
     const int64_t q = pb + lane + 64 * j;
     c[j] = v4i{0, 0, 0, 0};
     h[j] = 0;
-    if (q < p_end) { c[j] = __builtin_nontemporal_load(idx2 + q); h[j] = __builtin_nontemporal_load(w2 + q); }
+    if (q < p_end) {
+      c[j] = __builtin_nontemporal_load(idx2 + q);
+      if (!PACK) h[j] = __builtin_nontemporal_load(w2 + q);
+    }
   }
   for (;;) {
     float g0[2 * NP], g1[2 * NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-      g0[2 * j] = a.pop[(uint32_t)c[j].x & kMixPosMask];
-      g1[2 * j] = a.pop[(uint32_t)c[j].y & kMixPosMask];
-      g0[2 * j + 1] = a.pop[(uint32_t)c[j].z & kMixPosMask];
-      g1[2 * j + 1] = a.pop[(uint32_t)c[j].w & kMixPosMask];
+      g0[2 * j] = a.pop[mix_pos<PACK>((uint32_t)c[j].x, pmask, off)];
+      g1[2 * j] = a.pop[mix_pos<PACK>((uint32_t)c[j].y, pmask, off)];
+      g0[2 * j + 1] = a.pop[mix_pos<PACK>((uint32_t)c[j].z, pmask, off)];
+      g1[2 * j + 1] = a.pop[mix_pos<PACK>((uint32_t)c[j].w, pmask, off)];
     }
     const int64_t blk = __builtin_amdgcn_readfirstlane((int)(pb / (kMixBlock / 2)));
     const float s_lo = a.scale[blk];
@@ -364,7 +387,10 @@ __device__ __forceinline__ void seg_sum_mixed(MixAcc& acc, const MixArgs& a, int
 #pragma unroll
       for (int j = 0; j < NP; ++j) {
         const int64_t q = nb + lane + 64 * j;
-        if (q < p_end) { n[j] = __builtin_nontemporal_load(idx2 + q); m[j] = __builtin_nontemporal_load(w2 + q); }
+        if (q < p_end) {
+          n[j] = __builtin_nontemporal_load(idx2 + q);
+          if (!PACK) m[j] = __builtin_nontemporal_load(w2 + q);
+        }
       }
     }
 #pragma unroll
@@ -372,9 +398,10 @@ __device__ __forceinline__ void seg_sum_mixed(MixAcc& acc, const MixArgs& a, int
       const int64_t q = pb + lane + 64 * j;
       const float sc = q / (kMixBlock / 2) == blk ? s_lo : s_hi;
       const int64_t ca = 2 * q;
-      if (ca >= s && ca < e) chan_mixed<KIND>(acc, a, c[j].x, c[j].y, h[j] & 0xffffu, sc, g0[2 * j], g1[2 * j], rowv);
+      if (ca >= s && ca < e)
+        chan_mixed<KIND, PACK>(acc, a, c[j].x, c[j].y, h[j] & 0xffffu, sc, g0[2 * j], g1[2 * j], rowv);
       if (ca + 1 >= s && ca + 1 < e)
-        chan_mixed<KIND>(acc, a, c[j].z, c[j].w, h[j] >> 16, sc, g0[2 * j + 1], g1[2 * j + 1], rowv);
+        chan_mixed<KIND, PACK>(acc, a, c[j].z, c[j].w, h[j] >> 16, sc, g0[2 * j + 1], g1[2 * j + 1], rowv);
     }
     if (!more) break;
 #pragma unroll
@@ -386,7 +413,7 @@ __device__ __forceinline__ void seg_sum_mixed(MixAcc& acc, const MixArgs& a, int
   }
 }
 
-template <int G>
+template <int G, bool PACK>
 __global__ __launch_bounds__(64) void k_items_mixed(MixArgs a) {
   __shared__ float2 acc_lds[G][64];
   __shared__ float2 rowv[kMaxGroupRows];
@@ -411,12 +438,13 @@ __global__ __launch_bounds__(64) void k_items_mixed(MixArgs a) {
   __syncthreads();
   MixAcc acc{&acc_lds[0][lane]};
   if (active) {
+    const uint32_t off = PACK ? (uint32_t)a.info[g.inst].off : 0u;
     if (!g.phonon) {
-      if (a.parts & 1) seg_sum_mixed<K_EPH>(acc, a, item.lo, item.hi, lane, rowv);
+      if (a.parts & 1) seg_sum_mixed<K_EPH, PACK>(acc, a, item.lo, item.hi, lane, rowv, off);
     } else {
       const int64_t m = g.split;
-      if (a.parts & 2) seg_sum_mixed<K_PHE>(acc, a, item.lo, item.hi < m ? item.hi : m, lane, rowv);
-      if (a.parts & 4) seg_sum_mixed<K_PP>(acc, a, item.lo > m ? item.lo : m, item.hi, lane, rowv);
+      if (a.parts & 2) seg_sum_mixed<K_PHE, PACK>(acc, a, item.lo, item.hi < m ? item.hi : m, lane, rowv, off);
+      if (a.parts & 4) seg_sum_mixed<K_PP, PACK>(acc, a, item.lo > m ? item.lo : m, item.hi, lane, rowv, off);
     }
   }
   __syncthreads();
@@ -430,16 +458,26 @@ __global__ __launch_bounds__(64) void k_items_mixed(MixArgs a) {
   }
 }
 
-hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s) {
+template <bool PACK>
+hipError_t launch_items_mixed_fmt(const MixArgs& a, int slots, hipStream_t s) {
   const int64_t nb = a.n_items;
-  if (nb == 0) return hipSuccess;
   switch (slots) {
-    case 1: hipLaunchKernelGGL(k_items_mixed<1>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_items_mixed<8>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 16: hipLaunchKernelGGL(k_items_mixed<16>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_items_mixed<1, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_items_mixed<8, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_items_mixed<16, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s) {
+  if (a.n_items == 0) return hipSuccess;
+  if (a.wfmt == RTBTE_W_PACK8) {
+    if (!a.info || a.pack_p < 1 || a.pack_p > 20 || a.pack_m != std::min(53 - 2 * a.pack_p, 23))
+      return hipErrorInvalidValue;
+    return launch_items_mixed_fmt<true>(a, slots, s);
+  }
+  return launch_items_mixed_fmt<false>(a, slots, s);
 }
 
 // One FP32 word per state, coded as described above for the mixed gathers.
@@ -464,11 +502,13 @@ hipError_t launch_popf(float* pop, const double* z, const int32_t* row_group, co
   return hipGetLastError();
 }
 
-// Scale of each 512-channel block: its largest weight times 2^-15 (2^-15 if
-// all are 0), so stored values lie in [0, 2^15].  The 2^15 headroom keeps FP16
-// values of small weights out of FP16's subnormal range down to 2^-29 of the
-// block's largest weight; a power of two changes no rounding.
-__global__ __launch_bounds__(256) void k_mix_scales(const Channel* ch, int64_t n_ch, float* scale) {
+// Scale of each 512-channel block: its largest weight (rounded up to FP32)
+// times `headroom` (a power of two; `headroom` alone if all are 0).  The
+// 16-bit formats use 2^-15, so stored values lie in [0, 2^15] and FP16 values
+// of small weights stay out of FP16's subnormal range down to 2^-29 of the
+// block's largest weight; the packed 8-byte format uses 1 (values in [0, 1]).
+__global__ __launch_bounds__(256) void k_mix_scales(const Channel* ch, int64_t n_ch, float headroom,
+                                                    float* scale) {
   __shared__ double red[4];
   const int64_t b = blockIdx.x;
   double m = 0.0;
@@ -479,17 +519,17 @@ __global__ __launch_bounds__(256) void k_mix_scales(const Channel* ch, int64_t n
   __syncthreads();
   if (threadIdx.x == 0) {
     m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    // round the scale up so every scaled weight is <= 2^15
+    // round the scale up so every scaled weight is <= 1 / headroom
     float sf = (float)m;
     if ((double)sf < m) sf = nextafterf(sf, INFINITY);
-    scale[b] = (m > 0.0 ? sf : 1.0f) * 0x1p-15f;
+    scale[b] = (m > 0.0 ? sf : 1.0f) * headroom;
   }
 }
 
-hipError_t launch_mix_scales(const Channel* ch, int64_t n_ch, float* scale, hipStream_t s) {
+hipError_t launch_mix_scales(const Channel* ch, int64_t n_ch, float headroom, float* scale, hipStream_t s) {
   const int64_t nb = (n_ch + kMixBlock - 1) / kMixBlock;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mix_scales, dim3((unsigned)nb), dim3(256), 0, s, ch, n_ch, scale);
+  hipLaunchKernelGGL(k_mix_scales, dim3((unsigned)nb), dim3(256), 0, s, ch, n_ch, headroom, scale);
   return hipGetLastError();
 }
 
@@ -548,6 +588,54 @@ hipError_t launch_mix_convert(const Channel* ch, int64_t n_ch, const Group* grou
   if (n_ch == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mix_convert, dim3((unsigned)((n_ch + 255) / 256)), dim3(256), 0, s, ch, n_ch, groups,
                      n_groups, scale, wfmt, idx, wq);
+  return hipGetLastError();
+}
+
+// Packed 8-byte channels: weight r = w / scale in [0, 1] as a small float,
+// 6 exponent bits e (r = 2^(e - 63) (1 + m 2^-M), e >= 1; e = 0: zero, for
+// r < 2^-62) over M mantissa bits, rounded once to nearest even.
+__device__ __forceinline__ uint32_t to_pack_weight(double r, int M) {
+  if (!(r >= 0x1p-62)) return 0u;
+  const int e = ilogb(r);                                   // -62 .. 0
+  const double q = rint(ldexp(r, M - e)) - ldexp(1.0, M);   // 0 .. 2^M
+  uint32_t m = (uint32_t)q, E = (uint32_t)(e + 63);
+  if (m >= (1u << M)) { m = 0u; E += 1u; }
+  return (E << M) | m;
+}
+
+__global__ void k_mix_pack8(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                            const InstInfo* info, const float* scale, int P, int M, int2* words) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_ch) return;
+  int64_t lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (groups[mid].start <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const Group g = groups[lo];
+  const Channel x = ch[c];
+  const uint32_t off = (uint32_t)info[g.inst].off;
+  const uint32_t pmask = (1u << P) - 1u;
+  // slots between instances (weight 0, positions 0) hold zero words
+  const bool live = c >= g.start && c < g.end;
+  const uint32_t p0 = live ? (((uint32_t)x.i0 & (uint32_t)kPosMask) - off) & pmask : 0u;
+  const uint32_t p1 = live ? ((x.i1 & (uint32_t)kPosMask) - off) & pmask : 0u;
+  const uint32_t tag = live ? ((uint32_t)x.i0 >> kTagShift) & 15u : 0u;
+  const uint32_t w = live ? to_pack_weight(x.w / (double)scale[c / kMixBlock], M) : 0u;
+  const int lo_bits = 28 - P;                               // weight bits held by the first word
+  const uint32_t wx = p0 | (tag << P) | ((w & ((1u << lo_bits) - 1u)) << (P + 4));
+  const uint32_t wy = p1 | ((w >> lo_bits) << P) | (live ? (x.i1 & kEmBit) : 0u);
+  words[c] = make_int2((int)wx, (int)wy);
+}
+
+hipError_t launch_mix_pack8(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                            const InstInfo* info, const float* scale, int p_bits, int m_bits, int2* words,
+                            hipStream_t s) {
+  if (n_ch == 0) return hipSuccess;
+  if (p_bits < 1 || p_bits > 20 || m_bits != std::min(53 - 2 * p_bits, 23)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mix_pack8, dim3((unsigned)((n_ch + 255) / 256)), dim3(256), 0, s, ch, n_ch, groups,
+                     n_groups, info, scale, p_bits, m_bits, words);
   return hipGetLastError();
 }
 

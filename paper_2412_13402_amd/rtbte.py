@@ -17,8 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 OK, E_INVAL, E_NOMEM, E_HIP, E_STEP, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 PART_EPH, PART_PHE, PART_PHPH, PART_ALL = 1, 2, 4, 7
 FP64, MIXED = 0, 1
-# weight formats of MIXED (rtbte.h): FP16 + 11-bit tail, FP16, BF16 for e-ph / FP16 for ph-ph
-W_F16X, W_F16, W_BF16_EPH = 0, 1, 2
+# weight formats of MIXED (rtbte.h): automatic, packed 8-byte words, FP16 + 11-bit tail,
+# FP16, BF16 for e-ph / FP16 for ph-ph
+W_AUTO, W_PACK8, W_F16X, W_F16, W_BF16_EPH = 0, 1, 2, 3, 4
 
 _STATUS = {E_INVAL: "invalid argument", E_NOMEM: "out of memory", E_HIP: "HIP error",
            E_STEP: "step failure", E_NONFINITE: "non-finite state", E_UNSUPPORTED: "unsupported"}
@@ -117,6 +118,7 @@ def load():
     L.rtbte_get_tuning_source.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.rtbte_graph_launches.argtypes = [_vp]
     L.rtbte_graph_launches.restype = i64
+    L.rtbte_get_weight_format.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.rtbte_get_state.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]
     L.rtbte_set_state.argtypes = [_vp, _vp, ctypes.c_size_t]
     L.rtbte_profile.argtypes = [_vp, i32]
@@ -260,6 +262,12 @@ class Context:
         src, ms = ctypes.c_int32(), ctypes.c_double()
         self._check(load().rtbte_get_tuning_source(self._h, ctypes.byref(src), ctypes.byref(ms)))
         return src.value, ms.value
+
+    def weight_format(self):
+        """(RTBTE_W_* format or -1 for FP64, bytes per channel, relative rounding of a stored weight)."""
+        f, b, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self._check(load().rtbte_get_weight_format(self._h, ctypes.byref(f), ctypes.byref(b), ctypes.byref(u)))
+        return f.value, b.value, u.value
 
     def graph_launches(self) -> int:
         return int(load().rtbte_graph_launches(self._h))

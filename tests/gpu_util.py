@@ -66,3 +66,9 @@ def row_subset_problem(prob, rows_el, rows_ph):
     for k in ("pp_row", "pp_a", "pp_b", "pp_v2"):
         out[k] = np.ascontiguousarray(prob[k][kp])
     return out
+
+
+def weight_u(ctx):
+    """Relative rounding of a mixed context's weights as used in its kernel:
+    the stored format's bound plus the FP32 product with the block scale."""
+    return ctx.weight_format()[2] + 2.0 ** -24

@@ -64,7 +64,7 @@ def test_binding_structs_follow_the_header():
 def test_default_options():
     from paper_2412_13402_amd import rtbte
     o = rtbte.default_options()
-    assert o.precision == rtbte.FP64 and o.mixed_weights == rtbte.W_F16X
+    assert o.precision == rtbte.FP64 and o.mixed_weights == rtbte.W_AUTO
     assert (o.rtol, o.atol_el, o.atol_ph) == (1e-6, 1e-9, 1e-12)
     assert o.use_graph == 0 and o.tune == 0 and o.steps_per_poll == 8
     assert o.max_fails == 7 and o.safety == 0.96

@@ -14,12 +14,11 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import rel_norm, say, to_dev, torch_cuda
+from tests.gpu_util import rel_norm, say, to_dev, torch_cuda, weight_u
 
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-U_F16X = 2.0 ** -21
 U_SUB = 2.0 ** -39
 
 
@@ -60,7 +59,7 @@ def test_batched_rhs_is_bitwise_alone(prec):
         if prec == "fp64":
             assert np.all(np.abs(gi - ref) <= 1e-12 * A + 1e-300), i
         else:
-            bound = (U_F16X + 24 * U32) * A + U_SUB * o.max_weight() * M
+            bound = (weight_u(multi) + 24 * U32) * A + U_SUB * o.max_weight() * M
             assert np.all(np.abs(gi - ref) <= bound + 1e-300), i
             assert rel_norm(gi, ref) <= 1e-4
 

@@ -15,13 +15,12 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import rel_norm, say, to_dev, torch_cuda
+from tests.gpu_util import rel_norm, say, to_dev, torch_cuda, weight_u
 from tests.test_gpu_rhs import random_state
 
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-U_F16X = 2.0 ** -21
 U_SUB = 2.0 ** -39
 
 
@@ -70,7 +69,7 @@ def test_mixed_rhs_full_size(full):
             torch.cuda.synchronize()
             g = out.cpu().numpy()
             ref, S, A, M, Q = o.rhs(y, parts=parts, scales=True, unweighted=True)
-            bound = (U_F16X + 24 * U32) * A + U_SUB * wmax * M
+            bound = (weight_u(ctx) + 24 * U32) * A + U_SUB * wmax * M
             assert np.all(np.isfinite(g))
             assert np.all(np.abs(g - ref) <= bound + 1e-300), \
                 f"{nm} parts {parts}: worst {np.max(np.abs(g - ref) / np.maximum(A, 1e-300)):.3e}"

@@ -1,27 +1,31 @@
-"""Mixed-precision right-hand side against the FP64 oracle: 16-bit weight
-heads with per-512-channel FP32 scales, FP32 populations formed in FP64,
-compensated FP32 lane sums added in FP64.
+"""Mixed-precision right-hand side against the FP64 oracle: compact weights
+with per-512-channel FP32 scales, 4-byte population codes formed in FP64,
+FP32 factors and compensated FP32 lane sums added in FP64.
 
 Bounds: each row obeys the a priori bound
     |err_i| <= (u_w + 24 u_32) A_i + 2^-39 w_max M_i,
 with u_32 = 2^-24, A_i = sum |W| (|gain| + |loss|) and M_i = sum (|gain| +
 |loss|) over the row's channels, w_max the largest weight, and u_w the weight
-format's relative rounding: 2^-21 for the default FP16 head + 11-bit tail
-(22 significant bits, rounded once: 2^-22, plus the FP32 product with the
-scale), 2^-11 for FP16 alone, 2^-8 for BF16 (e-ph and ph-e weights in the
-BF16 format).  The u_32 count: each of the three occupation factors of a
-term comes back from its 4-byte code within 4 u_32 (electrons: the smaller
-of f and 1 - f rounded, its last bit replaced by the choice, the other one
-formed in FP32; phonons: N rounded, N + 1 formed in FP32), so gain and loss
-each carry <= 12 u_32 + 2 u_32 (two products), the difference, the product
-with the weight and the compensated lane sum add 3 u_32: 17 u_32 of A_i,
-bounded here by 24 u_32.  The states tested are physical (0 <= f <= 1,
-N >= 0), which these factor bounds assume.  The last term covers FP16 underflow: a block's largest weight
-is stored as 2^15, so a weight below 2^-29 of it is a subnormal FP16 value
-whose rounding error is at most 2^-25 * 2^-15 of the block scale.
+format's relative rounding plus 2^-24 for the FP32 product with the block
+scale: 2^-(M+1) for the packed 8-byte words (M mantissa bits; 2^-20 for the
+medium2d test grid), 2^-22 for the FP16 head + 11-bit tail, 2^-11 for FP16
+alone, 2^-8 for BF16 (e-ph and ph-e weights in the BF16 format); the
+context reports its own.  The u_32 count: each of the three occupation
+factors of a term comes back from its 4-byte code within 4 u_32 (electrons:
+the smaller of f and 1 - f rounded, its last bit replaced by the choice, the
+other one formed in FP32; phonons: N rounded, N + 1 formed in FP32), so gain
+and loss each carry <= 12 u_32 + 2 u_32 (two products), the difference, the
+product with the weight and the compensated lane sum add 3 u_32: 17 u_32 of
+A_i, bounded here by 24 u_32.  The states tested are physical (0 <= f <= 1,
+N >= 0), which these factor bounds assume.  The last term covers weights
+stored as zero or as subnormal values: below 2^-62 of the block's largest
+weight in the packed words, or FP16 subnormals (the block's largest weight
+is stored as 2^15 there, so a weight below 2^-29 of it rounds with an error
+of at most 2^-25 * 2^-15 of the block scale).
 
-Normwise: the default format must give <= 1e-4 relative on every workload.
-FP16 alone and BF16 are reported only: their rounding (2^-11, 2^-8 per weight)
+Normwise: the default format (the packed words at these sizes) and the
+FP16-with-tail format must give <= 1e-4 relative on every workload.  FP16
+alone and BF16 are reported only: their rounding (2^-11, 2^-8 per weight)
 does not average below 1e-4 on rows whose gain and loss nearly cancel (on the
 graphene-like workload FP16 alone gives about 1.1e-4 on the full right-hand
 side and 2.4e-4 on the ph-ph part).
@@ -38,7 +42,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import rel_norm, say, to_dev, torch_cuda
+from tests.gpu_util import rel_norm, say, to_dev, torch_cuda, weight_u
 from tests.test_gpu_rhs import medium2d, random_state
 
 pytestmark = pytest.mark.gpu
@@ -46,7 +50,6 @@ pytestmark = pytest.mark.gpu
 U32 = 2.0 ** -24
 U_BF16 = 2.0 ** -8
 U_F16 = 2.0 ** -11
-U_F16X = 2.0 ** -21
 U_SUB = 2.0 ** -39
 
 
@@ -82,27 +85,32 @@ def test_mixed_rhs_within_bounds(name):
     say(f"[mixed] rhs {name}")
     ctx = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED)
     assert ctx.counts() == o.counts()
+    fmt, nbytes, u = ctx.weight_format()
+    assert fmt == P.rtbte.W_PACK8 and nbytes == 8 and u <= 2.0 ** -19
     for seed, y in ((0, wl.y0), (1, random_state(wl, 1))):
         for parts in (7, 3, 4, 1, 2):
             out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
             ctx.rhs(to_dev(y), out, parts)
             torch.cuda.synchronize()
-            err = check_bounds(o, y, out.cpu().numpy(), parts, U_F16X, f"{name} seed {seed} parts {parts}")
+            err = check_bounds(o, y, out.cpu().numpy(), parts, weight_u(ctx), f"{name} seed {seed} parts {parts}")
             if err is not None:
                 say(f"    seed {seed} parts {parts}: normwise {err:.2e}")
                 assert err <= 1e-4, f"{name} seed {seed} parts {parts}: {err:.3e}"
 
 
-@pytest.mark.parametrize("fmt", ["f16", "bf16_eph"])
+@pytest.mark.parametrize("fmt", ["f16x", "f16", "bf16_eph"])
 @pytest.mark.parametrize("name", ["toy2d", "medium2d"])
-def test_16bit_weight_formats_within_bound(name, fmt):
+def test_10byte_weight_formats_within_bound(name, fmt):
     torch = torch_cuda()
     import paper_2412_13402_amd as P
     wl = wl_of(name)
     o = orc(name)
-    code, uw = {"f16": (P.rtbte.W_F16, U_F16), "bf16_eph": (P.rtbte.W_BF16_EPH, U_BF16)}[fmt]
+    code = {"f16x": P.rtbte.W_F16X, "f16": P.rtbte.W_F16, "bf16_eph": P.rtbte.W_BF16_EPH}[fmt]
     say(f"[mixed] {fmt} weights {name}")
     ctx = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED, mixed_weights=code)
+    assert ctx.weight_format()[:2] == (code, 10)
+    uw = weight_u(ctx)
+    assert uw == {"f16x": 2.0 ** -22, "f16": U_F16, "bf16_eph": U_BF16}[fmt] + U32
     for seed, y in ((0, wl.y0), (2, random_state(wl, 2))):
         for parts in (7, 1, 2, 4):
             out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
@@ -110,7 +118,9 @@ def test_16bit_weight_formats_within_bound(name, fmt):
             torch.cuda.synchronize()
             err = check_bounds(o, y, out.cpu().numpy(), parts, uw, f"{name} {fmt} seed {seed} parts {parts}")
             if err is not None:
-                say(f"    seed {seed} parts {parts}: normwise {err:.2e} (reported)")
+                say(f"    seed {seed} parts {parts}: normwise {err:.2e}" + ("" if fmt == "f16x" else " (reported)"))
+                if fmt == "f16x":
+                    assert err <= 1e-4
 
 
 def test_mixed_rejects_bad_weight_format():
@@ -135,7 +145,7 @@ def test_mixed_launch_shapes(shape):
     out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
     ctx.rhs(to_dev(y), out, 7)
     torch.cuda.synchronize()
-    err = check_bounds(o, y, out.cpu().numpy(), 7, U_F16X, f"shape {shape}")
+    err = check_bounds(o, y, out.cpu().numpy(), 7, weight_u(ctx), f"shape {shape}")
     assert err is not None and err <= 1e-4
 
 

@@ -17,12 +17,11 @@ import pytest
 import oracle
 import synth
 from oracle import integrators as I
-from tests.gpu_util import rel_norm, row_subset_problem, say, to_dev, torch_cuda
+from tests.gpu_util import rel_norm, row_subset_problem, say, to_dev, torch_cuda, weight_u
 
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-U_F16X = 2.0 ** -21
 U_SUB = 2.0 ** -39
 
 
@@ -55,7 +54,7 @@ def test_si3d_24_rhs_fp64_and_mixed():
             if prec == "fp64":
                 assert np.all(np.abs(g - ref) <= 1e-12 * A + 1e-300)
             else:
-                bound = (U_F16X + 24 * U32) * A + U_SUB * o.max_weight() * M
+                bound = (weight_u(cmx) + 24 * U32) * A + U_SUB * o.max_weight() * M
                 assert np.all(np.abs(g - ref) <= bound + 1e-300)
                 assert rel_norm(g, ref) <= 1e-4
             say(f"    {prec}: normwise {rel_norm(g, ref):.2e}")
@@ -110,7 +109,7 @@ def test_si3d_full_size_sampled_rows():
             if prec == P.rtbte.FP64:
                 assert np.all(np.abs(g - ref) <= 1e-12 * A + 1e-300)
             else:
-                bound = (U_F16X + 24 * U32) * A + U_SUB * sub.max_weight() * M
+                bound = (weight_u(ctx) + 24 * U32) * A + U_SUB * sub.max_weight() * M
                 assert np.all(np.abs(g - ref) <= bound + 1e-300)
             say(f"    sampled normwise {rel_norm(g, ref):.2e}")
         del ctx
