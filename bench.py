@@ -9,7 +9,10 @@ fused stage updates, the WRMS error norm and the device-side PID control.
 
 Prints one JSON line: channels/s (the metric), the roofline of the collision
 kernel (algorithmic bytes per launch over its HIP-event-timed duration), the
-simulated ps/s, and the FP64 oracle timed on this host's cores.  A second leg
+simulated ps/s, and the FP64 oracle timed on this host's cores.  The FP64
+channels are the library's default packed 12-byte layout; the same steps
+with the plain 16-byte layout are reported beside them
+("fp64_plain_channels").  A second leg
 runs the same workload and steps in mixed precision ("mixed": its channels/s,
 simulated ps/s and their speedup over FP64, its kernel roofline, the RHS error
 against the oracle after each of its first steps, and the population error
@@ -98,6 +101,7 @@ def main():
     ap.add_argument("--err-steps", type=int, default=5, help="mixed steps with a per-step RHS error report")
     ap.add_argument("--no-errors", action="store_true", help="skip the mixed accuracy pass (profiling runs)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 leg with plain 16-byte channels")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched leg")
     ap.add_argument("--batch-t-end", type=float, default=200.0, help="simulated fs of the batched leg")
     ap.add_argument("--si3d", action="store_true",
@@ -172,6 +176,28 @@ def main():
         "create_s": create_s,
         "generate_s": gen_s,
     }
+    fmt = ctx.weight_format()
+    rec["config"]["fp64_channel_bytes"] = fmt[1]
+    rec["config"]["fp64_weight_rounding"] = fmt[2]
+
+    if not args.no_plain:
+        # the same steps with the plain 16-byte FP64 channels (two 32-bit
+        # indices and the full FP64 weight), for comparison
+        t0 = time.perf_counter()
+        ctx_p = P.Context(wl.problem_arrays(), rtol=args.rtol, atol_el=1e-9, atol_ph=1e-12,
+                          group_rows_el=args.group_rows_el, group_rows_ph=args.group_rows_ph,
+                          item_channels=args.item_channels, fp64_layout=P.rtbte.F64_PLAIN)
+        torch.cuda.synchronize()
+        cp = time.perf_counter() - t0
+        leg_p = timed_steps(ctx_p, wl, args, C, "fp64 plain", start=leg["start"])
+        rec["fp64_plain_channels"] = {
+            "value": leg_p["value"], "unit": "channels/s", "ms_per_step": leg_p["ms_per_step"],
+            "sim_ps_per_s": leg_p["sim_ps_per_s"], "channel_bytes": 16,
+            "roofline": dict(leg_p["kernel"], traffic=measured_traffic(
+                args.workload if args.L is None else f"{args.workload}_L{args.L}", "fp64_plain")),
+            "create_s": cp,
+        }
+        del ctx_p
 
     ctx_m = None
     if not args.no_mixed:
@@ -460,7 +486,7 @@ def timed_steps(ctx, wl, args, C, label, start=None):
     kernel = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "kernel": ("k_items" if label == "fp64" else "k_items_mixed") + " (collision integrals: per-item row sums)",
+        "kernel": ("k_items_mixed" if label == "mixed" else "k_items") + " (collision integrals: per-item row sums)",
         "launches": k_n, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch,
     }
     return dict(value=evals * C / wall, ms_per_step=wall * 1e3 / args.steps, rhs_per_step=evals / args.steps,

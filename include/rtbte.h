@@ -174,7 +174,18 @@ typedef struct {
   const char *tune_cache;   /* text file of tuned shapes, one line per problem signature
                                (device, precision, sizes); read before tuning, appended
                                after.  NULL: env RTBTE_TUNE_CACHE; neither: no cache.         */
+  int32_t fp64_layout;      /* RTBTE_FP64 channel storage: RTBTE_F64_AUTO (default: packed
+                               when instances have at most 2^19 states), RTBTE_F64_PACKED
+                               (12 bytes: an 8-byte word of P-bit instance-relative
+                               positions, row tag, emission bit and high weight bits, and a
+                               4-byte word of low weight bits; the weight keeps
+                               min(80 - 2P, 52) mantissa bits, so it is exact for P <= 14
+                               and within 2^-43 relative for P <= 19; arithmetic stays
+                               FP64) or RTBTE_F64_PLAIN (16 bytes: two 32-bit indices and
+                               the FP64 weight)                                              */
 } rtbte_options;
+
+enum { RTBTE_F64_AUTO = 0, RTBTE_F64_PACKED = 1, RTBTE_F64_PLAIN = 2 };
 
 typedef struct {
   int64_t n_rhs_eph, n_rhs_phe, n_rhs_phph; /* evaluations of each part                 */
@@ -252,10 +263,11 @@ int rtbte_get_stats(const rtbte_ctx *ctx, int32_t inst, rtbte_stats *out);
 /* Launch shape in use: electron and phonon rows per group, channels per item. */
 int rtbte_get_tuning(const rtbte_ctx *ctx, int32_t *group_rows_el, int32_t *group_rows_ph,
                      int64_t *item_channels);
-/* Weight storage in use (RTBTE_MIXED; FP64 contexts report format -1, 16
- * bytes and 0): the RTBTE_W_* format, bytes per stored channel, and the
- * bound on the relative rounding of a stored weight (before the FP32
- * product with its block scale). */
+/* Channel storage in use: the RTBTE_W_* format of a mixed context (-1 for
+ * FP64 plain 16-byte channels, -2 for FP64 packed 12-byte channels), bytes
+ * per stored channel, and the bound on the relative rounding of a stored
+ * weight (mixed: before the FP32 product with its block scale; FP64 plain
+ * and FP64 packed with at most 2^14 states per instance: 0). */
 int rtbte_get_weight_format(const rtbte_ctx *ctx, int32_t *format, int32_t *bytes_per_channel,
                             double *weight_rounding);
 /* Where the shape came from: *source = 0 given or default, 1 tuned at create

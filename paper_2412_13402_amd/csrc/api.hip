@@ -113,8 +113,10 @@ struct rtbte_ctx {
   double* partial_items = nullptr;
   // mixed precision
   bool mixed = false;
-  int wfmt = -1;                  // weight format in use (RTBTE_W_*), -1 in FP64
-  int pack_p = 0, pack_m = 0;     // RTBTE_W_PACK8: position and mantissa bits
+  int wfmt = -1;                  // weight format in use (RTBTE_W_*); FP64: -1 plain, -2 packed
+  int pack_p = 0, pack_m = 0;     // packed layouts: position and mantissa bits
+  uint64_t* pk = nullptr;         // FP64 packed: 8-byte words
+  uint32_t* pkw = nullptr;        // FP64 packed: low weight words
   int2* mix_idx = nullptr;
   uint16_t* mix_wq = nullptr;
   float* mix_scale = nullptr;
@@ -218,6 +220,7 @@ void rtbte_default_options(rtbte_options* o) {
   o->mixed_weights = RTBTE_W_AUTO;
   o->tune = 0;
   o->tune_cache = nullptr;
+  o->fp64_layout = RTBTE_F64_AUTO;
 }
 
 const char* rtbte_last_error(const rtbte_ctx* ctx) {
@@ -342,7 +345,8 @@ hipError_t upload(T** d, const T* h, size_t n) {
 void free_ctx(rtbte_ctx* c) {
   if (!c) return;
   void* ps[] = {c->ch, c->groups, c->items, c->order, c->item_ptr, c->row_group, c->partial_items,
-                c->mix_idx, c->mix_wq, c->mix_scale, c->popf, c->row_inst, c->info_d, c->st, c->st_fast,
+                c->mix_idx, c->mix_wq, c->mix_scale, c->popf, c->pk, c->pkw, c->row_inst, c->info_d, c->st,
+                c->st_fast,
                 c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
                 c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
                 c->partial, c->tvec, c->summary_d};
@@ -421,6 +425,8 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   else rtbte_default_options(&o);
   if (o.precision != RTBTE_FP64 && o.precision != RTBTE_MIXED)
     return fail(nullptr, RTBTE_E_INVAL, "precision must be RTBTE_FP64 or RTBTE_MIXED");
+  if (o.fp64_layout < RTBTE_F64_AUTO || o.fp64_layout > RTBTE_F64_PLAIN)
+    return fail(nullptr, RTBTE_E_INVAL, "fp64_layout must be RTBTE_F64_AUTO, RTBTE_F64_PACKED or RTBTE_F64_PLAIN");
   if (o.mixed_weights < RTBTE_W_AUTO || o.mixed_weights > RTBTE_W_BF16_EPH)
     return fail(nullptr, RTBTE_E_INVAL, "mixed_weights must be one of RTBTE_W_AUTO .. RTBTE_W_BF16_EPH");
   if (o.group_rows_el == 0) o.group_rows_el = 8;
@@ -459,13 +465,25 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     free_ctx(c);
     return fail(nullptr, RTBTE_E_INVAL, "state vector too long (%lld > %d)", (long long)off, kPosMask);
   }
+  int64_t big = 1;   // largest instance; its positions need P bits
+  for (int i = 0; i < n_inst; ++i) big = std::max<int64_t>(big, (int64_t)problems[i].n_el + problems[i].n_ph);
+  int P = 1;
+  while (((int64_t)1 << P) < big) ++P;
+  if (o.precision == RTBTE_FP64) {
+    // packed 12-byte channels need P <= 19 (M = min(80 - 2P, 52) >= 42 mantissa bits)
+    if (o.fp64_layout == RTBTE_F64_PACKED && P > 19) {
+      free_ctx(c);
+      return fail(nullptr, RTBTE_E_INVAL, "RTBTE_F64_PACKED needs instances of at most 2^19 states (%lld given)",
+                  (long long)big);
+    }
+    const bool pk = o.fp64_layout == RTBTE_F64_PACKED || (o.fp64_layout == RTBTE_F64_AUTO && P <= 19);
+    c->wfmt = pk ? -2 : -1;
+    c->pack_p = pk ? P : 0;
+    c->pack_m = pk ? std::min(80 - 2 * P, 52) : 0;
+  }
   if (o.precision == RTBTE_MIXED) {
     // weight format: the packed 8-byte words need P-bit positions relative to
     // the instance with P <= 20 (mantissa M = min(53 - 2P, 23) >= 13 bits)
-    int64_t big = 1;
-    for (int i = 0; i < n_inst; ++i) big = std::max<int64_t>(big, (int64_t)problems[i].n_el + problems[i].n_ph);
-    int P = 1;
-    while (((int64_t)1 << P) < big) ++P;
     int w = o.mixed_weights;
     if (w == RTBTE_W_AUTO) w = P <= 20 ? RTBTE_W_PACK8 : RTBTE_W_F16X;
     if (w == RTBTE_W_PACK8 && P > 20) {
@@ -698,6 +716,20 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     }
     c->mixed = true;
   }
+  if (e == hipSuccess && c->wfmt == -2) {
+    // FP64 packed channels; the 16-byte channels are freed
+    c->pk = dalloc<uint64_t>((size_t)c->n_ch + 2, &e);
+    if (e == hipSuccess) c->pkw = dalloc<uint32_t>((size_t)c->n_ch + 4, &e);
+    if (e == hipSuccess) e = hipMemset(c->pk, 0, ((size_t)c->n_ch + 2) * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemset(c->pkw, 0, ((size_t)c->n_ch + 4) * sizeof(uint32_t));
+    if (e == hipSuccess)
+      e = launch_pack12(c->ch, c->n_ch, c->groups, c->n_groups, c->info_d, c->pack_p, c->pack_m, c->pk, c->pkw, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) {
+      e = hipFree(c->ch);
+      c->ch = nullptr;
+    }
+  }
   if (e == hipSuccess && n_inst > 1) {
     std::vector<int32_t> ri((size_t)c->ny);
     for (int i = 0; i < n_inst; ++i)
@@ -811,8 +843,8 @@ extern "C" int64_t rtbte_graph_launches(const rtbte_ctx* c) { return c ? c->grap
 extern "C" int rtbte_get_weight_format(const rtbte_ctx* c, int32_t* format, int32_t* bytes_per_channel,
                                        double* weight_rounding) {
   if (!c) return RTBTE_E_INVAL;
-  int32_t f = c->mixed ? c->wfmt : -1, b = 16;
-  double u = 0.0;
+  int32_t f = c->wfmt, b = c->wfmt == -2 ? 12 : 16;
+  double u = c->wfmt == -2 && c->pack_m < 52 ? std::ldexp(1.0, -(c->pack_m + 1)) : 0.0;
   if (c->mixed) {
     b = f == RTBTE_W_PACK8 ? 8 : 10;
     u = f == RTBTE_W_PACK8 ? std::ldexp(1.0, -(c->pack_m + 1))
@@ -830,9 +862,9 @@ extern "C" int rtbte_get_weight_format(const rtbte_ctx* c, int32_t* format, int3
 namespace {
 
 // Algorithmic bytes of one collision-kernel launch: every stored channel of
-// the selected parts once (16 B; mixed: 10 B and a 4 B scale per 512), the
-// populations once (8 B per state; mixed: 4 B), the group and item tables,
-// and the item row sums written.
+// the selected parts once (FP64: 16 B plain, 12 B packed; mixed: 8 or 10 B
+// and a 4 B scale per 512), the populations once (8 B per state; mixed: 4 B),
+// the group and item tables, and the item row sums written.
 double launch_bytes(const rtbte_ctx* c, int parts) {
   int64_t ch = 0;
   for (int i = 0; i < c->n_inst; ++i)
@@ -843,7 +875,7 @@ double launch_bytes(const rtbte_ctx* c, int parts) {
   if (c->mixed)
     return (c->wfmt == RTBTE_W_PACK8 ? 8.0 : 10.0) * (double)ch + 4.0 * (double)ch / kMixBlock +
            4.0 * (double)c->ny + tables;
-  return 16.0 * (double)ch + 8.0 * (double)c->ny + tables;
+  return (c->pk ? 12.0 : 16.0) * (double)ch + 8.0 * (double)c->ny + tables;
 }
 
 hipError_t harvest(rtbte_ctx* c) {
@@ -867,6 +899,11 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
                       bool stage, hipStream_t s) {
   RowArgs a{};
   a.ch = c->ch;
+  a.pk = c->pk;
+  a.pkw = c->pkw;
+  a.pack_p = c->pack_p;
+  a.pack_m = c->pack_m;
+  a.info = c->info_d;
   a.groups = c->groups;
   a.items = c->items;
   a.order = c->order;

@@ -75,8 +75,18 @@ struct Item {
 };
 
 // Arguments of the collision kernel (per-item row sums).
+// FP64 channels, packed (12 bytes): an 8-byte word per channel, low half
+// pos0 (bits 0..P-1) | tag (P..P+3) | weight field bits 32..59-P (P+4..31),
+// high half pos1 (0..P-1) | em (P) | weight field bits 60-P.. (P+1..31), and
+// a 4-byte word with weight field bits 0..31; positions relative to the
+// instance; the weight field is the FP64 bit pattern without its sign and its
+// 52 - M lowest mantissa bits, M = min(80 - 2P, 52) (rounded to nearest).
 struct RowArgs {
-  const Channel* ch;
+  const Channel* ch;        // 16-byte channels (nullptr when packed)
+  const uint64_t* pk;       // packed: [n_ch] 8-byte words
+  const uint32_t* pkw;      // packed: [n_ch] low weight words
+  int32_t pack_p, pack_m;   // packed: position bits P, mantissa bits M
+  const InstInfo* info;     // packed: instance offsets
   const Group* groups;
   const Item* items;
   const int32_t* order;     // [n_items] processing order (longest first)
@@ -110,6 +120,8 @@ struct FinishArgs {
 
 // Launchers (kernels.hip)
 hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s);
+hipError_t launch_pack12(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                         const InstInfo* info, int p_bits, int m_bits, uint64_t* pk, uint32_t* pkw, hipStream_t s);
 hipError_t launch_finish_rows(const FinishArgs& f, bool stage, hipStream_t s);
 
 // Mixed precision: weights relative to one FP32 scale per block of kMixBlock

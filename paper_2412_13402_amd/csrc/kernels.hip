@@ -40,9 +40,7 @@ enum { K_EPH = 0, K_PHE = 1, K_PP = 2 };
 //     G_em  = N (N_a+1)(N_b+1) - (N+1) N_a N_b
 //     G_abs = N (N_a+1) N_b    - (N+1) N_a (N_b+1)
 template <int KIND>
-__device__ __forceinline__ double term(const v4i c, double g0, double g1, double xr, double xr1) {
-  const double w = chan_w(c);
-  const bool em = (c.y < 0);
+__device__ __forceinline__ double term_w(bool em, double w, double g0, double g1, double xr, double xr1) {
   if (KIND == K_EPH) {            // xr = f_r, xr1 = 1 - f_r, g0 = f_s, g1 = N_p
     const double n1 = g1 + 1.0;
     const double gain = xr * (1.0 - g0) * (em ? n1 : g1);
@@ -58,6 +56,11 @@ __device__ __forceinline__ double term(const v4i c, double g0, double g1, double
     const double loss = xr1 * g0 * (em ? g1 : b1);
     return w * (gain - loss);
   }
+}
+
+template <int KIND>
+__device__ __forceinline__ double term(const v4i c, double g0, double g1, double xr, double xr1) {
+  return term_w<KIND>(c.y < 0, chan_w(c), g0, g1, xr, xr1);
 }
 
 // Per-lane accumulators of one wavefront: one slot per (row of the group,
@@ -125,9 +128,99 @@ __device__ __forceinline__ void seg_sum(LaneAcc<G>& acc, const Channel* __restri
   }
 }
 
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+// One packed FP64 channel: the 8-byte word (lo, hi) and the low weight word
+// wl (layout in internal.h; 32-bit operations only), the gathered partner
+// values g0, g1.
+template <int G, int KIND>
+__device__ __forceinline__ void chan_p12(LaneAcc<G>& acc, uint32_t lo, uint32_t hi, uint32_t wl, double g0,
+                                         double g1, const double* rowv, int P, int sh) {
+  const int tag = G == 1 ? 0 : (int)((lo >> P) & 15u);
+  const bool em = (hi >> P) & 1u;
+  const uint32_t wh = (lo >> (P + 4)) | ((hi >> (P + 1)) << (28 - P));   // field bits 32.. (exponent, top mantissa)
+  const uint32_t h32 = sh ? __builtin_amdgcn_alignbit(wh, wl, 32 - sh) : wh;
+  const double w = __hiloint2double((int)h32, (int)(wl << sh));
+  const double xr = rowv[tag];
+  const double xr1 = KIND == K_EPH ? 1.0 - xr : xr + 1.0;
+  acc.add(tag, term_w<KIND>(em, w, g0, g1, xr, xr1));
+}
+
+// Channels [s, e) of one kind from the packed FP64 stream, read as channel
+// pairs (16 B of words and 8 B of low weight words), lanes on consecutive
+// pairs, two pairs 64 apart per lane per batch (whole lines per load), with
+// the two-stage pipeline of seg_sum.  `off` is the instance's offset in z.
+template <int G, int KIND>
+__device__ __forceinline__ void seg_sum_p12(LaneAcc<G>& acc, const RowArgs& a, int64_t s, int64_t e, int lane,
+                                            const double* __restrict__ z, const double* rowv, uint32_t off) {
+  if (s >= e) return;
+  const v4u* A2 = reinterpret_cast<const v4u*>(a.pk);
+  const v2u* B2 = reinterpret_cast<const v2u*>(a.pkw);
+  const int P = a.pack_p, sh = 52 - a.pack_m;
+  const uint32_t pmask = (1u << P) - 1u;
+  const int64_t p_end = (e + 1) / 2;          // pairs [s / 2, p_end)
+  int64_t pb = s / 2;                          // first pair of the batch (wave-uniform)
+  v4u c[2];
+  v2u wl[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int64_t q = pb + lane + 64 * j;
+    c[j] = v4u{0u, 0u, 0u, 0u};
+    wl[j] = v2u{0u, 0u};
+    if (q < p_end) {
+      c[j] = __builtin_nontemporal_load(A2 + q);
+      wl[j] = __builtin_nontemporal_load(B2 + q);
+    }
+  }
+  for (;;) {
+    double g0[4], g1[4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      g0[2 * j] = z[(c[j].x & pmask) + off];
+      g1[2 * j] = z[(c[j].y & pmask) + off];
+      g0[2 * j + 1] = z[(c[j].z & pmask) + off];
+      g1[2 * j + 1] = z[(c[j].w & pmask) + off];
+    }
+    const int64_t nb = pb + 128;
+    const bool more = nb < p_end;
+    v4u n[2];
+    v2u m[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      n[j] = v4u{0u, 0u, 0u, 0u};
+      m[j] = v2u{0u, 0u};
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t q = nb + lane + 64 * j;
+        if (q < p_end) {
+          n[j] = __builtin_nontemporal_load(A2 + q);
+          m[j] = __builtin_nontemporal_load(B2 + q);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t ca = 2 * (pb + lane + 64 * j);
+      if (ca >= s && ca < e) chan_p12<G, KIND>(acc, c[j].x, c[j].y, wl[j].x, g0[2 * j], g1[2 * j], rowv, P, sh);
+      if (ca + 1 >= s && ca + 1 < e)
+        chan_p12<G, KIND>(acc, c[j].z, c[j].w, wl[j].y, g0[2 * j + 1], g1[2 * j + 1], rowv, P, sh);
+    }
+    if (!more) break;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      c[j] = n[j];
+      wl[j] = m[j];
+    }
+    pb = nb;
+  }
+}
+
 // One wavefront per block, so the LDS a block needs is one wavefront's
 // accumulator slots and occupancy is not capped by whole 4-wave blocks.
-template <int G>
+template <int G, bool PACK>
 __global__ __launch_bounds__(64) void k_items(RowArgs a) {
   __shared__ double acc_lds[1][G][64];
   __shared__ double rowv[1][kMaxGroupRows];
@@ -153,12 +246,24 @@ __global__ __launch_bounds__(64) void k_items(RowArgs a) {
   LaneAcc<G> acc{&acc_lds[wave][0][lane], 0.0};
   if (active) {
     const double* rv = rowv[wave];
-    if (!g.phonon) {
-      if (a.parts & 1) seg_sum<G, 64, K_EPH>(acc, a.ch, item.lo, item.hi, lane, a.z, rv);
+    const int64_t m = g.split;
+    const int64_t lo_pe = item.lo, hi_pe = item.hi < m ? item.hi : m;
+    const int64_t lo_pp = item.lo > m ? item.lo : m, hi_pp = item.hi;
+    if constexpr (PACK) {
+      const uint32_t off = (uint32_t)a.info[g.inst].off;
+      if (!g.phonon) {
+        if (a.parts & 1) seg_sum_p12<G, K_EPH>(acc, a, item.lo, item.hi, lane, a.z, rv, off);
+      } else {
+        if (a.parts & 2) seg_sum_p12<G, K_PHE>(acc, a, lo_pe, hi_pe, lane, a.z, rv, off);
+        if (a.parts & 4) seg_sum_p12<G, K_PP>(acc, a, lo_pp, hi_pp, lane, a.z, rv, off);
+      }
     } else {
-      const int64_t m = g.split;
-      if (a.parts & 2) seg_sum<G, 64, K_PHE>(acc, a.ch, item.lo, item.hi < m ? item.hi : m, lane, a.z, rv);
-      if (a.parts & 4) seg_sum<G, 64, K_PP>(acc, a.ch, item.lo > m ? item.lo : m, item.hi, lane, a.z, rv);
+      if (!g.phonon) {
+        if (a.parts & 1) seg_sum<G, 64, K_EPH>(acc, a.ch, item.lo, item.hi, lane, a.z, rv);
+      } else {
+        if (a.parts & 2) seg_sum<G, 64, K_PHE>(acc, a.ch, lo_pe, hi_pe, lane, a.z, rv);
+        if (a.parts & 4) seg_sum<G, 64, K_PP>(acc, a.ch, lo_pp, hi_pp, lane, a.z, rv);
+      }
     }
   }
   if (G == 1) {
@@ -178,15 +283,64 @@ __global__ __launch_bounds__(64) void k_items(RowArgs a) {
   }
 }
 
-hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s) {
+template <bool PACK>
+hipError_t launch_items_fmt(const RowArgs& a, int slots, hipStream_t s) {
   const int64_t nb = a.n_items;
-  if (nb == 0) return hipSuccess;
   switch (slots) {
-    case 1: hipLaunchKernelGGL(k_items<1>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_items<8>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 16: hipLaunchKernelGGL(k_items<16>, dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_items<1, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_items<8, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_items<16, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s) {
+  if (a.n_items == 0) return hipSuccess;
+  if (a.pk) {
+    if (!a.pkw || !a.info || a.pack_p < 1 || a.pack_p > 19 || a.pack_m != std::min(80 - 2 * a.pack_p, 52))
+      return hipErrorInvalidValue;
+    return launch_items_fmt<true>(a, slots, s);
+  }
+  return launch_items_fmt<false>(a, slots, s);
+}
+
+// Create time: the 16-byte FP64 channels to the packed 12-byte layout.
+__global__ void k_pack12(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                         const InstInfo* info, int P, int M, uint64_t* pk, uint32_t* pkw) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_ch) return;
+  int64_t lo = 0, hi = n_groups - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (groups[mid].start <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const Group g = groups[lo];
+  const Channel x = ch[c];
+  const bool live = c >= g.start && c < g.end;     // slots between instances stay zero
+  const uint32_t off = (uint32_t)info[g.inst].off, pmask = (1u << P) - 1u;
+  uint64_t bits = live ? (uint64_t)__double_as_longlong(x.w) & 0x7fffffffffffffffull : 0ull;
+  const int sh = 52 - M;
+  if (sh > 0) bits = (bits + ((1ull << (sh - 1)) - 1ull) + ((bits >> sh) & 1ull)) >> sh;   // nearest even
+  const uint32_t whigh = (uint32_t)(bits >> 32);   // at most min(59 - 2P, 31) bits
+  const uint32_t p0 = live ? (((uint32_t)x.i0 & (uint32_t)kPosMask) - off) & pmask : 0u;
+  const uint32_t p1 = live ? ((x.i1 & (uint32_t)kPosMask) - off) & pmask : 0u;
+  const uint32_t tag = live ? (((uint32_t)x.i0 >> kTagShift) & 15u) : 0u;
+  const uint32_t em = live ? (x.i1 >> 31) : 0u;
+  const int na = 28 - P;                             // weight bits held by the low half
+  const uint32_t w_lo = p0 | (tag << P) | ((whigh & ((1u << na) - 1u)) << (P + 4));
+  const uint32_t w_hi = p1 | (em << P) | ((whigh >> na) << (P + 1));
+  pk[c] = ((uint64_t)w_hi << 32) | w_lo;
+  pkw[c] = (uint32_t)bits;
+}
+
+hipError_t launch_pack12(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,
+                         const InstInfo* info, int p_bits, int m_bits, uint64_t* pk, uint32_t* pkw, hipStream_t s) {
+  if (n_ch == 0) return hipSuccess;
+  if (p_bits < 1 || p_bits > 19 || m_bits != std::min(80 - 2 * p_bits, 52)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pack12, dim3((unsigned)((n_ch + 255) / 256)), dim3(256), 0, s, ch, n_ch, groups, n_groups,
+                     info, p_bits, m_bits, pk, pkw);
   return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ FP64, MIXED = 0, 1
 # weight formats of MIXED (rtbte.h): automatic, packed 8-byte words, FP16 + 11-bit tail,
 # FP16, BF16 for e-ph / FP16 for ph-ph
 W_AUTO, W_PACK8, W_F16X, W_F16, W_BF16_EPH = 0, 1, 2, 3, 4
+# FP64 channel layouts (rtbte.h)
+F64_AUTO, F64_PACKED, F64_PLAIN = 0, 1, 2
 
 _STATUS = {E_INVAL: "invalid argument", E_NOMEM: "out of memory", E_HIP: "HIP error",
            E_STEP: "step failure", E_NONFINITE: "non-finite state", E_UNSUPPORTED: "unsupported"}
@@ -63,6 +65,7 @@ class Options(ctypes.Structure):
         ("steps_per_poll", ctypes.c_int32), ("group_rows_el", ctypes.c_int32),
         ("group_rows_ph", ctypes.c_int32), ("item_channels", ctypes.c_int64),
         ("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+        ("fp64_layout", ctypes.c_int32),
     ]
 
 

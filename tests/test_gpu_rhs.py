@@ -48,15 +48,19 @@ def random_state(wl, seed):
 CASES = ["toy2d", "tiny2d", "tiny3d", "lattice2d", "medium2d"]
 
 
+@pytest.mark.parametrize("layout", ["packed", "plain"])
 @pytest.mark.parametrize("name", CASES)
-def test_rhs_matches_oracle(name):
+def test_rhs_matches_oracle(name, layout):
     torch = torch_cuda()
     import paper_2412_13402_amd as P
     wl = workload(name)
     o = oracle_of(name)
-    say(f"[rhs] {name} n_y={wl.n_y} entries={len(wl.eph_row)}+{len(wl.pp_row)}")
-    ctx = P.Context(wl.problem_arrays())
+    say(f"[rhs] {name} ({layout}) n_y={wl.n_y} entries={len(wl.eph_row)}+{len(wl.pp_row)}")
+    code = P.rtbte.F64_PACKED if layout == "packed" else P.rtbte.F64_PLAIN
+    ctx = P.Context(wl.problem_arrays(), fp64_layout=code)
     assert ctx.counts() == o.counts()
+    # these grids need at most 14 position bits: packed weights are exact
+    assert ctx.weight_format() == ((-2, 12, 0.0) if layout == "packed" else (-1, 16, 0.0))
     for seed, y in ((0, wl.y0), (1, random_state(wl, 1)), (2, random_state(wl, 2))):
         yd = to_dev(y)
         for parts in (1, 2, 4, 3, 7):
@@ -190,3 +194,24 @@ def test_invalid_create_is_rejected(bad):
     with pytest.raises(P.RtbteError) as e:
         P.Context(Pr, **kw)
     assert e.value.code == P.rtbte.E_INVAL
+
+
+def test_fp64_layouts_agree_and_reject_oversize():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = workload("medium2d")
+    say("[rhs] packed vs plain FP64 channels")
+    y = random_state(wl, 9)
+    outs = []
+    for code in (P.rtbte.F64_PACKED, P.rtbte.F64_PLAIN):
+        ctx = P.Context(wl.problem_arrays(), fp64_layout=code)
+        out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+        ctx.rhs(to_dev(y), out, 7)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+    o = oracle_of("medium2d")
+    ref, S, A = o.rhs(y, parts=7, scales=True)
+    # exact weights in both; only the order of the lane sums differs
+    assert np.all(np.abs(outs[0] - outs[1]) <= 1e-14 * A + 1e-300)
+    with pytest.raises(P.RtbteError):
+        P.Context(wl.problem_arrays(), fp64_layout=7)
