@@ -221,6 +221,43 @@ int rtbte_counts(const rtbte_ctx *ctx, int32_t inst, int64_t counts[3]);
  * are device arrays of rtbte_ny() doubles and must not overlap. */
 int rtbte_rhs(rtbte_ctx *ctx, const double *y, double *ydot, int32_t parts, void *stream);
 
+/* Linearized (relaxation-time) rates of the parts in `parts` at the state y:
+ * rates[i] = -d(ydot_i)/d(y_i) with every partner population held fixed,
+ * i.e. the sum over row i's channels of W times the derivative of the
+ * channel's occupation factor (after Eq. (e-ph) and Eq. (ph-ph)) with
+ * respect to the row's own population.  With parts = RTBTE_PART_PHPH at
+ * phonons in Bose-Einstein equilibrium these are the mode-resolved
+ * three-phonon scattering rates (1/fs) the paper analyses its grids with.
+ * Same device buffers and stream as rtbte_rhs.  RTBTE_FP64 contexts only
+ * (RTBTE_E_UNSUPPORTED otherwise). */
+int rtbte_rates(rtbte_ctx *ctx, const double *y, double *rates, int32_t parts, void *stream);
+
+/* Energy-resolved averages of one instance's populations (the zone averages
+ * the paper plots beside the band structure and the phonon dispersion,
+ * Results, Fig. 1).  which = 0: carriers f binned by the band energy eps;
+ * which = 1: phonons N binned by hbar omega.  Bin k covers
+ * [e_lo + k de, e_lo + (k+1) de), de = (e_hi - e_lo) / n_bins; states outside
+ * [e_lo, e_hi) are left out.  y (and y_ref, may be NULL) are device states of
+ * rtbte_ny() doubles; out is HOST memory of 3 n_bins doubles receiving, per
+ * bin, the state count, the mean population and the mean of y - y_ref (0
+ * without y_ref).  Sums run in a fixed order (bitwise reproducible).  The call
+ * allocates a small device index, synchronizes `stream` and returns when out
+ * is written.  RTBTE_E_INVAL for a bad instance, `which`, bin count or range. */
+int rtbte_energy_average(rtbte_ctx *ctx, const double *y, const double *y_ref, int32_t inst, int32_t which,
+                         double e_lo, double e_hi, int32_t n_bins, double *out, void *stream);
+
+/* Effective temperature of each phonon branch of one instance (the branch
+ * temperatures of the paper's supplementary analysis): T_m solves
+ * sum_{j in m} hw_j N_BE(hw_j, T_m) = sum_{j in m} hw_j N_j over the branch's
+ * states with hw_j > 0 (Bose-Einstein occupations carrying the branch's
+ * energy), found by bisection in log T over [1e-2, 1e7] K; T_m = 0 when the
+ * branch energy is not positive.  mode_of (HOST, the instance's n_ph entries)
+ * gives each phonon state's branch in [0, n_modes); T_out is HOST memory of
+ * n_modes doubles.  y is a device state; the call synchronizes `stream`.
+ * RTBTE_E_INVAL for a bad instance, branch count or branch index. */
+int rtbte_mode_temperatures(rtbte_ctx *ctx, const double *y, int32_t inst, const int32_t *mode_of,
+                            int32_t n_modes, double *T_out, void *stream);
+
 /* Adaptive Zonneveld 4(3) ERK (Methods, ERK method) on the full RHS, every
  * instance with its own t, step size and PID history, until every instance
  * reaches t_out (one_step = 0) or has taken one accepted step (one_step = 1).
@@ -246,6 +283,29 @@ int rtbte_step_rk4(rtbte_ctx *ctx, double *y, double *t, double h_step, int64_t 
  * Only n_inst == 1 contexts support it (RTBTE_E_UNSUPPORTED otherwise). */
 int rtbte_step_multirate(rtbte_ctx *ctx, double *y, double *t, double *h_fast, double t_out,
                          double h_slow, int32_t one_step, void *stream);
+
+/* MIS multirate with an adaptive slow step (the extension the paper names
+ * for future work in its Discussion: both time steps chosen from
+ * tolerances).  The paper gives no slow error estimator; this one is step
+ * doubling (Hairer, Norsett & Wanner, Solving ODEs I, II.4): an attempt of
+ * size H takes one MIS step of H and two of H/2 from the same state, keeps
+ * the two-half-step result, and estimates its local error as
+ * (y_half - y_full) / 7 (the MIS order being 3).  The estimate's WRMS norm
+ * with the options' rtol, atol_el and atol_ph (weights from the state at the
+ * start of the attempt) decides acceptance; the next H is
+ * H safety eps^(-1/4), limited as for the ERK controller (eta_max,
+ * eta_max_first on the first accepted step, eta_fail_min .. eta_fail_max on
+ * rejection, at most max_fails consecutive rejections).  The fast part is
+ * integrated as in rtbte_step_multirate (full step, then the two halves, the
+ * fast solver's state carried through all three).
+ * h_slow[0] (device) holds the first slow step (must be > 0) and receives
+ * the next proposed one; t (device) and y are updated after every accepted
+ * step, so on an error they hold the last accepted state.  Advances to t_out
+ * (the last step shortened to land) or by one accepted step (one_step = 1).
+ * The first call allocates three state-sized work vectors kept by the
+ * context.  Single-instance contexts only (RTBTE_E_UNSUPPORTED otherwise). */
+int rtbte_step_multirate_adaptive(rtbte_ctx *ctx, double *y, double *t, double *h_fast, double *h_slow,
+                                  double t_out, int32_t one_step, void *stream);
 
 /* First-order operator splitting (the alternative the paper compares MIS
  * with, Results, Fig. 3): each step of h_slow advances the fast part

@@ -69,6 +69,7 @@ def _lib():
         L.orc_counts.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_rhs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_rates.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
         L.orc_max_weight.argtypes = [ctypes.c_void_p]
         L.orc_max_weight.restype = ctypes.c_double
         L.orc_rhs_rows.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -144,6 +145,16 @@ class Oracle:
         if unweighted:
             return out, S, A, M, Q
         return (out, S, A) if scales else out
+
+    def rates(self, y, parts: int = PART_ALL, magnitude: bool = False):
+        """Linearized rates -d(ydot_i)/d(y_i) of the parts in `parts`, partner
+        populations held fixed; with magnitude=True also sum |W|(|X|+|Y|)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        assert y.shape == (self.n_y,)
+        out = np.empty(self.n_y)
+        mag = np.empty(self.n_y) if magnitude else None
+        _lib().orc_rates(self._h, _p(y), _p(out), int(parts), _p(mag))
+        return (out, mag) if magnitude else out
 
     def max_weight(self) -> float:
         """Largest stored channel weight."""

@@ -305,3 +305,77 @@ class AdaptiveFastSolver:
         self.n_accept += a.n_accept
         self.n_reject += a.n_reject
         return v
+
+
+# ------------------------------------------------------- adaptive slow step
+def slow_controls(c: Controls) -> Controls:
+    """Controller of the slow step: an I controller on the step-doubling
+    estimate of a third-order method, eta = safety * eps^(-1/4), with the
+    safeguards of c (the paper leaves slow-step adaptivity to future work;
+    this is the textbook choice for a method without an embedded pair)."""
+    return Controls(rtol=c.rtol, atol_el=c.atol_el, atol_ph=c.atol_ph, k1=1.0, k2=0.0, k3=0.0, order=4,
+                    alt_sign=False, safety=c.safety, eta_max=c.eta_max, eta_max_first=c.eta_max_first,
+                    eta_fail_min=c.eta_fail_min, eta_fail_max=c.eta_fail_max, eps_floor=c.eps_floor,
+                    max_fails=c.max_fails)
+
+
+@dataclass
+class MisAdaptive:
+    """MRI (MIS) with the slow step chosen by step doubling (Hairer, Norsett &
+    Wanner, Solving ODEs I, II.4): an attempt of size H takes one MIS step of
+    H and two of H/2 from the same state; the two-half-step result is kept
+    and its local error is estimated by (y_half - y_full) / (2^3 - 1), the
+    MIS order being 3.  The estimate's WRMS norm (weights from the state at
+    the start of the attempt) decides acceptance; the step ratio comes from
+    slow_controls.  The fast solver is called in the order full step, first
+    half, second half, and keeps its own state across attempts."""
+    fast_rhs: object
+    slow_rhs: object
+    fast_solve: object
+    atol_vec: np.ndarray
+    c: Controls = field(default_factory=Controls)
+    H: float = 1.0
+    e1: float = 1.0
+    e2: float = 1.0
+    first: bool = True
+    n_accept: int = 0
+    n_reject: int = 0
+    history: list = field(default_factory=list)   # (t_new, H_used, eps) of accepted steps
+
+    def attempt(self, y, H):
+        """(y_half, eps) of one attempt of size H from y."""
+        y_full = mis_step(self.fast_rhs, self.slow_rhs, y, H, self.fast_solve)
+        y_half = mis_step(self.fast_rhs, self.slow_rhs, y, H / 2, self.fast_solve)
+        y_half = mis_step(self.fast_rhs, self.slow_rhs, y_half, H / 2, self.fast_solve)
+        est = (y_half - y_full) / 7.0
+        return y_half, wrms(est, y, self.c.rtol, self.atol_vec)
+
+    def advance(self, y, t, t_out, one_step=False):
+        cs = slow_controls(self.c)
+        fails = 0
+        while t < t_out:
+            H = self.H
+            last = t + H >= t_out
+            if last:
+                H = t_out - t
+            ynew, eps = self.attempt(y, H)
+            if not np.isfinite(eps):
+                raise StepFailure("non-finite error estimate")
+            if eps <= 1.0:
+                self.H = H * pid_eta(eps, self.e1, self.e2, True, self.first, cs)
+                self.e2, self.e1 = self.e1, max(eps, cs.eps_floor)
+                self.first = False
+                y = ynew
+                t = t_out if last else t + H
+                self.n_accept += 1
+                self.history.append((t, H, eps))
+                fails = 0
+                if one_step:
+                    break
+            else:
+                self.H = H * pid_eta(eps, self.e1, self.e2, False, self.first, cs)
+                self.n_reject += 1
+                fails += 1
+                if fails > cs.max_fails:
+                    raise StepFailure("too many consecutive error-test failures")
+        return y, t

@@ -283,6 +283,73 @@ void orc_rhs(const orc_lists *L, const double *y, double *ydot, int parts, doubl
   }
 }
 
+/* Linearized (relaxation-time) rates Gamma_i = -d(ydot_i)/d(y_i) with the
+ * partner populations held fixed: the sum over row i's channels of W times
+ * the derivative of its occupation factor with respect to the row's own
+ * population, from the factor definitions after Eq. (e-ph) and Eq. (ph-ph).
+ * On channels whose partner is the row's own state (q = 0 self-scattering)
+ * this is the standard scattering rate, not the Jacobian diagonal:
+ *   dF_em/df_r  = (1-f_s)(1+N_p) + f_s N_p      dF_abs/df_r = (1-f_s) N_p + f_s (1+N_p)
+ *   dF_abs/dN_p = f_r (1-f_s) - (1-f_r) f_s      (ph-e rows)
+ *   dG_em/dN    = (N_a+1)(N_b+1) - N_a N_b      dG_abs/dN   = (N_a+1) N_b - N_a (N_b+1)
+ * Neumaier-compensated sums; at phonons in equilibrium at temperature T the
+ * ph-ph part gives the mode-resolved three-phonon scattering rates. */
+static double row_rate(const orc_lists *L, const double *y, int64_t row, int parts, double *mag) {
+  const double *f = y, *N = y + L->n_el;
+  acc_t a = {0, 0, 0, 0, 0, 0};
+  if (row < L->n_el) {
+    if (parts & 1) {
+      const int32_t r = (int32_t)row;
+      for (int64_t j = L->el_ptr[r]; j < L->el_ptr[r + 1]; ++j) {
+        int64_t i = L->el_idx[j];
+        double fs = f[L->es[i]], Np = N[L->ep[i]];
+        if (L->w_em[i] != 0.0) {
+          double X = (1.0 - fs) * (1.0 + Np), Y = fs * Np;
+          acc_add(&a, L->w_em[i], L->w_em[i] * (X + Y), fabs(X) + fabs(Y));
+        }
+        if (L->w_abs[i] != 0.0) {
+          double X = (1.0 - fs) * Np, Y = fs * (1.0 + Np);
+          acc_add(&a, L->w_abs[i], L->w_abs[i] * (X + Y), fabs(X) + fabs(Y));
+        }
+      }
+    }
+  } else {
+    const int32_t p = (int32_t)(row - L->n_el);
+    if (parts & 2) {
+      for (int64_t j = L->phe_ptr[p]; j < L->phe_ptr[p + 1]; ++j) {
+        int64_t i = L->phe_idx[j];
+        double fr = f[L->er[i]], fs = f[L->es[i]];
+        double X = fr * (1.0 - fs), Y = (1.0 - fr) * fs;
+        acc_add(&a, L->w_phe[i], L->w_phe[i] * (X - Y), fabs(X) + fabs(Y));
+      }
+    }
+    if (parts & 4) {
+      for (int64_t j = L->pp_ptr[p]; j < L->pp_ptr[p + 1]; ++j) {
+        int64_t i = L->pp_idx[j];
+        double Na = N[L->pa[i]], Nb = N[L->pb[i]];
+        if (L->v_em[i] != 0.0) {
+          double X = (Na + 1.0) * (Nb + 1.0), Y = Na * Nb;
+          acc_add(&a, L->v_em[i], L->v_em[i] * (X - Y), fabs(X) + fabs(Y));
+        }
+        if (L->v_abs[i] != 0.0) {
+          double X = (Na + 1.0) * Nb, Y = Na * (Nb + 1.0);
+          acc_add(&a, L->v_abs[i], L->v_abs[i] * (X - Y), fabs(X) + fabs(Y));
+        }
+      }
+    }
+  }
+  if (mag) *mag = a.mag;
+  return a.s + a.c;
+}
+
+/* Rates of every row; optional mag[i] = sum |W| (|X| + |Y|) over the row's
+ * channels, with dF/dx = X +- Y (the magnitude the rate is formed from). */
+void orc_rates(const orc_lists *L, const double *y, double *out, int parts, double *mag) {
+  const int64_t ny = (int64_t)L->n_el + L->n_ph;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t row = 0; row < ny; ++row) out[row] = row_rate(L, y, row, parts, mag ? mag + row : NULL);
+}
+
 /* Largest stored channel weight. */
 double orc_max_weight(const orc_lists *L) {
   double m = 0.0;

@@ -125,6 +125,8 @@ struct rtbte_ctx {
   InstInfo* info_d = nullptr;
   InstState* st = nullptr;       // main integrator
   InstState* st_fast = nullptr;  // MIS fast integrator
+  InstState* st_slow = nullptr;  // MIS slow-step controller (adaptive multirate; one entry)
+  double* mra = nullptr;         // [3 * ny] adaptive multirate: full-step, half-step and estimate vectors
   double* kbuf[5] = {};
   double* zb[2] = {};
   double* ynew = nullptr;
@@ -152,6 +154,9 @@ struct rtbte_ctx {
   int64_t prof_n = 0;
   // host copy of the group table (work items are cut from it)
   std::vector<Group> groups_h;
+  // state energies (eV): eps of the electron states, hbar omega of the phonons
+  std::vector<double> energy_h;
+  double* energy_d = nullptr;
   // captured step sequences, replayed through HIP graphs (use_graph)
   struct GraphKey {
     const double* y; const double* forcing; const InstState* st;
@@ -346,7 +351,7 @@ void free_ctx(rtbte_ctx* c) {
   if (!c) return;
   void* ps[] = {c->ch, c->groups, c->items, c->order, c->item_ptr, c->row_group, c->partial_items,
                 c->mix_idx, c->mix_wq, c->mix_scale, c->popf, c->pk, c->pkw, c->row_inst, c->info_d, c->st,
-                c->st_fast,
+                c->st_fast, c->st_slow, c->mra, c->energy_d,
                 c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
                 c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
                 c->partial, c->tvec, c->summary_d};
@@ -461,6 +466,13 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     off += (int64_t)problems[i].n_el + problems[i].n_ph;
   }
   c->ny = off;
+  c->energy_h.resize((size_t)off);
+  for (int i = 0; i < n_inst; ++i) {
+    const rtbte_problem& p = problems[i];
+    if ((p.n_el > 0 && !p.eps) || (p.n_ph > 0 && !p.hw)) continue;   // check_problem rejected it already
+    std::copy(p.eps, p.eps + p.n_el, c->energy_h.begin() + c->info[i].off);
+    std::copy(p.hw, p.hw + p.n_ph, c->energy_h.begin() + c->info[i].off + p.n_el);
+  }
   if (c->ny > (int64_t)kPosMask) {
     free_ctx(c);
     return fail(nullptr, RTBTE_E_INVAL, "state vector too long (%lld > %d)", (long long)off, kPosMask);
@@ -692,6 +704,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   c->groups_h = std::move(groups);
   if (e == hipSuccess) e = build_items(c, o.item_channels);
   if (e == hipSuccess) e = upload(&c->info_d, c->info.data(), c->info.size());
+  if (e == hipSuccess && c->ny > 0) e = upload(&c->energy_d, c->energy_h.data(), c->energy_h.size());
   if (e == hipSuccess && o.precision == RTBTE_MIXED) {
     // compact weights with per-block FP32 scales; the FP64 channels are freed
     const bool pack = c->wfmt == RTBTE_W_PACK8;
@@ -757,6 +770,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   if (e == hipSuccess) e = hipMemset(c->forcing, 0, ny * sizeof(double));
   if (e == hipSuccess) c->st = dalloc<InstState>((size_t)n_inst, &e);
   if (e == hipSuccess) c->st_fast = dalloc<InstState>((size_t)n_inst, &e);
+  if (e == hipSuccess) c->st_slow = dalloc<InstState>(1, &e);
   if (e != hipSuccess) {
     fail(c, e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP, "work buffers: %s", hipGetErrorString(e));
     return cleanup(e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP);
@@ -795,6 +809,7 @@ extern "C" int rtbte_reset(rtbte_ctx* c) {
   }
   HIPCHK(c, hipMemcpy(c->st, s.data(), s.size() * sizeof(InstState), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->st_fast, s.data(), s.size() * sizeof(InstState), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->st_slow, s.data(), sizeof(InstState), hipMemcpyHostToDevice));
   c->extra_rhs[0] = c->extra_rhs[1] = c->extra_rhs[2] = 0;
   c->slow_steps = 0;
   c->split_slow_evals = 0;
@@ -896,8 +911,9 @@ hipError_t harvest(rtbte_ctx* c) {
 // kernel, the one that streams the channels and is timed when profiling),
 // then the per-row sums of items with the plain or stage epilogue.
 hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState* st, const FinishArgs& f,
-                      bool stage, hipStream_t s) {
+                      bool stage, hipStream_t s, bool deriv = false) {
   RowArgs a{};
+  a.deriv = deriv ? 1 : 0;
   a.ch = c->ch;
   a.pk = c->pk;
   a.pkw = c->pkw;
@@ -965,6 +981,18 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
 }
 
 }  // namespace
+
+extern "C" int rtbte_rates(rtbte_ctx* c, const double* y, double* rates, int32_t parts, void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (c->mixed) return fail(c, RTBTE_E_UNSUPPORTED, "rtbte_rates needs an RTBTE_FP64 context");
+  if (!y || !rates || parts < 1 || parts > 7) return fail(c, RTBTE_E_INVAL, "rtbte_rates: bad arguments");
+  if (y == rates) return fail(c, RTBTE_E_INVAL, "rtbte_rates: y and rates must not overlap");
+  HIPCHK(c, hipSetDevice(c->device));
+  FinishArgs f{};
+  f.out = rates;
+  HIPCHK(c, rhs_launch(c, y, parts, nullptr, f, false, (hipStream_t)stream, true));
+  return RTBTE_OK;
+}
 
 extern "C" int rtbte_rhs(rtbte_ctx* c, const double* y, double* ydot, int32_t parts, void* stream) {
   if (!c) return RTBTE_E_INVAL;
@@ -1224,64 +1252,162 @@ int rk4_segment(rtbte_ctx* c, double* y, double* t_in, int parts, const double* 
 
 }  // namespace
 
+namespace {
+
+// One MIS slow step of size hs from tc (Methods, MRI method): slow
+// right-hand sides at the stage values, each stage interval integrated by the
+// fast solver (adaptive ERK on st_fast with the device step h_in carried
+// along, or fixed RK4 substeps) with the constant forcing of Eq. (mis_coef).
+int mis_one(rtbte_ctx* c, double* y, double tc, double hs, bool fixed, const Ctl& ctl, const Tableau& tb,
+            hipStream_t s) {
+  const InstInfo& in = c->info[0];
+  const int64_t phoff = in.off + in.n_el;
+  double* t_in = c->tvec;      // fast solver time (device scalar)
+  double* h_in = c->tvec + 1;  // fast solver step (device scalar)
+  FinishArgs f{};
+  f.out = c->fs[0];
+  HIPCHK(c, rhs_launch(c, y, RTBTE_PART_PHPH, nullptr, f, false, s));
+  c->extra_rhs[2]++;
+  for (int i = 1; i < 4; ++i) {
+    const double* v[3] = {c->fs[0], c->fs[1], c->fs[2]};
+    HIPCHK(c, launch_lincomb(c->forcing, v, MIS_R[i], i, phoff, in.n_ph, s));
+    const double t0 = tc + MIS_C[i - 1] * hs, t1 = tc + MIS_C[i] * hs;
+    c->scal_h[2] = t0;
+    HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 2, sizeof(double), hipMemcpyHostToDevice, s));
+    int rc;
+    if (!fixed) {
+      rc = run(c, y, t_in, h_in, t1, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl, tb,
+               t1 - t0, 0, 0.0, s);
+    } else {
+      rc = rk4_segment(c, y, t_in, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, ctl, t0, t1, c->opt.h_fast, s);
+    }
+    if (rc) return rc;
+    if (i < 3) {
+      f.out = c->fs[i];
+      HIPCHK(c, rhs_launch(c, y, RTBTE_PART_PHPH, nullptr, f, false, s));
+      c->extra_rhs[2]++;
+    }
+  }
+  return RTBTE_OK;
+}
+
+// Checks shared by the multirate entry points; reads t (and h_fast) to the host.
+int mis_setup(rtbte_ctx* c, double* y, double* t, double* h_fast, double t_out, const char* who, bool* fixed,
+              Ctl* ctl, Tableau* tb, double* tc, hipStream_t s) {
+  if (c->n_inst != 1) return fail(c, RTBTE_E_UNSUPPORTED, "multirate stepping needs a single instance");
+  if (!y || !t || !h_fast || !std::isfinite(t_out)) return fail(c, RTBTE_E_INVAL, "%s: bad arguments", who);
+  HIPCHK(c, hipSetDevice(c->device));
+  *fixed = c->opt.fast_mode == 1;
+  if (*fixed && !(c->opt.h_fast > 0)) return fail(c, RTBTE_E_INVAL, "fixed fast mode needs h_fast > 0");
+  *ctl = make_ctl(c->opt, true, *fixed);
+  *tb = *fixed ? rk4() : zonneveld();
+  HIPCHK(c, hipMemcpyAsync(c->scal_h, t, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->tvec + 1, h_fast, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  *tc = c->scal_h[0];
+  return RTBTE_OK;
+}
+
+}  // namespace
+
 extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* h_fast, double t_out,
                                     double h_slow, int32_t one_step, void* stream) {
   if (!c) return RTBTE_E_INVAL;
-  if (c->n_inst != 1) return fail(c, RTBTE_E_UNSUPPORTED, "multirate stepping needs a single instance");
-  if (!y || !t || !h_fast || !(h_slow > 0) || !std::isfinite(t_out))
-    return fail(c, RTBTE_E_INVAL, "step_multirate: bad arguments");
-  HIPCHK(c, hipSetDevice(c->device));
+  if (!(h_slow > 0)) return fail(c, RTBTE_E_INVAL, "step_multirate: bad arguments");
   hipStream_t s = (hipStream_t)stream;
-  const bool fixed = c->opt.fast_mode == 1;
-  if (fixed && !(c->opt.h_fast > 0)) return fail(c, RTBTE_E_INVAL, "fixed fast mode needs h_fast > 0");
-  const Ctl ctl = make_ctl(c->opt, true, fixed);
-  const Tableau tb = fixed ? rk4() : zonneveld();
-  const InstInfo& in = c->info[0];
-  const int64_t phoff = in.off + in.n_el;
-  // host copy of t
-  HIPCHK(c, hipMemcpyAsync(c->scal_h, t, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(c->scal_h + 1, h_fast, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  double tc = c->scal_h[0];
-  double* t_in = c->tvec;      // fast solver time (device scalar)
-  double* h_in = c->tvec + 1;  // fast solver step (device scalar)
-  HIPCHK(c, hipMemcpyAsync(h_in, h_fast, sizeof(double), hipMemcpyDeviceToDevice, s));
+  bool fixed = false;
+  Ctl ctl{};
+  Tableau tb{};
+  double tc = 0.0;
+  int rc = mis_setup(c, y, t, h_fast, t_out, "step_multirate", &fixed, &ctl, &tb, &tc, s);
+  if (rc) return rc;
   while (tc < t_out) {
     double hs = h_slow;
     const bool last = tc + hs >= t_out;
     if (last) hs = t_out - tc;
-    // slow right-hand side at z_1
-    FinishArgs f{};
-    f.out = c->fs[0];
-    HIPCHK(c, rhs_launch(c, y, RTBTE_PART_PHPH, nullptr, f, false, s));
-    c->extra_rhs[2]++;
-    for (int i = 1; i < 4; ++i) {
-      const double* v[3] = {c->fs[0], c->fs[1], c->fs[2]};
-      HIPCHK(c, launch_lincomb(c->forcing, v, MIS_R[i], i, phoff, in.n_ph, s));
-      const double t0 = tc + MIS_C[i - 1] * hs, t1 = tc + MIS_C[i] * hs;
-      c->scal_h[2] = t0;
-      HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 2, sizeof(double), hipMemcpyHostToDevice, s));
-      int rc;
-      if (!fixed) {
-        rc = run(c, y, t_in, h_in, t1, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl, tb,
-                 t1 - t0, 0, 0.0, s);
-      } else {
-        rc = rk4_segment(c, y, t_in, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, ctl, t0, t1, c->opt.h_fast, s);
-      }
-      if (rc) return rc;
-      if (i < 3) {
-        f.out = c->fs[i];
-        HIPCHK(c, rhs_launch(c, y, RTBTE_PART_PHPH, nullptr, f, false, s));
-        c->extra_rhs[2]++;
-      }
-    }
+    rc = mis_one(c, y, tc, hs, fixed, ctl, tb, s);
+    if (rc) return rc;
     tc = last ? t_out : tc + hs;
     c->slow_steps++;
     if (one_step) break;
   }
   c->scal_h[4] = tc;
   HIPCHK(c, hipMemcpyAsync(t, c->scal_h + 4, sizeof(double), hipMemcpyHostToDevice, s));
-  if (!fixed) HIPCHK(c, hipMemcpyAsync(h_fast, h_in, sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (!fixed) HIPCHK(c, hipMemcpyAsync(h_fast, c->tvec + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t, double* h_fast, double* h_slow,
+                                             double t_out, int32_t one_step, void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (!h_slow) return fail(c, RTBTE_E_INVAL, "step_multirate_adaptive: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  bool fixed = false;
+  Ctl ctl{};
+  Tableau tb{};
+  double tc = 0.0;
+  int rc = mis_setup(c, y, t, h_fast, t_out, "step_multirate_adaptive", &fixed, &ctl, &tb, &tc, s);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->scal_h + 5, h_slow, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (!(c->scal_h[5] > 0.0) || !std::isfinite(c->scal_h[5]))
+    return fail(c, RTBTE_E_INVAL, "step_multirate_adaptive: the slow step h_slow must be positive");
+  if (!c->mra) {
+    hipError_t e = hipMalloc((void**)&c->mra, 3 * (size_t)c->ny * sizeof(double));
+    if (e != hipSuccess) {
+      c->mra = nullptr;
+      return fail(c, RTBTE_E_NOMEM, "step_multirate_adaptive: %s", hipGetErrorString(e));
+    }
+  }
+  double* y_full = c->mra;
+  double* y_half = c->mra + c->ny;
+  double* est = c->mra + 2 * c->ny;
+  // slow controller: I control on the step-doubling estimate of the
+  // third-order MIS step, eta = safety eps^(-1/4), the options' tolerances
+  Ctl cs = make_ctl(c->opt, false, false);
+  cs.k1 = 1.0;
+  cs.k2 = 0.0;
+  cs.k3 = 0.0;
+  cs.order = 4.0;
+  cs.alt_sign = 0;
+  cs.stages = 0;  // right-hand sides are counted by the MIS steps
+  HIPCHK(c, launch_begin(c->st_slow, t, h_slow, 1, t_out, one_step ? 1 : 0, 0.0, 0, 0.0, s));
+  const size_t nb = (size_t)c->ny * sizeof(double);
+  for (;;) {
+    InstState st{};
+    HIPCHK(c, hipMemcpyAsync(&st, c->st_slow, sizeof st, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (st.done) break;
+    const double H = st.h_use;
+    tc = st.t;
+    HIPCHK(c, hipMemcpyAsync(y_full, y, nb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(y_half, y, nb, hipMemcpyDeviceToDevice, s));
+    rc = mis_one(c, y_full, tc, H, fixed, ctl, tb, s);
+    if (rc == RTBTE_OK) rc = mis_one(c, y_half, tc, 0.5 * H, fixed, ctl, tb, s);
+    if (rc == RTBTE_OK) rc = mis_one(c, y_half, tc + 0.5 * H, 0.5 * H, fixed, ctl, tb, s);
+    if (rc) return rc;
+    // estimate (y_half - y_full) / (2^3 - 1); weights from the attempt's start
+    const double* dv[2] = {y_half, y_full};
+    const double one_m[2] = {1.0, -1.0}, seventh[1] = {1.0 / 7.0};
+    const double* ev[1] = {est};
+    HIPCHK(c, launch_lincomb(est, dv, one_m, 2, 0, c->ny, s));
+    HIPCHK(c, launch_lincomb(est, ev, seventh, 1, 0, c->ny, s));
+    HIPCHK(c, launch_wrms(est, y, c->info_d, c->st_slow, c->partial, 1, c->nchunk, cs, s));
+    HIPCHK(c, launch_control(c->st_slow, c->partial, c->info_d, 1, c->nchunk, cs, s));
+    HIPCHK(c, launch_commit(y, y_half, c->row_inst, c->st_slow, c->ny, s));
+    bool done = false;
+    int worst = 0;
+    rc = poll(c, c->st_slow, t, h_slow, s, &done, &worst);
+    if (rc) return rc;
+    if (done) {
+      c->last_status = worst;
+      if (worst == RTBTE_E_STEP) return fail(c, RTBTE_E_STEP, "too many consecutive slow-step failures");
+      if (worst == RTBTE_E_NONFINITE) return fail(c, RTBTE_E_NONFINITE, "non-finite slow error estimate");
+      break;
+    }
+  }
+  if (!fixed) HIPCHK(c, hipMemcpyAsync(h_fast, c->tvec + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   return RTBTE_OK;
 }
@@ -1319,14 +1445,16 @@ extern "C" int rtbte_step_split(rtbte_ctx* c, double* y, double* t, double h_fas
 
 extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* out) {
   if (!c || !out || inst < 0 || inst >= c->n_inst) return RTBTE_E_INVAL;
-  InstState s, f;
+  InstState s, f, w;
   if (hipSetDevice(c->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
       hipMemcpy(&s, c->st + inst, sizeof s, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(&f, c->st_fast + inst, sizeof f, hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(&f, c->st_fast + inst, sizeof f, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&w, c->st_slow, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
     return RTBTE_E_HIP;
   std::memset(out, 0, sizeof *out);
-  out->n_accept = s.n_accept + c->slow_steps;   // ERK steps, plus MIS slow steps (single instance)
-  out->n_reject = s.n_reject;
+  // ERK steps, plus MIS slow steps (fixed and adaptive; single-instance contexts)
+  out->n_accept = s.n_accept + c->slow_steps + (c->n_inst == 1 ? w.n_accept : 0);
+  out->n_reject = s.n_reject + (c->n_inst == 1 ? w.n_reject : 0);
   out->n_fast_accept = f.n_accept;
   out->n_fast_reject = f.n_reject;
   const int64_t main_evals = s.n_evals, fast_evals = f.n_evals;
@@ -1345,7 +1473,7 @@ extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* ou
 
 extern "C" int rtbte_get_state(const rtbte_ctx* c, void* buf, size_t* len) {
   if (!c || !len) return RTBTE_E_INVAL;
-  const size_t need = 2 * (size_t)c->n_inst * sizeof(InstState) + 5 * sizeof(int64_t);
+  const size_t need = (2 * (size_t)c->n_inst + 1) * sizeof(InstState) + 5 * sizeof(int64_t);
   if (!buf) {
     *len = need;
     return RTBTE_OK;
@@ -1355,25 +1483,29 @@ extern "C" int rtbte_get_state(const rtbte_ctx* c, void* buf, size_t* len) {
   if (hipSetDevice(c->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
       hipMemcpy(p, c->st, c->n_inst * sizeof(InstState), hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(p + c->n_inst * sizeof(InstState), c->st_fast, c->n_inst * sizeof(InstState),
-                hipMemcpyDeviceToHost) != hipSuccess)
+                hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(p + 2 * c->n_inst * sizeof(InstState), c->st_slow, sizeof(InstState), hipMemcpyDeviceToHost) !=
+          hipSuccess)
     return RTBTE_E_HIP;
   int64_t tail[5] = {c->extra_rhs[0], c->extra_rhs[1], c->extra_rhs[2], c->slow_steps, c->split_slow_evals};
-  std::memcpy(p + 2 * c->n_inst * sizeof(InstState), tail, sizeof tail);
+  std::memcpy(p + (2 * c->n_inst + 1) * sizeof(InstState), tail, sizeof tail);
   *len = need;
   return RTBTE_OK;
 }
 
 extern "C" int rtbte_set_state(rtbte_ctx* c, const void* buf, size_t len) {
   if (!c || !buf) return RTBTE_E_INVAL;
-  const size_t need = 2 * (size_t)c->n_inst * sizeof(InstState) + 5 * sizeof(int64_t);
+  const size_t need = (2 * (size_t)c->n_inst + 1) * sizeof(InstState) + 5 * sizeof(int64_t);
   if (len != need) return fail(c, RTBTE_E_INVAL, "state size %zu, expected %zu", len, need);
   const char* p = (const char*)buf;
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipMemcpy(c->st, p, c->n_inst * sizeof(InstState), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->st_fast, p + c->n_inst * sizeof(InstState), c->n_inst * sizeof(InstState),
                       hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->st_slow, p + 2 * c->n_inst * sizeof(InstState), sizeof(InstState),
+                      hipMemcpyHostToDevice));
   int64_t tail[5];
-  std::memcpy(tail, p + 2 * c->n_inst * sizeof(InstState), sizeof tail);
+  std::memcpy(tail, p + (2 * c->n_inst + 1) * sizeof(InstState), sizeof tail);
   c->extra_rhs[0] = tail[0];
   c->extra_rhs[1] = tail[1];
   c->extra_rhs[2] = tail[2];
@@ -1615,4 +1747,89 @@ extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const
     return tune_create(problems, n_inst, o, out);
   }
   return create_impl(problems, n_inst, &o, out);
+}
+
+// ---------------------------------------------------------------- observables
+namespace {
+
+// Upload a CSR (ptr[n+1], idx) built on the host, run `body`, free it.
+template <class F>
+int with_csr(rtbte_ctx* c, const std::vector<int32_t>& ptr, const std::vector<int32_t>& idx, hipStream_t s,
+             F&& body) {
+  int32_t *dp = nullptr, *di = nullptr;
+  hipError_t e = upload(&dp, ptr.data(), ptr.size());
+  if (e == hipSuccess) e = upload(&di, idx.empty() ? ptr.data() : idx.data(), std::max<size_t>(idx.size(), 1));
+  int rc = e == hipSuccess ? body(dp, di) : fail(c, RTBTE_E_NOMEM, "observables: %s", hipGetErrorString(e));
+  if (rc == RTBTE_OK) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(c, RTBTE_E_HIP, "observables: %s", hipGetErrorString(e));
+  }
+  if (dp) (void)hipFree(dp);
+  if (di) (void)hipFree(di);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int rtbte_energy_average(rtbte_ctx* c, const double* y, const double* y_ref, int32_t inst,
+                                    int32_t which, double e_lo, double e_hi, int32_t n_bins, double* out,
+                                    void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (!y || !out || inst < 0 || inst >= c->n_inst || (which != 0 && which != 1) || n_bins < 1 ||
+      !(e_hi > e_lo))
+    return fail(c, RTBTE_E_INVAL, "rtbte_energy_average: bad arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const InstInfo& in = c->info[inst];
+  const int64_t b0 = in.off + (which ? in.n_el : 0), n = which ? in.n_ph : in.n_el;
+  // states by bin (stable counting sort), bins [e_lo + k de, e_lo + (k+1) de)
+  std::vector<int32_t> ptr((size_t)n_bins + 1, 0), bin((size_t)n);
+  const double de = (e_hi - e_lo) / n_bins;
+  for (int64_t j = 0; j < n; ++j) {
+    const double x = c->energy_h[(size_t)(b0 + j)];
+    int32_t k = -1;
+    if (x >= e_lo && x < e_hi) k = std::min<int32_t>(n_bins - 1, (int32_t)std::floor((x - e_lo) / de));
+    bin[(size_t)j] = k;
+    if (k >= 0) ptr[(size_t)k + 1]++;
+  }
+  for (int k = 0; k < n_bins; ++k) ptr[(size_t)k + 1] += ptr[(size_t)k];
+  std::vector<int32_t> idx((size_t)ptr[(size_t)n_bins]), cur(ptr.begin(), ptr.end() - 1);
+  for (int64_t j = 0; j < n; ++j)
+    if (bin[(size_t)j] >= 0) idx[(size_t)cur[(size_t)bin[(size_t)j]]++] = (int32_t)(b0 + j);
+  double* dout = nullptr;
+  HIPCHK(c, hipMalloc((void**)&dout, 3 * (size_t)n_bins * sizeof(double)));
+  int rc = with_csr(c, ptr, idx, s, [&](int32_t* dp, int32_t* di) -> int {
+    HIPCHK(c, launch_bin_means(y, y_ref, di, dp, n_bins, dout, s));
+    HIPCHK(c, hipMemcpyAsync(out, dout, 3 * (size_t)n_bins * sizeof(double), hipMemcpyDeviceToHost, s));
+    return RTBTE_OK;
+  });
+  (void)hipFree(dout);
+  return rc;
+}
+
+extern "C" int rtbte_mode_temperatures(rtbte_ctx* c, const double* y, int32_t inst, const int32_t* mode_of,
+                                       int32_t n_modes, double* T_out, void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (!y || !mode_of || !T_out || inst < 0 || inst >= c->n_inst || n_modes < 1)
+    return fail(c, RTBTE_E_INVAL, "rtbte_mode_temperatures: bad arguments");
+  const InstInfo& in = c->info[inst];
+  for (int32_t j = 0; j < in.n_ph; ++j)
+    if (mode_of[j] < 0 || mode_of[j] >= n_modes)
+      return fail(c, RTBTE_E_INVAL, "rtbte_mode_temperatures: mode_of[%d] = %d out of range", j, mode_of[j]);
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> ptr((size_t)n_modes + 1, 0), idx((size_t)in.n_ph);
+  for (int32_t j = 0; j < in.n_ph; ++j) ptr[(size_t)mode_of[j] + 1]++;
+  for (int k = 0; k < n_modes; ++k) ptr[(size_t)k + 1] += ptr[(size_t)k];
+  std::vector<int32_t> cur(ptr.begin(), ptr.end() - 1);
+  for (int32_t j = 0; j < in.n_ph; ++j) idx[(size_t)cur[(size_t)mode_of[j]]++] = (int32_t)(in.off + in.n_el + j);
+  double* dT = nullptr;
+  HIPCHK(c, hipMalloc((void**)&dT, (size_t)n_modes * sizeof(double)));
+  int rc = with_csr(c, ptr, idx, s, [&](int32_t* dp, int32_t* di) -> int {
+    HIPCHK(c, launch_mode_temperature(y, c->energy_d, di, dp, n_modes, dT, s));
+    HIPCHK(c, hipMemcpyAsync(T_out, dT, (size_t)n_modes * sizeof(double), hipMemcpyDeviceToHost, s));
+    return RTBTE_OK;
+  });
+  (void)hipFree(dT);
+  return rc;
 }

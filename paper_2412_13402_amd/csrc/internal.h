@@ -95,6 +95,7 @@ struct RowArgs {
   const double* z;          // populations the integrals are evaluated at
   double* partial;          // [n_items][kMaxGroupRows] row sums of each item
   const InstState* st;      // stage mode: items of finished instances are skipped (else nullptr)
+  int32_t deriv;            // 1: each term is -W dF/dx_row (the rows then hold linearized rates)
 };
 
 // Arguments of the row kernel: sums of the items of each row's group, the
@@ -210,5 +211,11 @@ struct PrepArgs {
 };
 hipError_t launch_prep_count(const PrepArgs& p, hipStream_t s);
 hipError_t launch_prep_fill(const PrepArgs& p, hipStream_t s);
+
+// observables
+hipError_t launch_bin_means(const double* y, const double* yref, const int32_t* idx, const int32_t* ptr,
+                            int n_bins, double* out, hipStream_t s);
+hipError_t launch_mode_temperature(const double* y, const double* e, const int32_t* idx, const int32_t* ptr,
+                                   int n_modes, double* T_out, hipStream_t s);
 
 }  // namespace rtbte

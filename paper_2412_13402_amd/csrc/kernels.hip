@@ -39,28 +39,33 @@ enum { K_EPH = 0, K_PHE = 1, K_PP = 2 };
 //   ph-ph, phonon row l, partners a, b:
 //     G_em  = N (N_a+1)(N_b+1) - (N+1) N_a N_b
 //     G_abs = N (N_a+1) N_b    - (N+1) N_a (N_b+1)
-template <int KIND>
+// With DERIV the term is -w dF/dx_r instead, the derivative of the factor
+// with respect to the row's own population x_r (partners held fixed): the
+// row's sum then negates to the linearized (relaxation-time) rate.  Each
+// factor is x_r X - x_r' Y with x_r' = 1 - x_r (electron rows) or x_r + 1
+// (phonon rows), so dF/dx_r = X + Y or X - Y.
+template <int KIND, bool DERIV = false>
 __device__ __forceinline__ double term_w(bool em, double w, double g0, double g1, double xr, double xr1) {
   if (KIND == K_EPH) {            // xr = f_r, xr1 = 1 - f_r, g0 = f_s, g1 = N_p
     const double n1 = g1 + 1.0;
-    const double gain = xr * (1.0 - g0) * (em ? n1 : g1);
-    const double loss = xr1 * g0 * (em ? g1 : n1);
-    return w * (gain - loss);
+    const double X = (1.0 - g0) * (em ? n1 : g1), Y = g0 * (em ? g1 : n1);
+    if (DERIV) return -w * (X + Y);
+    return w * (xr * X - xr1 * Y);
   } else if (KIND == K_PHE) {     // xr = N_p, xr1 = N_p + 1, g0 = f_r, g1 = f_s
-    const double gain = g0 * (1.0 - g1) * xr;
-    const double loss = (1.0 - g0) * g1 * xr1;
-    return w * (gain - loss);
+    const double X = g0 * (1.0 - g1), Y = (1.0 - g0) * g1;
+    if (DERIV) return -w * (X - Y);
+    return w * (X * xr - Y * xr1);
   } else {                        // xr = N, xr1 = N + 1, g0 = N_a, g1 = N_b
     const double b1 = g1 + 1.0;
-    const double gain = xr * (g0 + 1.0) * (em ? b1 : g1);
-    const double loss = xr1 * g0 * (em ? g1 : b1);
-    return w * (gain - loss);
+    const double X = (g0 + 1.0) * (em ? b1 : g1), Y = g0 * (em ? g1 : b1);
+    if (DERIV) return -w * (X - Y);
+    return w * (xr * X - xr1 * Y);
   }
 }
 
-template <int KIND>
+template <int KIND, bool DERIV>
 __device__ __forceinline__ double term(const v4i c, double g0, double g1, double xr, double xr1) {
-  return term_w<KIND>(c.y < 0, chan_w(c), g0, g1, xr, xr1);
+  return term_w<KIND, DERIV>(c.y < 0, chan_w(c), g0, g1, xr, xr1);
 }
 
 // Per-lane accumulators of one wavefront: one slot per (row of the group,
@@ -78,19 +83,19 @@ struct LaneAcc {
 
 // One channel: w * factor with the gathered partner populations g0, g1 and
 // the row's own population (kept in LDS), added to the accumulator of its row.
-template <int G, int KIND>
+template <int G, int KIND, bool DERIV>
 __device__ __forceinline__ void chan_acc(LaneAcc<G>& acc, const v4i c, double g0, double g1,
                                          const double* rowv) {
   const int tag = G == 1 ? 0 : ((c.x >> kTagShift) & 15);
   const double xr = rowv[tag];
   const double xr1 = KIND == K_EPH ? 1.0 - xr : xr + 1.0;
-  acc.add(tag, term<KIND>(c, g0, g1, xr, xr1));
+  acc.add(tag, term<KIND, DERIV>(c, g0, g1, xr, xr1));
 }
 
 // Stream [s, e) with a two-stage software pipeline: the gathers of batch k
 // are issued before the stream loads of batch k+1, so waiting for the
 // gathers (in-order completion counters) leaves the next batch in flight.
-template <int G, int LANES, int KIND>
+template <int G, int LANES, int KIND, bool DERIV>
 __device__ __forceinline__ void seg_sum(LaneAcc<G>& acc, const Channel* __restrict__ ch, int64_t s,
                                         int64_t e, int lane, const double* __restrict__ z,
                                         const double* rowv) {
@@ -113,10 +118,10 @@ __device__ __forceinline__ void seg_sum(LaneAcc<G>& acc, const Channel* __restri
         n2 = ld_stream(ch + i + 2 * LANES);
         n3 = ld_stream(ch + i + 3 * LANES);
       }
-      chan_acc<G, KIND>(acc, c0, a0, b0, rowv);
-      chan_acc<G, KIND>(acc, c1, a1, b1, rowv);
-      chan_acc<G, KIND>(acc, c2, a2, b2, rowv);
-      chan_acc<G, KIND>(acc, c3, a3, b3, rowv);
+      chan_acc<G, KIND, DERIV>(acc, c0, a0, b0, rowv);
+      chan_acc<G, KIND, DERIV>(acc, c1, a1, b1, rowv);
+      chan_acc<G, KIND, DERIV>(acc, c2, a2, b2, rowv);
+      chan_acc<G, KIND, DERIV>(acc, c3, a3, b3, rowv);
       if (!more) break;
       c0 = n0; c1 = n1; c2 = n2; c3 = n3;
       i += STEP;
@@ -124,7 +129,7 @@ __device__ __forceinline__ void seg_sum(LaneAcc<G>& acc, const Channel* __restri
   }
   for (; i < e; i += LANES) {
     const v4i c = ld_stream(ch + i);
-    chan_acc<G, KIND>(acc, c, z[c.x & kPosMask], z[c.y & kPosMask], rowv);
+    chan_acc<G, KIND, DERIV>(acc, c, z[c.x & kPosMask], z[c.y & kPosMask], rowv);
   }
 }
 
@@ -134,7 +139,7 @@ typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 // One packed FP64 channel: the 8-byte word (lo, hi) and the low weight word
 // wl (layout in internal.h; 32-bit operations only), the gathered partner
 // values g0, g1.
-template <int G, int KIND>
+template <int G, int KIND, bool DERIV>
 __device__ __forceinline__ void chan_p12(LaneAcc<G>& acc, uint32_t lo, uint32_t hi, uint32_t wl, double g0,
                                          double g1, const double* rowv, int P, int sh) {
   const int tag = G == 1 ? 0 : (int)((lo >> P) & 15u);
@@ -144,14 +149,14 @@ __device__ __forceinline__ void chan_p12(LaneAcc<G>& acc, uint32_t lo, uint32_t 
   const double w = __hiloint2double((int)h32, (int)(wl << sh));
   const double xr = rowv[tag];
   const double xr1 = KIND == K_EPH ? 1.0 - xr : xr + 1.0;
-  acc.add(tag, term_w<KIND>(em, w, g0, g1, xr, xr1));
+  acc.add(tag, term_w<KIND, DERIV>(em, w, g0, g1, xr, xr1));
 }
 
 // Channels [s, e) of one kind from the packed FP64 stream, read as channel
 // pairs (16 B of words and 8 B of low weight words), lanes on consecutive
 // pairs, two pairs 64 apart per lane per batch (whole lines per load), with
 // the two-stage pipeline of seg_sum.  `off` is the instance's offset in z.
-template <int G, int KIND>
+template <int G, int KIND, bool DERIV>
 __device__ __forceinline__ void seg_sum_p12(LaneAcc<G>& acc, const RowArgs& a, int64_t s, int64_t e, int lane,
                                             const double* __restrict__ z, const double* rowv, uint32_t off) {
   if (s >= e) return;
@@ -204,9 +209,9 @@ __device__ __forceinline__ void seg_sum_p12(LaneAcc<G>& acc, const RowArgs& a, i
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t ca = 2 * (pb + lane + 64 * j);
-      if (ca >= s && ca < e) chan_p12<G, KIND>(acc, c[j].x, c[j].y, wl[j].x, g0[2 * j], g1[2 * j], rowv, P, sh);
+      if (ca >= s && ca < e) chan_p12<G, KIND, DERIV>(acc, c[j].x, c[j].y, wl[j].x, g0[2 * j], g1[2 * j], rowv, P, sh);
       if (ca + 1 >= s && ca + 1 < e)
-        chan_p12<G, KIND>(acc, c[j].z, c[j].w, wl[j].y, g0[2 * j + 1], g1[2 * j + 1], rowv, P, sh);
+        chan_p12<G, KIND, DERIV>(acc, c[j].z, c[j].w, wl[j].y, g0[2 * j + 1], g1[2 * j + 1], rowv, P, sh);
     }
     if (!more) break;
 #pragma unroll
@@ -220,7 +225,7 @@ __device__ __forceinline__ void seg_sum_p12(LaneAcc<G>& acc, const RowArgs& a, i
 
 // One wavefront per block, so the LDS a block needs is one wavefront's
 // accumulator slots and occupancy is not capped by whole 4-wave blocks.
-template <int G, bool PACK>
+template <int G, bool PACK, bool DERIV>
 __global__ __launch_bounds__(64) void k_items(RowArgs a) {
   __shared__ double acc_lds[1][G][64];
   __shared__ double rowv[1][kMaxGroupRows];
@@ -252,17 +257,17 @@ __global__ __launch_bounds__(64) void k_items(RowArgs a) {
     if constexpr (PACK) {
       const uint32_t off = (uint32_t)a.info[g.inst].off;
       if (!g.phonon) {
-        if (a.parts & 1) seg_sum_p12<G, K_EPH>(acc, a, item.lo, item.hi, lane, a.z, rv, off);
+        if (a.parts & 1) seg_sum_p12<G, K_EPH, DERIV>(acc, a, item.lo, item.hi, lane, a.z, rv, off);
       } else {
-        if (a.parts & 2) seg_sum_p12<G, K_PHE>(acc, a, lo_pe, hi_pe, lane, a.z, rv, off);
-        if (a.parts & 4) seg_sum_p12<G, K_PP>(acc, a, lo_pp, hi_pp, lane, a.z, rv, off);
+        if (a.parts & 2) seg_sum_p12<G, K_PHE, DERIV>(acc, a, lo_pe, hi_pe, lane, a.z, rv, off);
+        if (a.parts & 4) seg_sum_p12<G, K_PP, DERIV>(acc, a, lo_pp, hi_pp, lane, a.z, rv, off);
       }
     } else {
       if (!g.phonon) {
-        if (a.parts & 1) seg_sum<G, 64, K_EPH>(acc, a.ch, item.lo, item.hi, lane, a.z, rv);
+        if (a.parts & 1) seg_sum<G, 64, K_EPH, DERIV>(acc, a.ch, item.lo, item.hi, lane, a.z, rv);
       } else {
-        if (a.parts & 2) seg_sum<G, 64, K_PHE>(acc, a.ch, lo_pe, hi_pe, lane, a.z, rv);
-        if (a.parts & 4) seg_sum<G, 64, K_PP>(acc, a.ch, lo_pp, hi_pp, lane, a.z, rv);
+        if (a.parts & 2) seg_sum<G, 64, K_PHE, DERIV>(acc, a.ch, lo_pe, hi_pe, lane, a.z, rv);
+        if (a.parts & 4) seg_sum<G, 64, K_PP, DERIV>(acc, a.ch, lo_pp, hi_pp, lane, a.z, rv);
       }
     }
   }
@@ -283,13 +288,13 @@ __global__ __launch_bounds__(64) void k_items(RowArgs a) {
   }
 }
 
-template <bool PACK>
+template <bool PACK, bool DERIV>
 hipError_t launch_items_fmt(const RowArgs& a, int slots, hipStream_t s) {
   const int64_t nb = a.n_items;
   switch (slots) {
-    case 1: hipLaunchKernelGGL((k_items<1, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_items<8, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_items<16, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_items<1, PACK, DERIV>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_items<8, PACK, DERIV>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_items<16, PACK, DERIV>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -300,9 +305,9 @@ hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s) {
   if (a.pk) {
     if (!a.pkw || !a.info || a.pack_p < 1 || a.pack_p > 19 || a.pack_m != std::min(80 - 2 * a.pack_p, 52))
       return hipErrorInvalidValue;
-    return launch_items_fmt<true>(a, slots, s);
+    return a.deriv ? launch_items_fmt<true, true>(a, slots, s) : launch_items_fmt<true, false>(a, slots, s);
   }
-  return launch_items_fmt<false>(a, slots, s);
+  return a.deriv ? launch_items_fmt<false, true>(a, slots, s) : launch_items_fmt<false, false>(a, slots, s);
 }
 
 // Create time: the 16-byte FP64 channels to the packed 12-byte layout.
@@ -1182,6 +1187,94 @@ hipError_t launch_prep_count(const PrepArgs& p, hipStream_t s) {
 hipError_t launch_prep_fill(const PrepArgs& p, hipStream_t s) {
   if (p.n_dest == 0) return hipSuccess;
   hipLaunchKernelGGL(k_prep, dim3((unsigned)((p.n_dest + 3) / 4)), dim3(256), 0, s, p, 1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- observables
+// Energy-resolved averages: one wavefront per bin reduces the populations of
+// the bin's states (idx[ptr[b] .. ptr[b+1])) in a fixed order.  out[3b] = state
+// count, out[3b+1] = mean population, out[3b+2] = mean of (y - y_ref) (0 when
+// y_ref is null).
+__global__ __launch_bounds__(64) void k_bin_means(const double* __restrict__ y, const double* __restrict__ yref,
+                                                  const int32_t* idx, const int32_t* ptr, int n_bins, double* out) {
+  const int b = blockIdx.x;
+  if (b >= n_bins) return;
+  const int lane = threadIdx.x;
+  double sp = 0.0, sd = 0.0;
+  for (int32_t k = ptr[b] + lane; k < ptr[b + 1]; k += 64) {
+    const double v = y[idx[k]];
+    sp += v;
+    if (yref) sd += v - yref[idx[k]];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sp += __shfl_xor(sp, o, 64);
+    sd += __shfl_xor(sd, o, 64);
+  }
+  if (lane == 0) {
+    const int32_t n = ptr[b + 1] - ptr[b];
+    out[3 * b] = (double)n;
+    out[3 * b + 1] = n ? sp / n : 0.0;
+    out[3 * b + 2] = n ? sd / n : 0.0;
+  }
+}
+
+hipError_t launch_bin_means(const double* y, const double* yref, const int32_t* idx, const int32_t* ptr,
+                            int n_bins, double* out, hipStream_t s) {
+  if (n_bins <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin_means, dim3((unsigned)n_bins), dim3(64), 0, s, y, yref, idx, ptr, n_bins, out);
+  return hipGetLastError();
+}
+
+// Effective temperature of each phonon branch: the T at which Bose-Einstein
+// occupations of the branch's states carry the branch's energy sum hw N.
+// One block per branch; bisection in log T over [1e-2, 1e7] K, every sum a
+// fixed-order block reduction.  States with hw <= 0 are left out.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  const int t = threadIdx.x;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_mode_temperature(const double* __restrict__ y, const double* __restrict__ e,
+                                                          const int32_t* idx, const int32_t* ptr, int n_modes,
+                                                          double* T_out) {
+  __shared__ double red[4];
+  const int m = blockIdx.x;
+  if (m >= n_modes) return;
+  const double kB = 8.617333262e-5;   // eV/K
+  double v = 0.0;
+  for (int32_t k = ptr[m] + threadIdx.x; k < ptr[m + 1]; k += 256) {
+    const double w = e[idx[k]];
+    if (w > 0.0) v += w * y[idx[k]];
+  }
+  const double target = block_sum256(v, red);
+  if (!(target > 0.0)) {
+    if (threadIdx.x == 0) T_out[m] = 0.0;
+    return;
+  }
+  double lo = log(1e-2), hi = log(1e7);
+  for (int it = 0; it < 100; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double kT = kB * exp(mid);
+    double u = 0.0;
+    for (int32_t k = ptr[m] + threadIdx.x; k < ptr[m + 1]; k += 256) {
+      const double w = e[idx[k]];
+      if (w > 0.0) u += w / expm1(w / kT);
+    }
+    const double tot = block_sum256(u, red);
+    if (tot < target) lo = mid;
+    else hi = mid;
+  }
+  if (threadIdx.x == 0) T_out[m] = exp(0.5 * (lo + hi));
+}
+
+hipError_t launch_mode_temperature(const double* y, const double* e, const int32_t* idx, const int32_t* ptr,
+                                   int n_modes, double* T_out, hipStream_t s) {
+  if (n_modes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mode_temperature, dim3((unsigned)n_modes), dim3(256), 0, s, y, e, idx, ptr, n_modes, T_out);
   return hipGetLastError();
 }
 

@@ -111,9 +111,13 @@ def load():
     L.rtbte_ny.restype = i64
     L.rtbte_counts.argtypes = [_vp, i32, ctypes.POINTER(i64)]
     L.rtbte_rhs.argtypes = [_vp, _vp, _vp, i32, _vp]
+    L.rtbte_rates.argtypes = [_vp, _vp, _vp, i32, _vp]
+    L.rtbte_energy_average.argtypes = [_vp, _vp, _vp, i32, i32, dbl, dbl, i32, _vp, _vp]
+    L.rtbte_mode_temperatures.argtypes = [_vp, _vp, i32, _vp, i32, _vp, _vp]
     L.rtbte_step_adaptive.argtypes = [_vp, _vp, _vp, _vp, dbl, i32, _vp]
     L.rtbte_step_rk4.argtypes = [_vp, _vp, _vp, dbl, i64, _vp]
     L.rtbte_step_multirate.argtypes = [_vp, _vp, _vp, _vp, dbl, dbl, i32, _vp]
+    L.rtbte_step_multirate_adaptive.argtypes = [_vp, _vp, _vp, _vp, _vp, dbl, i32, _vp]
     L.rtbte_step_split.argtypes = [_vp, _vp, _vp, dbl, dbl, dbl, _vp]
     L.rtbte_reset.argtypes = [_vp]
     L.rtbte_get_stats.argtypes = [_vp, i32, ctypes.POINTER(Stats)]
@@ -228,6 +232,35 @@ class Context:
         self._check(load().rtbte_rhs(self._h, _dptr(y, self.ny, "y"), _dptr(ydot, self.ny, "ydot"),
                                      int(parts), _stream(stream)))
 
+    def rates(self, y, out, parts=PART_ALL, stream=None):
+        """Linearized rates -d(ydot_i)/d(y_i), partners held fixed (FP64 contexts)."""
+        self._check(load().rtbte_rates(self._h, _dptr(y, self.ny, "y"), _dptr(out, self.ny, "rates"),
+                                       int(parts), _stream(stream)))
+
+    def energy_average(self, y, e_lo, e_hi, n_bins, phonons=False, y_ref=None, inst=0, stream=None):
+        """Per energy bin: (state count, mean population, mean of y - y_ref)
+        of one instance's carriers (phonons=False, binned by eps) or phonons
+        (binned by hbar omega); numpy arrays of n_bins each."""
+        out = np.empty(3 * int(n_bins), dtype=np.float64)
+        ref = None if y_ref is None else _dptr(y_ref, self.ny, "y_ref")
+        self._check(load().rtbte_energy_average(self._h, _dptr(y, self.ny, "y"), ref, int(inst), int(bool(phonons)),
+                                                float(e_lo), float(e_hi), int(n_bins),
+                                                out.ctypes.data_as(_vp), _stream(stream)))
+        o = out.reshape(-1, 3)
+        return o[:, 0].copy(), o[:, 1].copy(), o[:, 2].copy()
+
+    def mode_temperatures(self, y, mode_of, n_modes, inst=0, stream=None):
+        """Effective temperature (K) of each phonon branch of one instance;
+        mode_of gives the branch of each of the instance's phonon states."""
+        m = np.ascontiguousarray(mode_of, dtype=np.int32)
+        if m.shape != (self.layout(inst)[2],):
+            raise ValueError(f"mode_of must have one entry per phonon state of instance {inst}")
+        out = np.empty(int(n_modes), dtype=np.float64)
+        self._check(load().rtbte_mode_temperatures(self._h, _dptr(y, self.ny, "y"), int(inst),
+                                                   m.ctypes.data_as(_vp), int(n_modes),
+                                                   out.ctypes.data_as(_vp), _stream(stream)))
+        return out
+
     def step_adaptive(self, y, t, h, t_out, one_step=False, stream=None):
         self._check(load().rtbte_step_adaptive(self._h, _dptr(y, self.ny, "y"), _dptr(t, self.n_inst, "t"),
                                                _dptr(h, self.n_inst, "h"), float(t_out), int(bool(one_step)),
@@ -241,6 +274,13 @@ class Context:
         self._check(load().rtbte_step_multirate(self._h, _dptr(y, self.ny, "y"), _dptr(t, 1, "t"),
                                                 _dptr(h_fast, 1, "h_fast"), float(t_out), float(h_slow),
                                                 int(bool(one_step)), _stream(stream)))
+
+    def step_multirate_adaptive(self, y, t, h_fast, h_slow, t_out, one_step=False, stream=None):
+        """MIS with the slow step chosen by step doubling; h_slow (device, 1
+        entry) holds the first slow step and receives the next one."""
+        self._check(load().rtbte_step_multirate_adaptive(self._h, _dptr(y, self.ny, "y"), _dptr(t, 1, "t"),
+                                                         _dptr(h_fast, 1, "h_fast"), _dptr(h_slow, 1, "h_slow"),
+                                                         float(t_out), int(bool(one_step)), _stream(stream)))
 
     def step_split(self, y, t, h_fast, h_slow, t_out, stream=None):
         self._check(load().rtbte_step_split(self._h, _dptr(y, self.ny, "y"), _dptr(t, 1, "t"), float(h_fast),

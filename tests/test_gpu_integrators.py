@@ -321,3 +321,72 @@ def test_operator_splitting_matches_oracle():
     st = ctx.stats()
     assert st["n_accept"] == 5 and st["n_rhs_phph"] == 5 * 4
     assert st["n_rhs_eph"] == 4 * (8 * 4 + 5)   # 7 full + 1 cut substeps per 5 fs step; 4 + 1 in the last
+
+
+def _mis_adaptive_oracle(Pr, y0, fast_solver, rtol, a_el, a_ph, H0, t_out):
+    o = oracle.Oracle(Pr)
+    M = I.MisAdaptive(lambda v: o.rhs(v, parts=3), lambda v: o.rhs(v, parts=4), fast_solver,
+                      atol_vec(Pr["n_el"], Pr["n_ph"], a_el, a_ph),
+                      I.Controls(rtol=rtol, atol_el=a_el, atol_ph=a_ph), H=H0)
+    y, t = y0.copy(), 0.0
+    while t < t_out:
+        y, t = M.advance(y, t, t_out, one_step=True)
+    return M, y
+
+
+@pytest.mark.parametrize("fast", ["fixed", "adaptive"])
+def test_multirate_adaptive_slow_step_matches_oracle(fast):
+    """Step-doubling slow control: the same accepted slow steps (times and
+    sizes), rejections and final state as the oracle."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    rtol, a_el, a_ph, H0, t_out = 1e-6, 1e-9, 1e-11, 8.0, 40.0
+    say(f"[int] MIS with adaptive slow step, {fast} fast solver")
+    if fast == "fixed":
+        kw = dict(fast_mode=1, h_fast=0.5)
+        solver = I.rk4_fixed_solver(0.5)
+    else:
+        kw = dict(fast_mode=0, fast_rtol=1e-8, fast_atol_el=1e-11, fast_atol_ph=1e-13)
+        solver = I.AdaptiveFastSolver(atol_vec(Pr["n_el"], Pr["n_ph"], 1e-11, 1e-13),
+                                      I.Controls(rtol=1e-8, atol_el=1e-11, atol_ph=1e-13), 0.1)
+    ctx = P.Context(Pr, rtol=rtol, atol_el=a_el, atol_ph=a_ph, **kw)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hf = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")
+    hs = torch.full((1,), H0, dtype=torch.float64, device="cuda")
+    hist = []
+    while t.item() < t_out:
+        ctx.step_multirate_adaptive(y, t, hf, hs, t_out, one_step=True)
+        torch.cuda.synchronize()
+        hist.append((t.item(), hs.item()))
+    M, yr = _mis_adaptive_oracle(Pr, y0, solver, rtol, a_el, a_ph, H0, t_out)
+    assert len(hist) == M.n_accept >= 4 and M.n_reject >= 1
+    ts = np.array([h[0] for h in hist])
+    tr = np.array([h[0] for h in M.history])
+    assert ts[-1] == t_out and np.allclose(ts, tr, rtol=1e-9, atol=0)
+    assert abs(hist[-1][1] - M.H) <= 1e-6 * M.H
+    assert close(y.cpu().numpy(), yr, 1e-10)
+    st = ctx.stats()
+    assert st["n_accept"] == M.n_accept and st["n_reject"] == M.n_reject
+    assert st["n_rhs_phph"] == 9 * (M.n_accept + M.n_reject)
+
+
+def test_multirate_adaptive_arguments():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    ctx = P.Context(Pr, fast_mode=1, h_fast=0.5)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hf = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")
+    hs = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.RtbteError):
+        ctx.step_multirate_adaptive(y, t, hf, hs, 10.0)
+    assert np.array_equal(y.cpu().numpy(), y0)
+    wl = synth.build("tiny2d")
+    batch = P.Context([wl.problem_arrays(), wl.problem_arrays()], fast_mode=1, h_fast=0.5)
+    yb = to_dev(np.concatenate([wl.y0, wl.y0]))
+    hs.fill_(1.0)
+    with pytest.raises(P.RtbteError):
+        batch.step_multirate_adaptive(yb, t, hf, hs, 10.0)

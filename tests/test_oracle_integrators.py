@@ -348,3 +348,82 @@ def test_split_step_is_first_order():
         errs.append(np.linalg.norm(y - yref))
     p = np.log2(errs[1] / errs[2])
     assert 0.8 < p < 1.3, errs
+
+
+def _linear_fast_slow(n=6, seed=3):
+    """y' = A_f y + A_s y with non-commuting symmetric negative definite
+    parts (fast eigenvalues -1 .. -2, slow -0.05 .. -0.2) and the exact fast
+    flow of v' = A_f v + r (r constant): v(t) = e^{A_f t} v0 + A_f^{-1}(e^{A_f t} - I) r."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(seed)
+    Q1, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Af = Q1 @ np.diag(-np.linspace(1.0, 2.0, n)) @ Q1.T
+    As = Q2 @ np.diag(-np.linspace(0.05, 0.2, n)) @ Q2.T
+    Afi = np.linalg.inv(Af)
+
+    def exact_fast(v, t0, t1, f):
+        r = f(np.zeros(n))            # the constant forcing of the stage
+        E = expm(Af * (t1 - t0))
+        return E @ v + Afi @ ((E - np.eye(n)) @ r)
+
+    y0 = rng.uniform(0.5, 1.5, n)
+    return Af, As, exact_fast, y0, (lambda H, y: expm((Af + As) * H) @ y)
+
+
+def test_step_doubling_estimate_is_the_local_error():
+    """(y_half - y_full)/7 approaches exact - y_half as H -> 0 (MIS order 3
+    with an exact fast flow), and shrinks like H^4."""
+    Af, As, fsolve, y0, flow = _linear_fast_slow()
+    M = I.MisAdaptive(lambda v: Af @ v, lambda v: As @ v, fsolve, np.full(len(y0), 1e-12),
+                      I.Controls(rtol=1.0, atol_el=1e-12, atol_ph=1e-12))
+    sizes, ratios = [], []
+    for H in (0.4, 0.2, 0.1, 0.05):
+        yf = I.mis_step(M.fast_rhs, M.slow_rhs, y0, H, fsolve)
+        yh = I.mis_step(M.fast_rhs, M.slow_rhs, y0, H / 2, fsolve)
+        yh = I.mis_step(M.fast_rhs, M.slow_rhs, yh, H / 2, fsolve)
+        est = (yh - yf) / 7.0
+        true = flow(H, y0) - yh
+        sizes.append(np.linalg.norm(est))
+        ratios.append(np.linalg.norm(est - true) / np.linalg.norm(true))
+        # the oracle's attempt computes the same estimate
+        yh2, eps = M.attempt(y0, H)
+        assert np.array_equal(yh2, yh)
+        assert abs(eps - I.wrms(est, y0, 1.0, np.full(len(y0), 1e-12))) <= 1e-15 * eps
+    assert ratios[-1] < 0.05 and ratios[-1] < ratios[0]
+    for a, b in zip(sizes, sizes[1:]):
+        assert 12.0 < a / b < 20.0
+
+
+def test_adaptive_slow_step_meets_tolerance():
+    """Global error at t_end falls with the tolerance (error-per-step control
+    of a third-order method: about tol^(3/4), 30x per 100x), stays within a
+    modest multiple of it, and the run lands on t_end; a too-large first
+    step is rejected and recovered from."""
+    Af, As, fsolve, y0, flow = _linear_fast_slow()
+    T = 4.0   # the solution decays by e^-4: relative errors stay meaningful
+    exact = flow(T, y0)
+    errs = []
+    for rtol in (1e-4, 1e-6, 1e-8):
+        atol = np.full(len(y0), rtol * 1e-3)
+        M = I.MisAdaptive(lambda v: Af @ v, lambda v: As @ v, fsolve, atol,
+                          I.Controls(rtol=rtol, atol_el=rtol * 1e-3, atol_ph=rtol * 1e-3), H=0.5)
+        y, t = M.advance(y0.copy(), 0.0, T)
+        assert t == T and M.history[-1][0] == T
+        errs.append(np.linalg.norm(y - exact) / np.linalg.norm(exact))
+        assert errs[-1] <= 30 * rtol
+    assert errs[0] > 10 * errs[1] > 100 * errs[2]
+    M = I.MisAdaptive(lambda v: Af @ v, lambda v: As @ v, fsolve, np.full(len(y0), 1e-10),
+                      I.Controls(rtol=1e-7, atol_el=1e-10, atol_ph=1e-10), H=25.0)
+    y, t = M.advance(y0.copy(), 0.0, T)
+    assert M.n_reject >= 1 and t == T
+    assert np.linalg.norm(y - exact) / np.linalg.norm(exact) <= 30e-7
+
+
+def test_slow_controller_is_an_i_controller():
+    """eta = safety eps^(-1/4) whatever the history; limits as for the ERK."""
+    c = I.slow_controls(I.Controls())
+    for eps in (1e-3, 0.5, 0.9):
+        for e1, e2 in ((1.0, 1.0), (0.2, 3.0)):
+            assert abs(I.pid_eta(eps, e1, e2, True, False, c) - min(c.safety * eps ** -0.25, c.eta_max)) < 1e-15
+    assert I.pid_eta(50.0, 1.0, 1.0, False, False, c) == max(c.safety * 50.0 ** -0.25, c.eta_fail_min)

@@ -217,3 +217,83 @@ def test_sampled_rows_equal_full_rhs():
     rows = np.array([0, 5, wl.n_el - 1, wl.n_el, wl.n_y - 1, 77])
     out, S2, A2 = o.rhs_rows(wl.y0, rows)
     assert np.array_equal(out, full[rows]) and np.array_equal(A2, A[rows])
+
+
+def test_rates_closed_forms_in_relaxation_time_limits():
+    """Linearized rates -d(ydot_i)/d(y_i) on the two relaxation-time problems
+    equal the closed forms: (36 pi/hbar)(1/N_q) sum |V3|^2 delta(0)(N_a+N_b+1)
+    for the decaying phonons, (2 pi/hbar)(1/N_q) sum |g|^2 delta(0)(1+N-f_s)
+    for the emitting electrons."""
+    P, y0, n = problems.pp_rta()
+    o = oracle.Oracle(P)
+    g = o.rates(y0, parts=4)
+    na, nb = y0[1 + P["pp_a"]], y0[1 + P["pp_b"]]
+    pref = 36.0 * np.pi / synth.HBAR_EV_FS / P["n_q_total"] / (P["sigma_pp"] * np.sqrt(np.pi))
+    for i in range(n):
+        sel = P["pp_row"] == i
+        assert np.isclose(g[1 + i], pref * np.sum(P["pp_v2"][sel] * (na[sel] + nb[sel] + 1)), rtol=1e-13)
+    P, y0, n = problems.eph_rta()
+    o = oracle.Oracle(P)
+    g = o.rates(y0, parts=1)
+    n_el = P["n_el"]
+    fs, Np = y0[P["eph_partner"]], y0[n_el + P["eph_phonon"]]
+    pref = 2.0 * np.pi / synth.HBAR_EV_FS / P["n_q_total"] / (P["sigma_eph"] * np.sqrt(np.pi))
+    for i in range(n):
+        sel = P["eph_row"] == i
+        assert np.isclose(g[i], pref * np.sum(P["eph_g2"][sel] * (1 + Np[sel] - fs[sel])), rtol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "tiny3d", "toy2d"])
+def test_rates_are_the_jacobian_diagonal(name):
+    """Every occupation factor is affine in the row's own population, so once
+    the entries whose partner is the row's own state are dropped (e-ph
+    s = r, ph-ph a = row or b = row: there the partners-fixed rate and the
+    Jacobian diagonal differ by construction), the rates are the Jacobian
+    diagonal, and the central difference of row i of the right-hand side in
+    y_i equals them up to rounding on every row (d = 1e-4; the difference
+    rounds at ~1e-16 A_i / d)."""
+    wl = synth.build(name)
+    P = dict(wl.problem_arrays())
+    ke = P["eph_partner"] != P["eph_row"]
+    kp = (P["pp_a"] != P["pp_row"]) & (P["pp_b"] != P["pp_row"])
+    for k in ("eph_row", "eph_partner", "eph_phonon", "eph_g2"):
+        P[k] = P[k][ke]
+    for k in ("pp_row", "pp_a", "pp_b", "pp_v2"):
+        P[k] = P[k][kp]
+    o = oracle.Oracle(P)
+    rng = np.random.default_rng(4)
+    y = np.concatenate([rng.uniform(0.05, 0.95, wl.n_el), rng.uniform(0.0, 2.0, wl.n_ph)])
+    d = 1e-4
+    checked = 0
+    for parts in (1, 2, 4):
+        g = o.rates(y, parts=parts)
+        A = o.rhs(y, parts=parts, scales=True)[2]
+        for i in range(wl.n_y):
+            if A[i] == 0.0:
+                assert g[i] == 0.0
+                continue
+            yp, ym = y.copy(), y.copy()
+            yp[i] += d; ym[i] -= d
+            fd = -(o.rhs(yp, parts=parts)[i] - o.rhs(ym, parts=parts)[i]) / (2 * d)
+            assert abs(fd - g[i]) <= 1e-9 * abs(g[i]) + 1e-10 * A[i], (parts, i, fd, g[i])
+            checked += 1
+    assert checked > 100
+
+
+def test_observables_definitions():
+    """Energy averages: constant populations average to the constant in every
+    occupied bin, the counts add up to the states inside the range, and the
+    change against the same state is zero.  Mode temperatures: Bose-Einstein
+    populations at T0 give back T0; hotter populations give a higher T."""
+    from oracle import observables as obs
+    wl = synth.build("tiny2d")
+    c, m, d = obs.energy_average(wl.eps, np.full(wl.n_el, 0.3), -5.0, 5.0, 40, ref=np.full(wl.n_el, 0.3))
+    assert c.sum() == np.sum((wl.eps >= -5.0) & (wl.eps < 5.0))
+    assert np.allclose(m[c > 0], 0.3, rtol=0, atol=1e-15) and np.all(d == 0.0)
+    modes = np.arange(wl.n_ph) % wl.grid["n_modes"]
+    for T0 in (150.0, 300.0, 1200.0):
+        N = synth.bose_einstein(wl.hw, T0)
+        T = obs.mode_temperature(wl.hw, N, modes, wl.grid["n_modes"])
+        assert np.allclose(T, T0, rtol=1e-10)
+        T2 = obs.mode_temperature(wl.hw, N * 1.1, modes, wl.grid["n_modes"])
+        assert np.all(T2 > T)
