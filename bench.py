@@ -78,10 +78,25 @@ def cpu_baseline(wl, seconds):
         if el >= seconds:
             break
     assert np.all(np.isfinite(ynew))
-    return o, dict(value=n * 5 * ch / el, unit="channels/s", cores=oracle.threads(), kind="oracle",
+    cores = oracle.threads()
+    # one thread: a single full right-hand side of the same state
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    o.rhs(y)
+    el1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return o, dict(value=n * 5 * ch / el, unit="channels/s", cores=cores, kind="oracle",
                    sample=f"{n} Zonneveld ERK attempt(s) = {5 * n} full right-hand sides of the "
                           f"same workload from its initial state ({el:.1f} s; list build {build_s:.1f} s "
-                          f"untimed)")
+                          f"untimed)",
+                   one_thread_value=ch / el1, one_thread_sample=f"1 full right-hand side ({el1:.1f} s)",
+                   cpu_model=model)
 
 
 def main():
@@ -179,6 +194,8 @@ def main():
     fmt = ctx.weight_format()
     rec["config"]["fp64_channel_bytes"] = fmt[1]
     rec["config"]["fp64_weight_rounding"] = fmt[2]
+    rec["roofline"]["launch_spread"] = launch_spread(ctx, torch, leg["y"])
+    rec["achievable"] = achievable_bandwidth(torch)
 
     if not args.no_plain:
         # the same steps with the plain 16-byte FP64 channels (two 32-bit
@@ -217,10 +234,10 @@ def main():
             "speedup_rhs_kernel_vs_fp64": k["avg_launch_ms"] / km["avg_launch_ms"],
             "rhs_per_step": leg_m["rhs_per_step"],
             "t_span_fs": leg_m["t_span"], "fp64_t_span_fs": leg["t_span"],
-            "dtype": "weights FP16 head + 11-bit tail (22 significant bits) with per-512 FP32 scales; "
-                     "FP32 population codes, products and compensated lane sums; FP64 state, stages, "
-                     "WRMS and control",
-            "roofline": dict(km, traffic=tm),
+            "dtype": f"weights in {ctx_m.weight_format()[1]}-byte packed channels (relative rounding "
+                     f"{ctx_m.weight_format()[2]:.2g}) with per-512 FP32 scales; FP32 population codes, "
+                     "products and compensated lane sums; FP64 state, stages, WRMS and control",
+            "roofline": dict(km, traffic=tm, launch_spread=launch_spread(ctx_m, torch, leg_m["y"])),
             "create_s": create_m,
         }
 
@@ -252,6 +269,44 @@ def main():
         torch.cuda.empty_cache()
         rec["si3d"] = si3d_leg(P, torch, np, args)
     print(json.dumps(rec), flush=True)
+
+
+def launch_spread(ctx, torch, y, reps=20):
+    """Per-launch times of the collision kernel (HIP events on its stream)
+    over `reps` full right-hand sides: median, p10 and p90 in ms."""
+    import numpy as np
+    out = torch.empty_like(y)
+    ms = []
+    for _ in range(reps):
+        ctx.profile(True)
+        ctx.rhs(y, out, 7)
+        k_ms, k_n, _ = ctx.profile_read()
+        ms.append(k_ms / max(k_n, 1))
+    ctx.profile(False)
+    return {"reps": reps, "median_ms": float(np.median(ms)), "p10_ms": float(np.percentile(ms, 10)),
+            "p90_ms": float(np.percentile(ms, 90))}
+
+
+def achievable_bandwidth(torch, gib=4):
+    """What plain library kernels reach on this GPU: a read-only reduction
+    and a device copy over `gib` GiB (the ceiling a streaming kernel can
+    expect in practice, beside the 8 TB/s peak)."""
+    x = torch.ones((gib << 30) // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    res = {}
+    for name, fn, nbytes in (("read_sum", lambda: x.sum(), x.numel() * 8),
+                             ("copy", lambda: y.copy_(x), 2 * x.numel() * 8)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_GBps"] = nbytes * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return res
 
 
 def kernel_roofline(ctx, torch, y, parts, reps=3):

@@ -183,6 +183,12 @@ typedef struct {
                                and within 2^-43 relative for P <= 19; arithmetic stays
                                FP64) or RTBTE_F64_PLAIN (16 bytes: two 32-bit indices and
                                the FP64 weight)                                              */
+  int32_t fp64_check;       /* RTBTE_MIXED only.  0 (default): off.  K > 0: the context also
+                               keeps the FP64 lists (packed when instances have at most 2^19
+                               states, else plain: 12 or 16 more bytes per channel) so that
+                               rtbte_check_fp64 can measure the mixed right-hand side against
+                               FP64, and the stepping calls do so at every K-th poll,
+                               reporting the last value in rtbte_stats.err_vs_fp64_last     */
 } rtbte_options;
 
 enum { RTBTE_F64_AUTO = 0, RTBTE_F64_PACKED = 1, RTBTE_F64_PLAIN = 2 };
@@ -193,6 +199,8 @@ typedef struct {
   int64_t n_fast_accept, n_fast_reject;     /* fast steps inside MIS                    */
   double t, h_last, h_min, h_max, eps_last;
   int32_t status;                           /* RTBTE_* status of the last stepping call */
+  double err_vs_fp64_last;                  /* last ||f_mixed - f_fp64|| / ||f_fp64|| of
+                                               this instance (fp64_check); -1: none     */
 } rtbte_stats;
 
 void rtbte_default_options(rtbte_options *opts);
@@ -231,6 +239,16 @@ int rtbte_rhs(rtbte_ctx *ctx, const double *y, double *ydot, int32_t parts, void
  * Same device buffers and stream as rtbte_rhs.  RTBTE_FP64 contexts only
  * (RTBTE_E_UNSUPPORTED otherwise). */
 int rtbte_rates(rtbte_ctx *ctx, const double *y, double *rates, int32_t parts, void *stream);
+
+/* The mixed-precision right-hand side at the device state y against the
+ * FP64 one from the lists an RTBTE_MIXED context keeps when created with
+ * fp64_check > 0: err[inst] (HOST, n_inst doubles, may be NULL) =
+ * ||f_mixed(y) - f_fp64(y)|| / ||f_fp64(y)|| in the 2-norm over each
+ * instance's rows (0 when both vanish).  Also recorded for rtbte_stats.
+ * Two right-hand sides, not counted in the statistics; synchronizes
+ * `stream`.  RTBTE_E_UNSUPPORTED for FP64 contexts and for mixed contexts
+ * without the FP64 lists. */
+int rtbte_check_fp64(rtbte_ctx *ctx, const double *y, double *err, void *stream);
 
 /* Energy-resolved averages of one instance's populations (the zone averages
  * the paper plots beside the band structure and the phonon dispersion,

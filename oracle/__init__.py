@@ -77,6 +77,7 @@ def _lib():
         L.orc_brute_rhs.argtypes = ([ctypes.c_int] * 7 + [ctypes.c_void_p] * 5 +
                                     [ctypes.c_double] * 4 + [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int])
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _LIB = L
     return _LIB
 
@@ -87,6 +88,11 @@ def _p(a):
 
 def threads() -> int:
     return int(_lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops."""
+    _lib().orc_set_threads(int(n))
 
 
 class Oracle:

@@ -482,6 +482,16 @@ void orc_brute_rhs(int dim, int L, int n_bands, int n_modes, int n_k_total, int 
   }
 }
 
+/* Thread count of the OpenMP loops (timing of the oracle with one thread). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int orc_threads(void) {
 #ifdef _OPENMP
   extern int omp_get_max_threads(void);

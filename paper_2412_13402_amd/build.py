@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librtbte.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "diagnostics.hip", "api.hip")]
 
 
 def hipcc_command(out=LIB, arch="gfx950"):

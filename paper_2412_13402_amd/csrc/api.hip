@@ -22,6 +22,11 @@
 
 using namespace rtbte;
 
+namespace rtbte {
+hipError_t launch_diff_norms(const double* a, const double* b, const InstInfo* info, double* partial, int n_inst,
+                             int nchunk, hipStream_t s);
+}
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -115,6 +120,10 @@ struct rtbte_ctx {
   bool mixed = false;
   int wfmt = -1;                  // weight format in use (RTBTE_W_*); FP64: -1 plain, -2 packed
   int pack_p = 0, pack_m = 0;     // packed layouts: position and mantissa bits
+  int f64_m = 0;                  // FP64 packed lists: mantissa bits kept
+  bool keep64 = false;            // a mixed context that also holds the FP64 lists
+  std::vector<double> err64;      // [n_inst] last mixed-vs-FP64 right-hand-side difference (-1: none)
+  int64_t polls = 0;              // polls since the last periodic FP64 check
   uint64_t* pk = nullptr;         // FP64 packed: 8-byte words
   uint32_t* pkw = nullptr;        // FP64 packed: low weight words
   int2* mix_idx = nullptr;
@@ -226,6 +235,7 @@ void rtbte_default_options(rtbte_options* o) {
   o->tune = 0;
   o->tune_cache = nullptr;
   o->fp64_layout = RTBTE_F64_AUTO;
+  o->fp64_check = 0;
 }
 
 const char* rtbte_last_error(const rtbte_ctx* ctx) {
@@ -439,6 +449,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   if (!valid_group_rows(o.group_rows_el) || !valid_group_rows(o.group_rows_ph))
     return fail(nullptr, RTBTE_E_INVAL, "group_rows_el / group_rows_ph must be 0, 1, 2, 4, 8, 12 or 16");
   if (o.item_channels < 0) return fail(nullptr, RTBTE_E_INVAL, "item_channels must be >= 0");
+  if (o.fp64_check < 0) return fail(nullptr, RTBTE_E_INVAL, "fp64_check must be >= 0");
   if (!(o.rtol >= 0) || !(o.atol_el >= 0) || !(o.atol_ph >= 0) || o.pid_order <= 0 ||
       o.steps_per_poll < 1 || o.max_fails < 0)
     return fail(nullptr, RTBTE_E_INVAL, "invalid tolerances or controller options");
@@ -492,6 +503,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     c->wfmt = pk ? -2 : -1;
     c->pack_p = pk ? P : 0;
     c->pack_m = pk ? std::min(80 - 2 * P, 52) : 0;
+    c->f64_m = c->pack_m;
   }
   if (o.precision == RTBTE_MIXED) {
     // weight format: the packed 8-byte words need P-bit positions relative to
@@ -511,7 +523,12 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     c->wfmt = w;
     c->pack_p = P;
     c->pack_m = std::min(53 - 2 * P, 23);   // at most FP32's 23 mantissa bits; spare high bits stay 0
+    // FP64 lists kept for the mixed-vs-FP64 check: packed when P <= 19 (the
+    // FP64 default), else the plain 16-byte channels
+    c->keep64 = o.fp64_check > 0;
+    c->f64_m = c->keep64 && P <= 19 ? std::min(80 - 2 * P, 52) : 0;
   }
+  c->err64.assign((size_t)n_inst, -1.0);
   c->counts.assign(3 * (size_t)n_inst, 0);
 
   // Pass 1: upload raw entries and count kept channels per destination group.
@@ -619,9 +636,10 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     int64_t pos = 0;
     for (int i = 0; i < n_inst; ++i) {
       // every instance starts on a 512-channel boundary (the slots between
-      // instances are never read), so mixed-precision scale blocks never
-      // straddle two instances: an instance is stored, and computes, exactly
-      // as it would alone
+      // instances hold zeros and are only read by masked-off lanes), so
+      // mixed-precision scale blocks and the 256-channel tiles of the FP64
+      // packed stream never straddle two instances: an instance is stored,
+      // and computes, exactly as it would alone
       pos = (pos + kMixBlock - 1) / kMixBlock * kMixBlock;
       const InstInfo& in = c->info[i];
       const int32_t nge = (int32_t)cnt_e[i].size(), ngp = (int32_t)cnt_pe[i].size();
@@ -723,20 +741,22 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
       e = launch_mix_convert(c->ch, c->n_ch, c->groups, c->n_groups, c->mix_scale, c->wfmt, c->mix_idx,
                              c->mix_wq, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e == hipSuccess) {
+    if (e == hipSuccess && !c->keep64) {
       e = hipFree(c->ch);
       c->ch = nullptr;
     }
     c->mixed = true;
   }
-  if (e == hipSuccess && c->wfmt == -2) {
+  if (e == hipSuccess && (c->mixed ? c->f64_m > 0 : c->wfmt == -2)) {
     // FP64 packed channels; the 16-byte channels are freed
     c->pk = dalloc<uint64_t>((size_t)c->n_ch + 2, &e);
-    if (e == hipSuccess) c->pkw = dalloc<uint32_t>((size_t)c->n_ch + 4, &e);
+    // low weight words: whole 256-channel tiles (read a tile at a time)
+    const size_t nw = ((size_t)c->n_ch + 255) / 256 * 256 + 256;
+    if (e == hipSuccess) c->pkw = dalloc<uint32_t>(nw, &e);
     if (e == hipSuccess) e = hipMemset(c->pk, 0, ((size_t)c->n_ch + 2) * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMemset(c->pkw, 0, ((size_t)c->n_ch + 4) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(c->pkw, 0, nw * sizeof(uint32_t));
     if (e == hipSuccess)
-      e = launch_pack12(c->ch, c->n_ch, c->groups, c->n_groups, c->info_d, c->pack_p, c->pack_m, c->pk, c->pkw, 0);
+      e = launch_pack12(c->ch, c->n_ch, c->groups, c->n_groups, c->info_d, c->pack_p, c->f64_m, c->pk, c->pkw, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) {
       e = hipFree(c->ch);
@@ -859,7 +879,7 @@ extern "C" int rtbte_get_weight_format(const rtbte_ctx* c, int32_t* format, int3
                                        double* weight_rounding) {
   if (!c) return RTBTE_E_INVAL;
   int32_t f = c->wfmt, b = c->wfmt == -2 ? 12 : 16;
-  double u = c->wfmt == -2 && c->pack_m < 52 ? std::ldexp(1.0, -(c->pack_m + 1)) : 0.0;
+  double u = c->wfmt == -2 && c->f64_m < 52 ? std::ldexp(1.0, -(c->f64_m + 1)) : 0.0;
   if (c->mixed) {
     b = f == RTBTE_W_PACK8 ? 8 : 10;
     u = f == RTBTE_W_PACK8 ? std::ldexp(1.0, -(c->pack_m + 1))
@@ -910,15 +930,17 @@ hipError_t harvest(rtbte_ctx* c) {
 // The right-hand side in two launches: per-item row sums (the collision
 // kernel, the one that streams the channels and is timed when profiling),
 // then the per-row sums of items with the plain or stage epilogue.
+// fp64: use the FP64 lists of a mixed context that keeps them (not timed).
 hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState* st, const FinishArgs& f,
-                      bool stage, hipStream_t s, bool deriv = false) {
+                      bool stage, hipStream_t s, bool deriv = false, bool fp64 = false) {
+  const bool use_mixed = c->mixed && !fp64;
   RowArgs a{};
   a.deriv = deriv ? 1 : 0;
   a.ch = c->ch;
   a.pk = c->pk;
   a.pkw = c->pkw;
   a.pack_p = c->pack_p;
-  a.pack_m = c->pack_m;
+  a.pack_m = c->f64_m;
   a.info = c->info_d;
   a.groups = c->groups;
   a.items = c->items;
@@ -929,7 +951,7 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
   a.partial = c->partial_items;
   a.st = st;
   MixArgs m{};
-  if (c->mixed) {
+  if (use_mixed) {
     m.idx = c->mix_idx;
     m.wq = c->mix_wq;
     m.scale = c->mix_scale;
@@ -948,12 +970,12 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
     m.st = st;
   }
   auto launch = [&]() {
-    if (!c->mixed) return launch_items(a, c->slots, s);
+    if (!use_mixed) return launch_items(a, c->slots, s);
     hipError_t e2 = launch_popf(c->popf, z, c->row_group, c->groups, c->ny, s);
     return e2 == hipSuccess ? launch_items_mixed(m, c->slots, s) : e2;
   };
   hipError_t e;
-  if (!c->prof) {
+  if (!c->prof || fp64) {
     e = launch();
   } else {
     std::pair<hipEvent_t, hipEvent_t> ev;
@@ -981,6 +1003,46 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
 }
 
 }  // namespace
+
+namespace {
+
+// Mixed-precision right-hand side against the FP64 lists kept beside it, at
+// the state y: err64[inst] = ||f_mixed - f_fp64|| / ||f_fp64|| (2-norms over
+// the instance's rows).  Diagnostic launches: not counted, not timed.
+int check_fp64(rtbte_ctx* c, const double* y, hipStream_t s) {
+  FinishArgs f{};
+  f.out = c->tmp;
+  HIPCHK(c, rhs_launch(c, y, RTBTE_PART_ALL, nullptr, f, false, s));
+  f.out = c->tmp2;
+  HIPCHK(c, rhs_launch(c, y, RTBTE_PART_ALL, nullptr, f, false, s, false, true));
+  HIPCHK(c, launch_diff_norms(c->tmp, c->tmp2, c->info_d, c->partial, c->n_inst, c->nchunk, s));
+  std::vector<double> part(2 * (size_t)c->n_inst * c->nchunk);
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int i = 0; i < c->n_inst; ++i) {
+    double d2 = 0.0, b2 = 0.0;
+    for (int j = 0; j < c->nchunk; ++j) {
+      d2 += part[2 * ((size_t)i * c->nchunk + j)];
+      b2 += part[2 * ((size_t)i * c->nchunk + j) + 1];
+    }
+    c->err64[(size_t)i] = b2 > 0.0 ? std::sqrt(d2 / b2) : (d2 > 0.0 ? INFINITY : 0.0);
+  }
+  return RTBTE_OK;
+}
+
+}  // namespace
+
+extern "C" int rtbte_check_fp64(rtbte_ctx* c, const double* y, double* err, void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (!c->mixed || !c->keep64)
+    return fail(c, RTBTE_E_UNSUPPORTED, "rtbte_check_fp64 needs an RTBTE_MIXED context created with fp64_check > 0");
+  if (!y) return fail(c, RTBTE_E_INVAL, "rtbte_check_fp64: bad arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = check_fp64(c, y, (hipStream_t)stream);
+  if (rc == RTBTE_OK && err)
+    for (int i = 0; i < c->n_inst; ++i) err[i] = c->err64[(size_t)i];
+  return rc;
+}
 
 extern "C" int rtbte_rates(rtbte_ctx* c, const double* y, double* rates, int32_t parts, void* stream) {
   if (!c) return RTBTE_E_INVAL;
@@ -1193,6 +1255,11 @@ int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_ste
     }
     int rc = poll(c, st, t, h, s, &done, &worst);
     if (rc) return rc;
+    if (c->keep64 && ++c->polls >= c->opt.fp64_check) {
+      c->polls = 0;
+      rc = check_fp64(c, y, s);
+      if (rc) return rc;
+    }
   }
   c->last_status = worst;
   if (worst == RTBTE_E_STEP) return fail(c, RTBTE_E_STEP, "too many consecutive error-test failures");
@@ -1467,6 +1534,7 @@ extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* ou
   out->h_min = s.h_min;
   out->h_max = s.h_max;
   out->eps_last = s.eps;
+  out->err_vs_fp64_last = c->err64[(size_t)inst];
   out->status = c->last_status;
   return RTBTE_OK;
 }

@@ -1,0 +1,48 @@
+// Diagnostics outside the collision kernels: the normwise difference of two
+// right-hand sides per instance (the mixed-precision path against the FP64
+// lists kept beside it).
+#include "internal.h"
+
+namespace rtbte {
+
+// Per-instance sums of (a_i - b_i)^2 and b_i^2; grid (nchunk, n_inst), fixed
+// summation order: partial[2 (inst nchunk + chunk) + {0, 1}].
+__global__ __launch_bounds__(256) void k_diff_norms(const double* __restrict__ a, const double* __restrict__ b,
+                                                    const InstInfo* info, double* partial, int nchunk) {
+  __shared__ double red[2][4];
+  const int inst = blockIdx.y;
+  const InstInfo in = info[inst];
+  const int64_t n = (int64_t)in.n_el + in.n_ph;
+  const int64_t cs = (n + nchunk - 1) / nchunk;
+  const int64_t lo = (int64_t)blockIdx.x * cs;
+  const int64_t hi = lo + cs < n ? lo + cs : n;
+  double d2 = 0.0, b2 = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double bb = b[in.off + i], d = a[in.off + i] - bb;
+    d2 += d * d;
+    b2 += bb * bb;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 += __shfl_xor(d2, o, 64);
+    b2 += __shfl_xor(b2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x / 64] = d2;
+    red[1][threadIdx.x / 64] = b2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t k = 2 * ((int64_t)inst * nchunk + blockIdx.x);
+    partial[k] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    partial[k + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+hipError_t launch_diff_norms(const double* a, const double* b, const InstInfo* info, double* partial, int n_inst,
+                             int nchunk, hipStream_t s) {
+  if (n_inst <= 0 || nchunk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diff_norms, dim3(nchunk, n_inst), dim3(256), 0, s, a, b, info, partial, nchunk);
+  return hipGetLastError();
+}
+
+}  // namespace rtbte

@@ -152,32 +152,32 @@ __device__ __forceinline__ void chan_p12(LaneAcc<G>& acc, uint32_t lo, uint32_t 
   acc.add(tag, term_w<KIND, DERIV>(em, w, g0, g1, xr, xr1));
 }
 
-// Channels [s, e) of one kind from the packed FP64 stream, read as channel
-// pairs (16 B of words and 8 B of low weight words), lanes on consecutive
-// pairs, two pairs 64 apart per lane per batch (whole lines per load), with
-// the two-stage pipeline of seg_sum.  `off` is the instance's offset in z.
+// Channels [s, e) of one kind from the packed FP64 stream in batches of one
+// 256-channel tile: the words are read as channel pairs (16 B), lanes on
+// consecutive pairs, two pairs 64 apart per lane, and the low weight words of
+// a lane's four channels as one 16-byte load (the tile-permuted order written
+// by k_pack12), so every load instruction covers whole lines; two-stage
+// pipeline as in seg_sum.  Batches start on tile boundaries (channels before
+// s are masked off; tiles never straddle instances).  `off` is the
+// instance's offset in z.
 template <int G, int KIND, bool DERIV>
 __device__ __forceinline__ void seg_sum_p12(LaneAcc<G>& acc, const RowArgs& a, int64_t s, int64_t e, int lane,
                                             const double* __restrict__ z, const double* rowv, uint32_t off) {
   if (s >= e) return;
   const v4u* A2 = reinterpret_cast<const v4u*>(a.pk);
-  const v2u* B2 = reinterpret_cast<const v2u*>(a.pkw);
+  const v4u* B4 = reinterpret_cast<const v4u*>(a.pkw);
   const int P = a.pack_p, sh = 52 - a.pack_m;
   const uint32_t pmask = (1u << P) - 1u;
-  const int64_t p_end = (e + 1) / 2;          // pairs [s / 2, p_end)
-  int64_t pb = s / 2;                          // first pair of the batch (wave-uniform)
+  const int64_t p_end = (e + 1) / 2;           // pairs [s / 2, p_end)
+  int64_t pb = (s / 2) & ~(int64_t)127;        // first pair of the batch (wave-uniform, tile-aligned)
   v4u c[2];
-  v2u wl[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int64_t q = pb + lane + 64 * j;
     c[j] = v4u{0u, 0u, 0u, 0u};
-    wl[j] = v2u{0u, 0u};
-    if (q < p_end) {
-      c[j] = __builtin_nontemporal_load(A2 + q);
-      wl[j] = __builtin_nontemporal_load(B2 + q);
-    }
+    if (q < p_end) c[j] = __builtin_nontemporal_load(A2 + q);
   }
+  v4u wl = __builtin_nontemporal_load(B4 + pb / 2 + lane);   // the tile is allocated whole
   for (;;) {
     double g0[4], g1[4];
 #pragma unroll
@@ -190,35 +190,30 @@ __device__ __forceinline__ void seg_sum_p12(LaneAcc<G>& acc, const RowArgs& a, i
     const int64_t nb = pb + 128;
     const bool more = nb < p_end;
     v4u n[2];
-    v2u m[2];
+    v4u m = v4u{0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      n[j] = v4u{0u, 0u, 0u, 0u};
-      m[j] = v2u{0u, 0u};
-    }
+    for (int j = 0; j < 2; ++j) n[j] = v4u{0u, 0u, 0u, 0u};
     if (more) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int64_t q = nb + lane + 64 * j;
-        if (q < p_end) {
-          n[j] = __builtin_nontemporal_load(A2 + q);
-          m[j] = __builtin_nontemporal_load(B2 + q);
-        }
+        if (q < p_end) n[j] = __builtin_nontemporal_load(A2 + q);
       }
+      m = __builtin_nontemporal_load(B4 + nb / 2 + lane);
     }
+    const uint32_t wlo[4] = {wl.x, wl.y, wl.z, wl.w};
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t ca = 2 * (pb + lane + 64 * j);
-      if (ca >= s && ca < e) chan_p12<G, KIND, DERIV>(acc, c[j].x, c[j].y, wl[j].x, g0[2 * j], g1[2 * j], rowv, P, sh);
+      if (ca >= s && ca < e)
+        chan_p12<G, KIND, DERIV>(acc, c[j].x, c[j].y, wlo[2 * j], g0[2 * j], g1[2 * j], rowv, P, sh);
       if (ca + 1 >= s && ca + 1 < e)
-        chan_p12<G, KIND, DERIV>(acc, c[j].z, c[j].w, wl[j].y, g0[2 * j + 1], g1[2 * j + 1], rowv, P, sh);
+        chan_p12<G, KIND, DERIV>(acc, c[j].z, c[j].w, wlo[2 * j + 1], g0[2 * j + 1], g1[2 * j + 1], rowv, P, sh);
     }
     if (!more) break;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      c[j] = n[j];
-      wl[j] = m[j];
-    }
+    for (int j = 0; j < 2; ++j) c[j] = n[j];
+    wl = m;
     pb = nb;
   }
 }
@@ -337,7 +332,10 @@ __global__ void k_pack12(const Channel* ch, int64_t n_ch, const Group* groups, i
   const uint32_t w_lo = p0 | (tag << P) | ((whigh & ((1u << na) - 1u)) << (P + 4));
   const uint32_t w_hi = p1 | (em << P) | ((whigh >> na) << (P + 1));
   pk[c] = ((uint64_t)w_hi << 32) | w_lo;
-  pkw[c] = (uint32_t)bits;
+  // low weight words in tile-permuted order: within each 256-channel tile,
+  // lane l's channels 2l, 2l + 1, 128 + 2l, 129 + 2l sit at 4l .. 4l + 3
+  const int64_t r = c & 255;
+  pkw[(c & ~(int64_t)255) | (((r & 127) >> 1) << 2) | ((r >> 7) << 1) | (r & 1)] = (uint32_t)bits;
 }
 
 hipError_t launch_pack12(const Channel* ch, int64_t n_ch, const Group* groups, int64_t n_groups,

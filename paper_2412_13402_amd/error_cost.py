@@ -163,6 +163,8 @@ def main(argv=None):
     ap.add_argument("--rk4-min-h", type=float, default=0.01)
     ap.add_argument("--mri-min-hs", type=float, default=0.05)
     ap.add_argument("--quick", action="store_true", help="a few points per method")
+    ap.add_argument("--methods", default="rk4,erk,mri,split,mria",
+                    help="comma-separated subset of rk4, erk, mri, split, mria (MRI with adaptive slow step)")
     ap.add_argument("--out", default=None, help="write the JSON result here")
     ap.add_argument("--ref-save", default=None, help="save the reference states (.npz)")
     ap.add_argument("--ref-load", default=None, help="reuse reference states saved by --ref-save")
@@ -195,15 +197,16 @@ def main(argv=None):
             H.rows.append(dict(method=label.split()[0], params=label, failed=str(e)))
             log(f"  {label}: failed ({e})")
 
-    for h in rk4:
+    methods = set(a.methods.split(","))
+    for h in rk4 if "rk4" in methods else ():
         attempt(f"RK4 h={h:g}", H.rk4, h)
-    for rt in erk:
+    for rt in erk if "erk" in methods else ():
         attempt(f"ERK rtol={rt:g}", H.erk, rt, history=(rt == 1e-5))
-    for hs, rt in mri:
+    for hs, rt in mri if "mri" in methods else ():
         attempt(f"MRI h_s={hs:g} rtol={rt:g}", H.mri, hs, rt)
-    for hf, hs in SPLIT:
+    for hf, hs in SPLIT if "split" in methods else ():
         attempt(f"split {hf:g}/{hs:g}", H.split, hf, hs)
-    for rt in (MRIA_RTOL[::2] if a.quick else MRIA_RTOL):
+    for rt in (MRIA_RTOL[::2] if a.quick else MRIA_RTOL) if "mria" in methods else ():
         attempt(f"MRI-adaptive rtol={rt:g}", H.mri_adaptive, rt)
     res["runs"] = H.rows
     text = json.dumps(res)

@@ -66,6 +66,7 @@ class Options(ctypes.Structure):
         ("group_rows_ph", ctypes.c_int32), ("item_channels", ctypes.c_int64),
         ("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
         ("fp64_layout", ctypes.c_int32),
+        ("fp64_check", ctypes.c_int32),
     ]
 
 
@@ -76,6 +77,7 @@ class Stats(ctypes.Structure):
         ("n_fast_accept", ctypes.c_int64), ("n_fast_reject", ctypes.c_int64),
         ("t", ctypes.c_double), ("h_last", ctypes.c_double), ("h_min", ctypes.c_double),
         ("h_max", ctypes.c_double), ("eps_last", ctypes.c_double), ("status", ctypes.c_int32),
+        ("err_vs_fp64_last", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -112,6 +114,7 @@ def load():
     L.rtbte_counts.argtypes = [_vp, i32, ctypes.POINTER(i64)]
     L.rtbte_rhs.argtypes = [_vp, _vp, _vp, i32, _vp]
     L.rtbte_rates.argtypes = [_vp, _vp, _vp, i32, _vp]
+    L.rtbte_check_fp64.argtypes = [_vp, _vp, _vp, _vp]
     L.rtbte_energy_average.argtypes = [_vp, _vp, _vp, i32, i32, dbl, dbl, i32, _vp, _vp]
     L.rtbte_mode_temperatures.argtypes = [_vp, _vp, i32, _vp, i32, _vp, _vp]
     L.rtbte_step_adaptive.argtypes = [_vp, _vp, _vp, _vp, dbl, i32, _vp]
@@ -236,6 +239,14 @@ class Context:
         """Linearized rates -d(ydot_i)/d(y_i), partners held fixed (FP64 contexts)."""
         self._check(load().rtbte_rates(self._h, _dptr(y, self.ny, "y"), _dptr(out, self.ny, "rates"),
                                        int(parts), _stream(stream)))
+
+    def check_fp64(self, y, stream=None):
+        """Per instance ||f_mixed(y) - f_fp64(y)|| / ||f_fp64(y)|| (mixed
+        contexts created with fp64_check > 0)."""
+        out = np.empty(self.n_inst, dtype=np.float64)
+        self._check(load().rtbte_check_fp64(self._h, _dptr(y, self.ny, "y"), out.ctypes.data_as(_vp),
+                                            _stream(stream)))
+        return out
 
     def energy_average(self, y, e_lo, e_hi, n_bins, phonons=False, y_ref=None, inst=0, stream=None):
         """Per energy bin: (state count, mean population, mean of y - y_ref)

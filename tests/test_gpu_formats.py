@@ -98,3 +98,27 @@ def test_mixed_packed_at_2_20_states_and_f16x_beyond():
     check(ctx2, prob2, y2, False)
     with pytest.raises(P.RtbteError):
         P.Context(prob2, precision=P.rtbte.MIXED, mixed_weights=P.rtbte.W_PACK8)
+
+
+@pytest.mark.parametrize("n_log2", [19, 20])
+def test_fp64_check_keeps_the_fp64_layout_of_the_size(n_log2):
+    """A mixed context with fp64_check keeps packed FP64 lists up to 2^19
+    states and plain ones beyond; its check equals the host difference of
+    the mixed right-hand side and an FP64 context's."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    n = 1 << n_log2
+    prob, y = many_states(1000, n - 1000, seed=4)
+    say(f"[formats] FP64 check at 2^{n_log2} states")
+    cm = P.Context(prob, precision=P.rtbte.MIXED, fp64_check=1)
+    cd = P.Context(prob)
+    assert cd.weight_format()[0] == (-2 if n_log2 <= 19 else -1)
+    yd = to_dev(y)
+    gm, gd = torch.empty_like(yd), torch.empty_like(yd)
+    cm.rhs(yd, gm, P.PART_ALL)
+    cd.rhs(yd, gd, P.PART_ALL)
+    torch.cuda.synchronize()
+    a, b = gm.cpu().numpy(), gd.cpu().numpy()
+    e_host = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    e = cm.check_fp64(yd)[0]
+    assert abs(e - e_host) <= 1e-12 * e_host and 0 < e < 1e-3   # 13-15 mantissa bits here

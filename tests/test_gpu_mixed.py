@@ -185,3 +185,54 @@ def test_mixed_adaptive_run_tracks_fp64():
     # both runs are within tolerance of the exact solution; their distance is
     # tolerance-sized
     assert np.max(np.abs(res[P.rtbte.MIXED] - res[P.rtbte.FP64])) <= 1e-4
+
+
+def _host_rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_fp64_check_equals_the_two_paths():
+    """A mixed context keeping the FP64 lists reports ||f_mixed - f_fp64|| /
+    ||f_fp64||: the same value as the mixed and the FP64 contexts' right-hand
+    sides give on the host, within 1e-4; stepping records it at the polls
+    without counting its evaluations."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = wl_of("medium2d")
+    say("[mixed] FP64 check")
+    cm = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED, fp64_check=1, steps_per_poll=4)
+    cd = P.Context(wl.problem_arrays())
+    y = to_dev(random_state(wl, 7))
+    gm = torch.empty_like(y)
+    gd = torch.empty_like(y)
+    cm.rhs(y, gm, 7)
+    cd.rhs(y, gd, 7)
+    torch.cuda.synchronize()
+    e_host = _host_rel(gm.cpu().numpy(), gd.cpu().numpy())
+    e = cm.check_fp64(y)[0]
+    assert abs(e - e_host) <= 1e-12 * e_host and 0 < e <= 1e-4
+    assert cm.stats()["err_vs_fp64_last"] == e
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    y2 = to_dev(wl.y0)
+    cm.step_rk4(y2, t, 1.0, 8)
+    torch.cuda.synchronize()
+    st = cm.stats()
+    assert st["n_rhs_eph"] == 4 * 8 + 1 and st["n_rhs_phph"] == 4 * 8 + 1   # the eager rhs above counts
+    e_end = cm.check_fp64(y2)[0]
+    assert st["err_vs_fp64_last"] == e_end and 0 < e_end <= 1e-4
+
+
+def test_fp64_check_batched_and_unsupported():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    ws = [synth.build("tiny2d", seed=synth.MASTER_SEED + 11 + i) for i in range(2)]
+    cb = P.Context([w.problem_arrays() for w in ws], precision=P.rtbte.MIXED, fp64_check=1)
+    y = np.concatenate([w.y0 for w in ws])
+    eb = cb.check_fp64(to_dev(y))
+    for i, w in enumerate(ws):
+        c1 = P.Context(w.problem_arrays(), precision=P.rtbte.MIXED, fp64_check=1)
+        assert c1.check_fp64(to_dev(w.y0))[0] == eb[i]
+        assert P.Context(w.problem_arrays(), precision=P.rtbte.MIXED).stats()["err_vs_fp64_last"] == -1.0
+    for ctx in (P.Context(ws[0].problem_arrays()), P.Context(ws[0].problem_arrays(), precision=P.rtbte.MIXED)):
+        with pytest.raises(P.RtbteError):
+            ctx.check_fp64(to_dev(ws[0].y0))
