@@ -297,8 +297,11 @@ int rtbte_step_rk4(rtbte_ctx *ctx, double *y, double *t, double h_step, int64_t 
  * h_slow, fast part I^{e-ph} + I^{ph-e} integrated over each stage interval
  * with forcing, by the fast integrator chosen in the options.  Advances to
  * t_out (the last slow step is shortened to land on it) or by one slow step
- * (one_step = 1).  h_fast[inst] (device) carries the adaptive fast step.
- * Only n_inst == 1 contexts support it (RTBTE_E_UNSUPPORTED otherwise). */
+ * (one_step = 1).  h_fast[inst] (device) carries each instance's adaptive
+ * fast step.  In a batched context the slow steps are common: every
+ * instance must be at the same t (RTBTE_E_UNSUPPORTED otherwise), and each
+ * integrates its fast part with its own adaptive steps; an instance computes
+ * exactly what it computes alone. */
 int rtbte_step_multirate(rtbte_ctx *ctx, double *y, double *t, double *h_fast, double t_out,
                          double h_slow, int32_t one_step, void *stream);
 
@@ -329,8 +332,9 @@ int rtbte_step_multirate_adaptive(rtbte_ctx *ctx, double *y, double *t, double *
  * with, Results, Fig. 3): each step of h_slow advances the fast part
  * I^{e-ph} + I^{ph-e} over the step by RK4 substeps of h_fast (the last one
  * cut to land), then the slow part I^{ph-ph} over the same interval by one
- * RK4 step.  Advances *t (device) to t_out, the last step shortened to land.
- * Only n_inst == 1 contexts support it (RTBTE_E_UNSUPPORTED otherwise). */
+ * RK4 step.  Advances t (device, one entry per instance) to t_out, the last
+ * step shortened to land.  In a batched context the steps are common: every
+ * instance must be at the same t (RTBTE_E_UNSUPPORTED otherwise). */
 int rtbte_step_split(rtbte_ctx *ctx, double *y, double *t, double h_fast, double h_slow, double t_out,
                      void *stream);
 

@@ -25,6 +25,7 @@ using namespace rtbte;
 namespace rtbte {
 hipError_t launch_diff_norms(const double* a, const double* b, const InstInfo* info, double* partial, int n_inst,
                              int nchunk, hipStream_t s);
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t s);
 }
 
 namespace {
@@ -1294,7 +1295,7 @@ namespace {
 
 // Fixed RK4 substeps of h over [t0, t1] on `parts` (plus `forcing` on the
 // phonon rows, if given), the last substep cut to land on t1; runs on the
-// fast-integrator state with the device scalar t_in as its clock.
+// fast-integrator state with the device clocks t_in (one per instance).
 int rk4_segment(rtbte_ctx* c, double* y, double* t_in, int parts, const double* forcing, const Ctl& ctl,
                 double t0, double t1, double h, hipStream_t s) {
   const Tableau tb = rk4();
@@ -1305,13 +1306,11 @@ int rk4_segment(rtbte_ctx* c, double* y, double* t_in, int parts, const double* 
     tt += h;
     ++nfull;
   }
-  c->scal_h[2] = t0;
-  HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 2, sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, launch_fill(t_in, t0, c->n_inst, s));
   int rc = RTBTE_OK;
   if (nfull > 0) rc = run(c, y, t_in, nullptr, 0.0, 0, parts, forcing, c->st_fast, ctl, tb, 0.0, nfull, h, s);
   if (rc == RTBTE_OK && t1 - tt > 0) {
-    c->scal_h[3] = tt;
-    HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 3, sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_fill(t_in, tt, c->n_inst, s));
     rc = run(c, y, t_in, nullptr, 0.0, 0, parts, forcing, c->st_fast, ctl, tb, 0.0, 1, t1 - tt, s);
   }
   return rc;
@@ -1327,20 +1326,18 @@ namespace {
 // along, or fixed RK4 substeps) with the constant forcing of Eq. (mis_coef).
 int mis_one(rtbte_ctx* c, double* y, double tc, double hs, bool fixed, const Ctl& ctl, const Tableau& tb,
             hipStream_t s) {
-  const InstInfo& in = c->info[0];
-  const int64_t phoff = in.off + in.n_el;
-  double* t_in = c->tvec;      // fast solver time (device scalar)
-  double* h_in = c->tvec + 1;  // fast solver step (device scalar)
+  double* t_in = c->tvec;               // fast solver clocks (one per instance)
+  double* h_in = c->tvec + c->n_inst;   // fast solver steps (one per instance)
   FinishArgs f{};
   f.out = c->fs[0];
   HIPCHK(c, rhs_launch(c, y, RTBTE_PART_PHPH, nullptr, f, false, s));
   c->extra_rhs[2]++;
   for (int i = 1; i < 4; ++i) {
     const double* v[3] = {c->fs[0], c->fs[1], c->fs[2]};
-    HIPCHK(c, launch_lincomb(c->forcing, v, MIS_R[i], i, phoff, in.n_ph, s));
+    for (int k = 0; k < c->n_inst; ++k)
+      HIPCHK(c, launch_lincomb(c->forcing, v, MIS_R[i], i, c->info[k].off + c->info[k].n_el, c->info[k].n_ph, s));
     const double t0 = tc + MIS_C[i - 1] * hs, t1 = tc + MIS_C[i] * hs;
-    c->scal_h[2] = t0;
-    HIPCHK(c, hipMemcpyAsync(t_in, c->scal_h + 2, sizeof(double), hipMemcpyHostToDevice, s));
+    if (!fixed) HIPCHK(c, launch_fill(t_in, t0, c->n_inst, s));
     int rc;
     if (!fixed) {
       rc = run(c, y, t_in, h_in, t1, 0, RTBTE_PART_EPH | RTBTE_PART_PHE, c->forcing, c->st_fast, ctl, tb,
@@ -1358,20 +1355,25 @@ int mis_one(rtbte_ctx* c, double* y, double tc, double hs, bool fixed, const Ctl
   return RTBTE_OK;
 }
 
-// Checks shared by the multirate entry points; reads t (and h_fast) to the host.
+// Checks shared by the multirate entry points; reads t to the host (every
+// instance must be at the same time: the slow steps are common) and h_fast
+// into the fast solvers' step slots.
 int mis_setup(rtbte_ctx* c, double* y, double* t, double* h_fast, double t_out, const char* who, bool* fixed,
               Ctl* ctl, Tableau* tb, double* tc, hipStream_t s) {
-  if (c->n_inst != 1) return fail(c, RTBTE_E_UNSUPPORTED, "multirate stepping needs a single instance");
   if (!y || !t || !h_fast || !std::isfinite(t_out)) return fail(c, RTBTE_E_INVAL, "%s: bad arguments", who);
   HIPCHK(c, hipSetDevice(c->device));
   *fixed = c->opt.fast_mode == 1;
   if (*fixed && !(c->opt.h_fast > 0)) return fail(c, RTBTE_E_INVAL, "fixed fast mode needs h_fast > 0");
   *ctl = make_ctl(c->opt, true, *fixed);
   *tb = *fixed ? rk4() : zonneveld();
-  HIPCHK(c, hipMemcpyAsync(c->scal_h, t, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(c->tvec + 1, h_fast, sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> th((size_t)c->n_inst);
+  HIPCHK(c, hipMemcpyAsync(th.data(), t, th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->tvec + c->n_inst, h_fast, (size_t)c->n_inst * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  *tc = c->scal_h[0];
+  for (double v : th)
+    if (v != th[0]) return fail(c, RTBTE_E_UNSUPPORTED, "%s: every instance must start at the same time", who);
+  *tc = th[0];
   return RTBTE_OK;
 }
 
@@ -1398,9 +1400,10 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
     c->slow_steps++;
     if (one_step) break;
   }
-  c->scal_h[4] = tc;
-  HIPCHK(c, hipMemcpyAsync(t, c->scal_h + 4, sizeof(double), hipMemcpyHostToDevice, s));
-  if (!fixed) HIPCHK(c, hipMemcpyAsync(h_fast, c->tvec + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, launch_fill(t, tc, c->n_inst, s));
+  if (!fixed)
+    HIPCHK(c, hipMemcpyAsync(h_fast, c->tvec + c->n_inst, (size_t)c->n_inst * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   return RTBTE_OK;
 }
@@ -1408,6 +1411,8 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
 extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t, double* h_fast, double* h_slow,
                                              double t_out, int32_t one_step, void* stream) {
   if (!c) return RTBTE_E_INVAL;
+  if (c->n_inst != 1)
+    return fail(c, RTBTE_E_UNSUPPORTED, "multirate stepping with an adaptive slow step needs a single instance");
   if (!h_slow) return fail(c, RTBTE_E_INVAL, "step_multirate_adaptive: bad arguments");
   hipStream_t s = (hipStream_t)stream;
   bool fixed = false;
@@ -1474,7 +1479,7 @@ extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t,
       break;
     }
   }
-  if (!fixed) HIPCHK(c, hipMemcpyAsync(h_fast, c->tvec + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (!fixed) HIPCHK(c, hipMemcpyAsync(h_fast, c->tvec + c->n_inst, sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   return RTBTE_OK;
 }
@@ -1482,15 +1487,17 @@ extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t,
 extern "C" int rtbte_step_split(rtbte_ctx* c, double* y, double* t, double h_fast, double h_slow, double t_out,
                                 void* stream) {
   if (!c) return RTBTE_E_INVAL;
-  if (c->n_inst != 1) return fail(c, RTBTE_E_UNSUPPORTED, "split stepping needs a single instance");
   if (!y || !t || !(h_fast > 0) || !(h_slow > 0) || !std::isfinite(t_out))
     return fail(c, RTBTE_E_INVAL, "step_split: bad arguments");
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
   const Ctl ctl = make_ctl(c->opt, true, true);
-  HIPCHK(c, hipMemcpyAsync(c->scal_h, t, sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> th((size_t)c->n_inst);
+  HIPCHK(c, hipMemcpyAsync(th.data(), t, th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  double tc = c->scal_h[0];
+  for (double v : th)
+    if (v != th[0]) return fail(c, RTBTE_E_UNSUPPORTED, "step_split: every instance must start at the same time");
+  double tc = th[0];
   double* t_in = c->tvec;
   while (tc < t_out) {
     double hs = h_slow;
@@ -1504,8 +1511,7 @@ extern "C" int rtbte_step_split(rtbte_ctx* c, double* y, double* t, double h_fas
     tc = last ? t_out : tc + hs;
     c->slow_steps++;
   }
-  c->scal_h[4] = tc;
-  HIPCHK(c, hipMemcpyAsync(t, c->scal_h + 4, sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(c, launch_fill(t, tc, c->n_inst, s));
   HIPCHK(c, hipStreamSynchronize(s));
   return RTBTE_OK;
 }

@@ -1,6 +1,6 @@
-// Diagnostics outside the collision kernels: the normwise difference of two
+// Small kernels outside the collision path: the normwise difference of two
 // right-hand sides per instance (the mixed-precision path against the FP64
-// lists kept beside it).
+// lists kept beside it) and a fill of the inner solvers' clocks.
 #include "internal.h"
 
 namespace rtbte {
@@ -42,6 +42,22 @@ hipError_t launch_diff_norms(const double* a, const double* b, const InstInfo* i
                              int nchunk, hipStream_t s) {
   if (n_inst <= 0 || nchunk <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_diff_norms, dim3(nchunk, n_inst), dim3(256), 0, s, a, b, info, partial, nchunk);
+  return hipGetLastError();
+}
+
+}  // namespace rtbte
+
+namespace rtbte {
+
+// p[i] = v for i < n (per-instance clocks of the inner solves).
+__global__ void k_fill(double* p, double v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
   return hipGetLastError();
 }
 

@@ -282,8 +282,8 @@ class Context:
                                           float(h_step), int(n_steps), _stream(stream)))
 
     def step_multirate(self, y, t, h_fast, t_out, h_slow, one_step=False, stream=None):
-        self._check(load().rtbte_step_multirate(self._h, _dptr(y, self.ny, "y"), _dptr(t, 1, "t"),
-                                                _dptr(h_fast, 1, "h_fast"), float(t_out), float(h_slow),
+        self._check(load().rtbte_step_multirate(self._h, _dptr(y, self.ny, "y"), _dptr(t, self.n_inst, "t"),
+                                                _dptr(h_fast, self.n_inst, "h_fast"), float(t_out), float(h_slow),
                                                 int(bool(one_step)), _stream(stream)))
 
     def step_multirate_adaptive(self, y, t, h_fast, h_slow, t_out, one_step=False, stream=None):
@@ -294,7 +294,7 @@ class Context:
                                                          float(t_out), int(bool(one_step)), _stream(stream)))
 
     def step_split(self, y, t, h_fast, h_slow, t_out, stream=None):
-        self._check(load().rtbte_step_split(self._h, _dptr(y, self.ny, "y"), _dptr(t, 1, "t"), float(h_fast),
+        self._check(load().rtbte_step_split(self._h, _dptr(y, self.ny, "y"), _dptr(t, self.n_inst, "t"), float(h_fast),
                                             float(h_slow), float(t_out), _stream(stream)))
 
     def reset(self):

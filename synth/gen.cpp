@@ -229,37 +229,69 @@ struct Model {
 
 const int ROWS_PER_CHUNK = 16;
 
+// Time reversal: the image of a state under k -> -k (the same band or branch).
+inline int inv_el(const Model &m, int f) {
+  const int nb = m.p.n_bands;
+  return m.g.neg(f / nb) * nb + f % nb;
+}
+inline int inv_ph(const Model &m, int l) {
+  const int nm = m.p.n_modes;
+  return m.g.neg(l / nm) * nm + l % nm;
+}
+
+// Sorted ids of a triplet or of its time-reversed image, whichever is
+// lexicographically smaller: the key every random decision about the
+// triplet is drawn from, so |V3|^2 and the thinning are the same for a
+// triplet in any order and for its image (real crystals have time-reversal
+// symmetry, which keeps N even in q and the carrier number conserved).
+inline void canon3(int a, int b, int c, int ia, int ib, int ic, int out[3]) {
+  int x[3] = {a, b, c}, y[3] = {ia, ib, ic};
+  std::sort(x, x + 3);
+  std::sort(y, y + 3);
+  const bool use_y = std::lexicographical_compare(y, y + 3, x, x + 3);
+  for (int i = 0; i < 3; ++i) out[i] = use_y ? y[i] : x[i];
+}
+
 // Is the unordered e-ph pair stored, and with which |g|^2?  Decided on the
-// canonical orientation (lower full id first) so both directions agree.
+// canonical orientation (lower full id first) so both directions agree, and
+// keyed on the smaller of the pair and its time-reversed image.
 inline bool pair_channel(const Model &m, int f_lo, int f_hi, int nu, int q_lo_to_hi, double *g2) {
   const synth_params &p = m.p;
   double w = m.hw[(size_t)q_lo_to_hi * p.n_modes + nu];
   double e_lo = m.eps_full[f_lo], e_hi = m.eps_full[f_hi];
   double x1 = std::fabs(e_lo - w - e_hi), x2 = std::fabs(e_lo + w - e_hi);
   if (std::min(x1, x2) > p.shell_eph) return false;
+  int k_lo = f_lo, k_hi = f_hi;
+  {
+    const int a = inv_el(m, f_lo), b = inv_el(m, f_hi);
+    const int i_lo = std::min(a, b), i_hi = std::max(a, b);
+    if (i_lo < k_lo || (i_lo == k_lo && i_hi < k_hi)) { k_lo = i_lo; k_hi = i_hi; }
+  }
   if (p.keep_eph < 1.0) {
-    uint64_t packed = (uint64_t)f_lo | ((uint64_t)f_hi << 21) | ((uint64_t)nu << 42) | (1ull << 50);
+    uint64_t packed = (uint64_t)k_lo | ((uint64_t)k_hi << 21) | ((uint64_t)nu << 42) | (1ull << 50);
     if (!(keep_u01(packed, p.seed) < p.keep_eph)) return false;
   }
-  u32x4 c{{(uint32_t)f_lo, (uint32_t)f_hi, (uint32_t)nu, STREAM_EPH}};
+  u32x4 c{{(uint32_t)k_lo, (uint32_t)k_hi, (uint32_t)nu, STREAM_EPH}};
   u32x4 r = philox4x32_10(c, m.k0, m.k1);
   *g2 = std::exp(p.g2_mu + p.g2_sig * normal01(r.v[1], r.v[2]));
   return true;
 }
 
 // Is the q-point triplet (q0, q1, q2), q0 + q1 + q2 = 0, kept by the
-// q-level thinning?  Decided on the sorted ids: the same for every ordering.
+// q-level thinning?  Decided on the canonical sorted ids: the same for every
+// ordering and for the time-reversed triplet.
 inline bool qtriplet_kept(const Model &m, int q0, int q1, int q2) {
   if (!(m.p.keep_pp_q < 1.0)) return true;
-  int id[3] = {q0, q1, q2};
-  std::sort(id, id + 3);
+  int id[3];
+  canon3(q0, q1, q2, m.g.neg(q0), m.g.neg(q1), m.g.neg(q2), id);
   uint64_t packed = (uint64_t)id[0] | ((uint64_t)id[1] << 21) | ((uint64_t)id[2] << 42) | (1ull << 62);
   return keep_u01(packed, m.p.seed) < m.p.keep_pp_q;
 }
 
 // Is the unordered phonon triplet stored, and with which |V3|^2?  The shell
-// test uses the sorted frequencies, the hash the sorted ids: both are
-// invariant under permutation of the three phonons.
+// test uses the sorted frequencies, the hash the canonical sorted ids: both
+// are invariant under permutation of the three phonons and under time
+// reversal.
 inline bool triplet_channel(const Model &m, int l0, int l1, int l2, double *v2) {
   const synth_params &p = m.p;
   const int nm = p.n_modes;
@@ -268,8 +300,8 @@ inline bool triplet_channel(const Model &m, int l0, int l1, int l2, double *v2) 
   const double hi = std::max(std::max(wa, wb), wc), lo = std::min(std::min(wa, wb), wc);
   const double mid = std::max(std::min(wa, wb), std::min(std::max(wa, wb), wc));
   if (!(std::fabs(hi - (mid + lo)) <= p.shell_pp)) return false;
-  int id[3] = {l0, l1, l2};
-  std::sort(id, id + 3);
+  int id[3];
+  canon3(l0, l1, l2, inv_ph(m, l0), inv_ph(m, l1), inv_ph(m, l2), id);
   if (p.keep_pp < 1.0) {
     uint64_t packed = (uint64_t)id[0] | ((uint64_t)id[1] << 21) | ((uint64_t)id[2] << 42) | (1ull << 63);
     if (!(keep_u01(packed, p.seed) < p.keep_pp)) return false;

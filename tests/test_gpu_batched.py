@@ -92,3 +92,63 @@ def test_batched_mixed_graph_run_is_bitwise_alone():
         assert np.array_equal(got[off:off + ne + nph], yi.cpu().numpy()), i
         assert multi.stats(i)["n_accept"] == single.stats(0)["n_accept"]
         assert multi.stats(i)["n_reject"] == single.stats(0)["n_reject"]
+
+
+@pytest.mark.parametrize("mode", ["mis-fixed", "mis-adaptive", "split"])
+def test_batched_multirate_is_bitwise_alone(mode):
+    """MIS (fixed or adaptive fast solver) and operator splitting in a batch:
+    common slow steps, each instance's fast part on its own steps; every
+    instance ends bitwise where it ends alone.  (Largest linearized rates of
+    these instances: fast part ~1/fs, slow ~0.006/fs, so 0.5 fs fast and 20 fs
+    slow steps are stable.)"""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    ws = batch()
+    n = len(ws)
+    kw = dict(fast_mode=1, h_fast=0.5) if mode == "mis-fixed" else \
+        dict(fast_mode=0, fast_rtol=1e-7, fast_atol_el=1e-10, fast_atol_ph=1e-12)
+    say(f"[batched] {mode} of {n} instances")
+
+    def advance(ctx, y, t, h):
+        if mode == "split":
+            ctx.step_split(y, t, 0.5, 20.0, 60.0)
+        else:
+            ctx.step_multirate(y, t, h, 60.0, 20.0)
+
+    multi = P.Context([w.problem_arrays() for w in ws], **kw)
+    y = to_dev(stack(ws))
+    t = torch.zeros(n, dtype=torch.float64, device="cuda")
+    h = torch.full((n,), 0.2, dtype=torch.float64, device="cuda")
+    advance(multi, y, t, h)
+    torch.cuda.synchronize()
+    assert torch.all(t == 60.0)
+    yb = y.cpu().numpy()
+    for i, w in enumerate(ws):
+        off, ne, nph = multi.layout(i)
+        one = P.Context(w.problem_arrays(), **kw)
+        y1 = to_dev(w.y0)
+        t1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        h1 = torch.full((1,), 0.2, dtype=torch.float64, device="cuda")
+        advance(one, y1, t1, h1)
+        torch.cuda.synchronize()
+        assert np.array_equal(yb[off:off + ne + nph], y1.cpu().numpy()), (mode, i)
+        if mode == "mis-adaptive":
+            assert h[i].item() == h1.item()
+            s1, sb = one.stats(), multi.stats(i)
+            assert (s1["n_fast_accept"], s1["n_fast_reject"]) == (sb["n_fast_accept"], sb["n_fast_reject"])
+
+
+def test_batched_multirate_needs_a_common_time():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    ws = batch()[:2]
+    multi = P.Context([w.problem_arrays() for w in ws], fast_mode=1, h_fast=0.5)
+    y0 = stack(ws)
+    y = to_dev(y0)
+    t = torch.tensor([0.0, 1.0], dtype=torch.float64, device="cuda")
+    h = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.RtbteError):
+        multi.step_multirate(y, t, h, 40.0, 20.0)
+    with pytest.raises(P.RtbteError):
+        multi.step_split(y, t, 0.5, 20.0, 40.0)
+    assert np.array_equal(y.cpu().numpy(), y0)

@@ -297,3 +297,29 @@ def test_observables_definitions():
         assert np.allclose(T, T0, rtol=1e-10)
         T2 = obs.mode_temperature(wl.hw, N * 1.1, modes, wl.grid["n_modes"])
         assert np.all(T2 > T)
+
+
+def test_carrier_number_and_inversion_kept_by_the_dynamics():
+    """From the (inversion-symmetric) initial state of a thinned 3D grid,
+    RK4 on the full right-hand side keeps N(q) = N(-q) and f(k) = f(-k) to
+    rounding and the carrier number constant: the e-ph scattering only moves
+    carriers, and the time-reversal symmetry of the inputs keeps the phonon
+    populations even in q."""
+    from tests.test_synth import _neg
+    from oracle import integrators as I
+    wl = synth.build("tiny3d", keep_eph=0.6, keep_pp=0.6, keep_pp_q=0.7)
+    o = oracle.Oracle(wl.problem_arrays())
+    g = wl.grid
+    L, dim, nm = g["L"], g["dim"], g["n_modes"]
+    pinv = np.array([_neg(l // nm, L, dim) * nm + l % nm for l in range(wl.n_ph)])
+    win = {(int(k), int(b)): r for r, (k, b) in enumerate(zip(wl.el_k, wl.el_band))}
+    einv = np.array([win[(_neg(int(wl.el_k[r]), L, dim), int(wl.el_band[r]))] for r in range(wl.n_el)])
+    y = wl.y0.copy()
+    n0 = y[:wl.n_el].sum()
+    for _ in range(20):
+        y = I.rk4_step(o.rhs, y, 0.05)
+    f, N = y[:wl.n_el], y[wl.n_el:]
+    assert np.max(np.abs(N - N[pinv])) <= 1e-14 * np.max(N)
+    assert np.max(np.abs(f - f[einv])) <= 1e-14
+    assert abs(f.sum() - n0) <= 1e-13 * n0
+    assert np.max(np.abs(N - wl.y0[wl.n_el:])) > 1e-4 * np.max(N)   # the populations did move

@@ -110,3 +110,31 @@ def test_window_and_initial_state():
     kT = synth.KB_EV_PER_K * 300.0
     assert np.isclose(synth.fermi_dirac(kT * np.log(3.0), 300.0), 0.25, rtol=1e-15, atol=0)
     assert np.isclose(synth.bose_einstein(kT * np.log(2.0), 300.0), 1.0, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "tiny3d"])
+def test_time_reversal_symmetry(name):
+    """With every kind of thinning active, the stored channels are closed
+    under k -> -k with the same values: (lam; a, b) implies (-lam; -a, -b)
+    with the same |V3|^2, and (r -> s, nu q) implies (-r -> -s, nu -q) with
+    the same |g|^2 (real crystals have this symmetry; it keeps N even in q
+    and so the carrier number conserved)."""
+    wl = synth.build(name, keep_eph=0.6, keep_pp=0.6, keep_pp_q=0.7)
+    g = wl.grid
+    L, dim, nm = g["L"], g["dim"], g["n_modes"]
+
+    def inv_ph(l):
+        q, nu = divmod(int(l), nm)
+        return _neg(q, L, dim) * nm + nu
+    win = {(int(k), int(b)): r for r, (k, b) in enumerate(zip(wl.el_k, wl.el_band))}
+
+    def inv_el(r):
+        return win[(_neg(int(wl.el_k[r]), L, dim), int(wl.el_band[r]))]
+    pp = {(int(l), int(a), int(b)): v for l, a, b, v in zip(wl.pp_row, wl.pp_a, wl.pp_b, wl.pp_v2)}
+    assert pp
+    for (l, a, b), v in pp.items():
+        assert pp.get((inv_ph(l), inv_ph(a), inv_ph(b))) == v
+    ep = {(int(r), int(s), int(p)): v for r, s, p, v in zip(wl.eph_row, wl.eph_partner, wl.eph_phonon, wl.eph_g2)}
+    assert ep
+    for (r, s, p), v in ep.items():
+        assert ep.get((inv_el(r), inv_el(s), inv_ph(p))) == v
