@@ -147,8 +147,10 @@ typedef struct {
   /* PID controller (Eq. (pid_controller)): h' = h * safety * eps_k^(-k1/p) *
      eps_{k-1}^(-k2/p) * eps_{k-2}^(-k3/p); pid_alt_sign = 1 uses +k2/p.
      Ratio limited to <= eta_max (eta_max_first on the first step) after an
-     accepted step and to [eta_fail_min, eta_fail_max] after a rejected one;
-     errors below eps_floor count as eps_floor. */
+     accepted step and to [eta_fail_min, eta_fail_max] after a rejected one
+     (and to <= eta_fail_repeat from the small_nef-th consecutive rejection
+     on); errors below eps_floor count as eps_floor; more than max_fails
+     consecutive rejections end the call with RTBTE_E_STEP. */
   double pid_k1, pid_k2, pid_k3;
   int32_t pid_order, pid_alt_sign;
   double safety, eta_max, eta_max_first, eta_fail_min, eta_fail_max, eps_floor;
@@ -189,6 +191,9 @@ typedef struct {
                                rtbte_check_fp64 can measure the mixed right-hand side against
                                FP64, and the stepping calls do so at every K-th poll,
                                reporting the last value in rtbte_stats.err_vs_fp64_last     */
+  int32_t small_nef;        /* from the small_nef-th consecutive error-test failure on (default
+                               2), the step ratio after a rejection is also capped by        */
+  double eta_fail_repeat;   /* eta_fail_repeat (default 0.3), as the ARKODE integrators do   */
 } rtbte_options;
 
 enum { RTBTE_F64_AUTO = 0, RTBTE_F64_PACKED = 1, RTBTE_F64_PLAIN = 2 };
@@ -315,7 +320,8 @@ int rtbte_step_multirate(rtbte_ctx *ctx, double *y, double *t, double *h_fast, d
  * with the options' rtol, atol_el and atol_ph (weights from the state at the
  * start of the attempt) decides acceptance; the next H is
  * H safety eps^(-1/4), limited as for the ERK controller (eta_max,
- * eta_max_first on the first accepted step, eta_fail_min .. eta_fail_max on
+ * eta_max_first on the first accepted step, eta_fail_min .. eta_fail_max
+ * (and eta_fail_repeat from the small_nef-th consecutive failure) on
  * rejection, at most max_fails consecutive rejections).  The fast part is
  * integrated as in rtbte_step_multirate (full step, then the two halves, the
  * fast solver's state carried through all three).

@@ -128,21 +128,28 @@ class Controls:
     eta_max_first: float = 1e4
     eta_fail_min: float = 0.1
     eta_fail_max: float = 0.9
+    # from the second consecutive error-test failure on, the ratio is also
+    # capped by eta_fail_repeat (the defaults of the ARKODE integrators the
+    # paper runs with default settings; the paper prints no safeguards)
+    small_nef: int = 2
+    eta_fail_repeat: float = 0.3
     eps_floor: float = 1e-10
     max_fails: int = 7
 
 
-def pid_eta(eps, e1, e2, accepted: bool, first: bool, c: Controls) -> float:
+def pid_eta(eps, e1, e2, accepted: bool, first: bool, c: Controls, fails: int = 1) -> float:
     """Step ratio h'/h: safety * eps_k^(-k1/p) eps_{k-1}^(-+k2/p) eps_{k-2}^(-k3/p),
     then limited to [.., eta_max] on acceptance or [eta_fail_min, eta_fail_max]
-    on rejection."""
+    on rejection, and to <= eta_fail_repeat once `fails` (consecutive
+    failures, this one included) reaches small_nef."""
     e0 = max(eps, c.eps_floor)
     s2 = 1.0 if c.alt_sign else -1.0
     eta = (c.safety * e0 ** (-c.k1 / c.order) * max(e1, c.eps_floor) ** (s2 * c.k2 / c.order)
            * max(e2, c.eps_floor) ** (-c.k3 / c.order))
     if accepted:
         return min(eta, c.eta_max_first if first else c.eta_max)
-    return min(max(eta, c.eta_fail_min), c.eta_fail_max)
+    eta = min(max(eta, c.eta_fail_min), c.eta_fail_max)
+    return min(eta, c.eta_fail_repeat) if fails >= c.small_nef else eta
 
 
 def hnw_initial_step(rhs, y0, c: Controls, atol_vec, order=4):
@@ -215,9 +222,9 @@ class Adaptive:
                 if one_step:
                     break
             else:
-                self.h = h * pid_eta(eps, self.e1, self.e2, False, self.first, self.c)
-                self.n_reject += 1
                 fails += 1
+                self.h = h * pid_eta(eps, self.e1, self.e2, False, self.first, self.c, fails)
+                self.n_reject += 1
                 if fails > self.c.max_fails:
                     raise StepFailure("too many consecutive error-test failures")
         return y, t
@@ -316,7 +323,7 @@ def slow_controls(c: Controls) -> Controls:
     return Controls(rtol=c.rtol, atol_el=c.atol_el, atol_ph=c.atol_ph, k1=1.0, k2=0.0, k3=0.0, order=4,
                     alt_sign=False, safety=c.safety, eta_max=c.eta_max, eta_max_first=c.eta_max_first,
                     eta_fail_min=c.eta_fail_min, eta_fail_max=c.eta_fail_max, eps_floor=c.eps_floor,
-                    max_fails=c.max_fails)
+                    max_fails=c.max_fails, small_nef=c.small_nef, eta_fail_repeat=c.eta_fail_repeat)
 
 
 @dataclass
@@ -373,9 +380,9 @@ class MisAdaptive:
                 if one_step:
                     break
             else:
-                self.H = H * pid_eta(eps, self.e1, self.e2, False, self.first, cs)
-                self.n_reject += 1
                 fails += 1
+                self.H = H * pid_eta(eps, self.e1, self.e2, False, self.first, cs, fails)
+                self.n_reject += 1
                 if fails > cs.max_fails:
                     raise StepFailure("too many consecutive error-test failures")
         return y, t

@@ -237,6 +237,8 @@ void rtbte_default_options(rtbte_options* o) {
   o->tune_cache = nullptr;
   o->fp64_layout = RTBTE_F64_AUTO;
   o->fp64_check = 0;
+  o->small_nef = 2;
+  o->eta_fail_repeat = 0.3;
 }
 
 const char* rtbte_last_error(const rtbte_ctx* ctx) {
@@ -451,6 +453,8 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     return fail(nullptr, RTBTE_E_INVAL, "group_rows_el / group_rows_ph must be 0, 1, 2, 4, 8, 12 or 16");
   if (o.item_channels < 0) return fail(nullptr, RTBTE_E_INVAL, "item_channels must be >= 0");
   if (o.fp64_check < 0) return fail(nullptr, RTBTE_E_INVAL, "fp64_check must be >= 0");
+  if (o.small_nef < 1 || !(o.eta_fail_repeat > 0.0))
+    return fail(nullptr, RTBTE_E_INVAL, "small_nef must be >= 1 and eta_fail_repeat > 0");
   if (!(o.rtol >= 0) || !(o.atol_el >= 0) || !(o.atol_ph >= 0) || o.pid_order <= 0 ||
       o.steps_per_poll < 1 || o.max_fails < 0)
     return fail(nullptr, RTBTE_E_INVAL, "invalid tolerances or controller options");
@@ -1084,6 +1088,8 @@ Ctl make_ctl(const rtbte_options& o, bool fast, bool fixed) {
   t.eta_max_first = o.eta_max_first;
   t.eta_fail_min = o.eta_fail_min;
   t.eta_fail_max = o.eta_fail_max;
+  t.eta_fail_repeat = o.eta_fail_repeat;
+  t.small_nef = o.small_nef;
   t.eps_floor = o.eps_floor;
   t.rtol = fast ? o.fast_rtol : o.rtol;
   t.atol_el = fast ? o.fast_atol_el : o.atol_el;
@@ -1162,6 +1168,7 @@ bool same_ctl(const Ctl& a, const Ctl& b) {
   return a.k1 == b.k1 && a.k2 == b.k2 && a.k3 == b.k3 && a.order == b.order && a.safety == b.safety &&
          a.eta_max == b.eta_max && a.eta_max_first == b.eta_max_first && a.eta_fail_min == b.eta_fail_min &&
          a.eta_fail_max == b.eta_fail_max && a.eps_floor == b.eps_floor && a.rtol == b.rtol &&
+         a.eta_fail_repeat == b.eta_fail_repeat && a.small_nef == b.small_nef &&
          a.atol_el == b.atol_el && a.atol_ph == b.atol_ph && a.max_fails == b.max_fails &&
          a.alt_sign == b.alt_sign && a.fixed == b.fixed && a.stages == b.stages;
 }

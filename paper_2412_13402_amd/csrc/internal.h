@@ -61,8 +61,10 @@ struct InstInfo {
 // Controller constants (PID of Eq. (pid_controller) and its safeguards).
 struct Ctl {
   double k1, k2, k3, order, safety, eta_max, eta_max_first, eta_fail_min, eta_fail_max, eps_floor;
+  double eta_fail_repeat;              // ratio cap from the small_nef-th consecutive failure on
   double rtol, atol_el, atol_ph;
   int32_t max_fails, alt_sign, fixed;  // fixed: fixed step, every step accepted
+  int32_t small_nef;
   int32_t stages;                      // right-hand-side evaluations per attempt
 };
 

@@ -835,14 +835,17 @@ __device__ __forceinline__ double wrms_total(const double* partial, int inst, in
 }
 
 // ------------------------------------------------------------- step control
-// PID ratio of Eq. (pid_controller) with the safeguards of the options.
-__device__ double pid_eta(double eps, double e1, double e2, bool accepted, bool first, const Ctl& c) {
+// PID ratio of Eq. (pid_controller) with the safeguards of the options;
+// `fails` counts the consecutive failures, this one included.
+__device__ double pid_eta(double eps, double e1, double e2, bool accepted, bool first, const Ctl& c,
+                          int fails = 1) {
   const double e0 = fmax(eps, c.eps_floor);
   const double s2 = c.alt_sign ? 1.0 : -1.0;
   double eta = c.safety * pow(e0, -c.k1 / c.order) * pow(fmax(e1, c.eps_floor), s2 * c.k2 / c.order) *
                pow(fmax(e2, c.eps_floor), -c.k3 / c.order);
   if (accepted) return fmin(eta, first ? c.eta_max_first : c.eta_max);
-  return fmin(fmax(eta, c.eta_fail_min), c.eta_fail_max);
+  eta = fmin(fmax(eta, c.eta_fail_min), c.eta_fail_max);
+  return fails >= c.small_nef ? fmin(eta, c.eta_fail_repeat) : eta;
 }
 
 __device__ void plan_next(InstState& s) {
@@ -903,8 +906,8 @@ __global__ void k_control(InstState* st, const double* partial, const InstInfo* 
     if (s.t >= s.t_out || s.one_step) s.done = 1;
   } else {
     s.accepted = 0;
-    s.h = s.h_use * pid_eta(eps, s.e1, s.e2, false, s.first != 0, c);
     s.fails++;
+    s.h = s.h_use * pid_eta(eps, s.e1, s.e2, false, s.first != 0, c, s.fails);
     s.n_reject++;
     if (s.fails > c.max_fails) {
       s.status = -4;  // RTBTE_E_STEP

@@ -51,7 +51,7 @@ class Harness:
     spaced times.  Every context replays its step sequence from HIP graphs and
     polls every 2 steps (tiny fast intervals need a step or two each)."""
 
-    def __init__(self, prob, y0, n_el, t_end, n_checks, precision=0):
+    def __init__(self, prob, y0, n_el, t_end, n_checks, precision=0, progress=None):
         import torch
         from . import rtbte as R
         self.torch = torch
@@ -64,6 +64,7 @@ class Harness:
         self.precision = precision
         self.ref = None
         self.rows = []
+        self.progress = progress    # called with (t, wall) at every check time
 
     def _ctx(self, **kw):
         return self.R.Context(self.prob, precision=self.precision, use_graph=1, steps_per_poll=2, **kw)
@@ -84,6 +85,8 @@ class Harness:
             torch.cuda.synchronize()
             wall += time.perf_counter() - w0
             states.append(y.cpu().numpy())
+            if self.progress:
+                self.progress(tc, wall)
         return states, wall
 
     def reference(self, hs=0.01, rtol=1e-10, atol=1e-15):
@@ -171,8 +174,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     import synth
     wl = synth.build(a.workload, L=a.L)
-    H = Harness(wl.problem_arrays(), wl.y0, wl.n_el, a.t_end, a.checks)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
+    H = Harness(wl.problem_arrays(), wl.y0, wl.n_el, a.t_end, a.checks,
+                progress=lambda tc, w: log(f"    t = {tc:g} fs, {w:.2f} s"))
     log(f"[error-cost] {a.workload} L={a.L}: n_el {wl.n_el} n_ph {wl.n_ph}, to {a.t_end:g} fs")
     res = {"workload": f"{a.workload} L={a.L}", "t_end_fs": a.t_end}
     if a.ref_load:

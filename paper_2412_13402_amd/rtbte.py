@@ -67,6 +67,8 @@ class Options(ctypes.Structure):
         ("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
         ("fp64_layout", ctypes.c_int32),
         ("fp64_check", ctypes.c_int32),
+        ("small_nef", ctypes.c_int32),
+        ("eta_fail_repeat", ctypes.c_double),
     ]
 
 
