@@ -192,8 +192,9 @@ typedef struct {
                                FP64, and the stepping calls do so at every K-th poll,
                                reporting the last value in rtbte_stats.err_vs_fp64_last     */
   int32_t small_nef;        /* from the small_nef-th consecutive error-test failure on (default
-                               2), the step ratio after a rejection is also capped by        */
-  double eta_fail_repeat;   /* eta_fail_repeat (default 0.3), as the ARKODE integrators do   */
+                               5), the step ratio after a rejection is also capped by        */
+  double eta_fail_repeat;   /* eta_fail_repeat (default 0.3): a rescue for steps the PID
+                               history factors keep from shrinking                          */
 } rtbte_options;
 
 enum { RTBTE_F64_AUTO = 0, RTBTE_F64_PACKED = 1, RTBTE_F64_PLAIN = 2 };

@@ -128,10 +128,10 @@ class Controls:
     eta_max_first: float = 1e4
     eta_fail_min: float = 0.1
     eta_fail_max: float = 0.9
-    # from the second consecutive error-test failure on, the ratio is also
-    # capped by eta_fail_repeat (the defaults of the ARKODE integrators the
-    # paper runs with default settings; the paper prints no safeguards)
-    small_nef: int = 2
+    # from the small_nef-th consecutive error-test failure on, the ratio is
+    # also capped by eta_fail_repeat (a rescue for steps that the history
+    # factors keep from shrinking; the paper prints no safeguards)
+    small_nef: int = 5
     eta_fail_repeat: float = 0.3
     eps_floor: float = 1e-10
     max_fails: int = 7

@@ -237,7 +237,7 @@ void rtbte_default_options(rtbte_options* o) {
   o->tune_cache = nullptr;
   o->fp64_layout = RTBTE_F64_AUTO;
   o->fp64_check = 0;
-  o->small_nef = 2;
+  o->small_nef = 5;
   o->eta_fail_repeat = 0.3;
 }
 

@@ -173,10 +173,11 @@ def test_pid_properties():
     assert c.eta_max < I.pid_eta(1e-30, 1.0, 1.0, True, True, c) <= c.eta_max_first
     assert I.pid_eta(1e12, 1.0, 1.0, False, False, c) == c.eta_fail_min
     assert I.pid_eta(1.01, 1.0, 1.0, False, False, c) == c.eta_fail_max
-    # repeated failures: capped at eta_fail_repeat from the second on
-    assert I.pid_eta(1.01, 1.0, 1.0, False, False, c, fails=1) == c.eta_fail_max
-    assert I.pid_eta(1.01, 1.0, 1.0, False, False, c, fails=2) == c.eta_fail_repeat == 0.3
-    assert I.pid_eta(1e12, 1.0, 1.0, False, False, c, fails=5) == c.eta_fail_min
+    # repeated failures: capped at eta_fail_repeat from the small_nef-th on
+    assert c.small_nef == 5 and c.eta_fail_repeat == 0.3
+    assert I.pid_eta(1.01, 1.0, 1.0, False, False, c, fails=c.small_nef - 1) == c.eta_fail_max
+    assert I.pid_eta(1.01, 1.0, 1.0, False, False, c, fails=c.small_nef) == c.eta_fail_repeat
+    assert I.pid_eta(1e12, 1.0, 1.0, False, False, c, fails=c.small_nef + 2) == c.eta_fail_min
 
 
 def test_adaptive_meets_tolerance_on_relaxation():
