@@ -96,3 +96,34 @@ def test_mixed_populations_after_1ps_full_size(full):
     say(f"    max population difference {d.max():.2e}")
     assert np.all(np.isfinite(res[P.rtbte.MIXED]))
     assert d.max() <= 1e-6
+
+
+def test_observables_full_size(full):
+    """Rates of every part on every row within 1e-12 of their magnitude sums;
+    energy-resolved averages and branch temperatures against the oracle's
+    definitions, at full size and at the BE(300 K) recovery point."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    from oracle import observables as obs
+    wl, o = full
+    ctx = P.Context(wl.problem_arrays())
+    y = random_state(wl, 12)
+    dy = to_dev(y)
+    say("[fullsize] rates")
+    for parts in (7, 4):
+        out = torch.empty_like(dy)
+        ctx.rates(dy, out, parts)
+        torch.cuda.synchronize()
+        ref, mag = o.rates(y, parts, magnitude=True)
+        assert np.all(np.abs(out.cpu().numpy() - ref) <= 1e-12 * mag + 1e-300), parts
+    say("[fullsize] energy averages and branch temperatures")
+    ne = wl.n_el
+    c, m, _ = ctx.energy_average(dy, float(wl.eps.min()), float(wl.eps.max()) + 1e-9, 64)
+    c0, m0, _ = obs.energy_average(wl.eps, y[:ne], float(wl.eps.min()), float(wl.eps.max()) + 1e-9, 64)
+    assert np.array_equal(c, c0) and np.allclose(m, m0, rtol=1e-13, atol=1e-300)
+    nm = wl.grid["n_modes"]
+    modes = np.arange(wl.n_ph) % nm
+    T = ctx.mode_temperatures(dy, modes, nm)
+    assert np.allclose(T, obs.mode_temperature(wl.hw, y[ne:], modes, nm), rtol=1e-9, atol=0)
+    T300 = ctx.mode_temperatures(to_dev(wl.y0), modes, nm)
+    assert np.allclose(T300, 300.0, rtol=1e-9, atol=0)

@@ -401,3 +401,24 @@ def test_multirate_adaptive_arguments():
     hs.fill_(1.0)
     with pytest.raises(P.RtbteError):
         batch.step_multirate_adaptive(yb, t, hf, hs, 10.0)
+
+
+def test_multirate_adaptive_in_mixed_precision_tracks_fp64():
+    """The adaptive slow step on a mixed context: same method, mixed
+    right-hand sides; the run ends within the tolerance-sized distance of
+    the FP64 run."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    res = {}
+    for prec in (P.rtbte.FP64, P.rtbte.MIXED):
+        ctx = P.Context(Pr, precision=prec, rtol=1e-6, atol_el=1e-9, atol_ph=1e-11, fast_mode=1, h_fast=0.5)
+        y = to_dev(y0)
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hf = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hs = torch.full((1,), 8.0, dtype=torch.float64, device="cuda")
+        ctx.step_multirate_adaptive(y, t, hf, hs, 40.0)
+        torch.cuda.synchronize()
+        assert t.item() == 40.0
+        res[prec] = y.cpu().numpy()
+    assert np.max(np.abs(res[P.rtbte.MIXED] - res[P.rtbte.FP64])) <= 1e-5
