@@ -36,10 +36,15 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the collision kernels' source (comments and blank lines left
+    out, so that the hash changes with the code only)."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "internal.h"):
-        with open(os.path.join(ROOT, "paper_2412_13402_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2412_13402_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -126,7 +126,7 @@ typedef struct {
 
 /* Options; rtbte_default_options fills every field. */
 typedef struct {
-  int32_t precision;       /* RTBTE_FP64 (default) or RTBTE_MIXED: 16-bit weights relative
+  int32_t precision;       /* RTBTE_FP64 (default) or RTBTE_MIXED: compact weights relative
                               to one FP32 scale per 512 channels (format: mixed_weights),
                               populations gathered as one FP32 code per state (formed in
                               FP64), factors and products in FP32, per-lane compensated

@@ -5,8 +5,9 @@
 // Collision integrals (Methods, Eq. (e-ph) and Eq. (ph-ph)).  Destination rows
 // of y' form groups of up to 16 consecutive rows of one kind; a group's
 // channels are cut into work items of bounded length, each streamed once by
-// one wavefront, 16 bytes per channel, with non-temporal loads; lanes stride
-// by 64 so every load instruction reads a contiguous 1 KB block.  The group's channels are stored
+// one wavefront with non-temporal loads (FP64: 16 bytes per channel, or 12 in
+// the packed layout; mixed precision: 8 or 10), laid out so that every load
+// instruction of a wavefront reads whole lines.  The group's channels are stored
 // merged in partner order, so rows that share partners (the modes of one
 // phonon wave vector; neighbouring electron k-points) gather their
 // populations from the same cache lines at the same time.  Each lane keeps
@@ -399,8 +400,10 @@ hipError_t launch_finish_rows(const FinishArgs& f, bool stage, hipStream_t s) {
 #ifndef MIX_PAIRS
 #define MIX_PAIRS 2
 #endif
-// Weights are stored relative to the FP32 scale of their 512-channel block as
-// FP16 heads, extended by an 11-bit significand tail held in the index word
+// Weights are stored relative to the FP32 scale of their 512-channel block:
+// by default as a small float (6-bit exponent, min(53 - 2P, 23)-bit
+// mantissa) in the same 64-bit word as the P-bit partner positions, else as
+// FP16 heads extended by an 11-bit significand tail held in the index word
 // (or FP16 alone, or BF16 for e-ph and ph-e, on request); the factors are
 // evaluated in FP32 from one FP32 word per state (4-byte gathers):
 //   phonon:   N; N + 1 is formed in FP32 (relative error <= 2u for N >= 0);
