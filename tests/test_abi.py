@@ -76,3 +76,38 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(rtbte, "lib_path", lambda: str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError, match="not built"):
         rtbte.load()
+
+
+def test_header_compiles_as_c_and_matches_the_binding_layout(tmp_path):
+    """A C99 program includes the header (-Wall -Werror), links the library,
+    fills the default options and prints the sizes and offsets of the ABI
+    structures: they must equal the ctypes binding's, field by field."""
+    import shutil
+    import subprocess
+    from paper_2412_13402_amd import rtbte
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"rtbte_problem": rtbte.Problem, "rtbte_options": rtbte.Options, "rtbte_stats": rtbte.Stats}
+    lines = []
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "abi.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"rtbte.h\"\n"
+                   "int main(void) {\n  rtbte_options o;\n  rtbte_default_options(&o);\n"
+                   '  printf("defaults %d %d %g %d\\n", o.precision, o.max_fails, o.eta_fail_repeat, o.small_nef);\n'
+                   + "\n".join(lines) + "\n  return 0;\n}\n")
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(rtbte.lib_path())
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe), "-L", libdir, "-lrtbte", f"-Wl,-rpath,{libdir}"], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line and not line.startswith("defaults"))
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+    d = next(line for line in out if line.startswith("defaults")).split()
+    assert d[1:] == ["0", "7", "0.3", "5"]
