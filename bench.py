@@ -126,6 +126,7 @@ def main():
     ap.add_argument("--batch-t-end", type=float, default=200.0, help="simulated fs of the batched leg")
     ap.add_argument("--si3d", action="store_true",
                     help="add the silicon-like 3D leg (40^3, ~2.5e9 channels; minutes): MIS vs ERK")
+    ap.add_argument("--no-toy", action="store_true", help="skip the small RK4 leg")
     ap.add_argument("--si-L", type=int, default=40)
     ap.add_argument("--si-t-end", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -273,7 +274,50 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         rec["si3d"] = si3d_leg(P, torch, np, args)
+    if not args.no_toy:
+        rec["toy"] = toy_leg(P, torch, np, with_oracle=not args.no_cpu_baseline)
     print(json.dumps(rec), flush=True)
+
+
+def toy_leg(P, torch, np, with_oracle=True):
+    """The small e-ph-only case (18x18 square grid, 3 modes): fixed-step RK4,
+    1 fs x 100, on the GPU (steps replayed from HIP graphs) and, beside it,
+    the same run of the oracle on the host cores; launch-bound on the GPU, so
+    no roofline figure."""
+    import synth
+    wl = synth.build("toy2d")
+    ctx = P.Context(wl.problem_arrays(), use_graph=1)
+    dev = torch.device("cuda:0")
+    y = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.step_rk4(y, t, 1.0, 8)                  # warm-up: first launches, graph capture
+    y.copy_(torch.tensor(wl.y0, dtype=torch.float64, device=dev))
+    t.zero_()
+    ctx.reset()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ctx.step_rk4(y, t, 1.0, 100)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    C = sum(ctx.counts())
+    res = {"workload": "toy2d: 18x18 square grid, 2 bands, 3 modes, e-ph only; RK4 1 fs x 100",
+           "channels": C, "gpu_wall_s": wall, "gpu_sim_ps_per_s": 0.1 / wall,
+           "gpu_channels_per_s": 400 * C / wall}
+    if with_oracle:
+        import oracle
+        from oracle import integrators as I
+        o = oracle.Oracle(wl.problem_arrays())
+        yr = wl.y0.copy()
+        w0 = time.perf_counter()
+        for _ in range(100):
+            yr = I.rk4_step(o.rhs, yr, 1.0)
+        ow = time.perf_counter() - w0
+        res.update(oracle_wall_s=ow, oracle_sim_ps_per_s=0.1 / ow, oracle_cores=oracle.threads(),
+                   max_abs_diff_vs_oracle=float(np.max(np.abs(y.cpu().numpy() - yr))))
+    log(f"[bench] toy RK4 1 fs x 100: GPU {wall * 1e3:.1f} ms" +
+        (f", oracle {res['oracle_wall_s'] * 1e3:.1f} ms, max |diff| {res['max_abs_diff_vs_oracle']:.2e}"
+         if with_oracle else ""))
+    return res
 
 
 def launch_spread(ctx, torch, y, reps=20):
