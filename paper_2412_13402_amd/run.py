@@ -38,6 +38,8 @@ def main(argv=None):
     ap.add_argument("--fast-rtol", type=float, default=1e-5)
     ap.add_argument("--checks", type=int, default=10)
     ap.add_argument("--graph", type=int, default=1, help="replay step sequences from HIP graphs")
+    ap.add_argument("--pid-alt-sign", type=int, default=0,
+                    help="1: PID with +k2 on the previous error (ARKODE's form) instead of the printed one")
     a = ap.parse_args(argv)
 
     import torch
@@ -53,7 +55,8 @@ def main(argv=None):
         dict(fast_mode=0, fast_rtol=a.fast_rtol, fast_atol_el=a.atol_el, fast_atol_ph=a.atol_ph)
     t0 = time.perf_counter()
     ctx = R.Context(wl.problem_arrays(), precision=R.FP64 if a.precision == "fp64" else R.MIXED,
-                    rtol=a.rtol, atol_el=a.atol_el, atol_ph=a.atol_ph, use_graph=a.graph, **fast_kw)
+                    rtol=a.rtol, atol_el=a.atol_el, atol_ph=a.atol_ph, use_graph=a.graph,
+                    pid_alt_sign=a.pid_alt_sign, **fast_kw)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     counts = ctx.counts()
@@ -103,7 +106,7 @@ def main(argv=None):
                fast_steps=st["n_fast_accept"], rhs_eph=st["n_rhs_eph"], rhs_phph=st["n_rhs_phph"],
                h_last=st["h_last"], h_slow_last=float(hs.item()) if a.method == "mis-adaptive" else None,
                options=dict(rtol=a.rtol, atol_el=a.atol_el, atol_ph=a.atol_ph, h=a.h, h_slow=a.h_slow,
-                            h_fast=a.h_fast, fast_rtol=a.fast_rtol),
+                            h_fast=a.h_fast, fast_rtol=a.fast_rtol, pid_alt_sign=a.pid_alt_sign),
                history=history)
     print(json.dumps(res))
     return res
