@@ -114,8 +114,9 @@ def test_starting_step_matches_oracle():
         assert abs(t.item() - h_ref) <= 1e-12 * h_ref
 
 
-@pytest.mark.parametrize("name", ["toy2d", "coupled"])
-def test_adaptive_steps_replay_on_oracle(name):
+@pytest.mark.parametrize("name,alt", [("toy2d", 0), ("coupled", 0), ("coupled", 1)])
+def test_adaptive_steps_replay_on_oracle(name, alt):
+    """Printed PID form (alt 0, the default) and ARKODE's (+k2, alt 1)."""
     torch = torch_cuda()
     import paper_2412_13402_amd as P
     if name == "coupled":
@@ -123,8 +124,8 @@ def test_adaptive_steps_replay_on_oracle(name):
     else:
         Pr, y0 = wl_of(name).problem_arrays(), wl_of(name).y0
     n_el, n_ph = Pr["n_el"], Pr["n_ph"]
-    say(f"[int] adaptive replay {name}")
-    ctx = P.Context(Pr, rtol=1e-6, atol_el=1e-9, atol_ph=1e-12)
+    say(f"[int] adaptive replay {name} alt {alt}")
+    ctx = P.Context(Pr, rtol=1e-6, atol_el=1e-9, atol_ph=1e-12, pid_alt_sign=alt)
     y = to_dev(y0)
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
     h = torch.full((1,), 0.05, dtype=torch.float64, device="cuda")
@@ -140,7 +141,7 @@ def test_adaptive_steps_replay_on_oracle(name):
     assert close(y.cpu().numpy(), yr)
     # free-running oracle with the same controller takes the same steps
     a = I.Adaptive(rhs=o.rhs, atol_vec=atol_vec(n_el, n_ph, 1e-9, 1e-12),
-                   c=I.Controls(rtol=1e-6, atol_el=1e-9, atol_ph=1e-12), h=0.05)
+                   c=I.Controls(rtol=1e-6, atol_el=1e-9, atol_ph=1e-12, alt_sign=bool(alt)), h=0.05)
     yy = y0.copy()
     tt = 0.0
     for _ in range(25):
