@@ -67,6 +67,8 @@ def cpu_baseline(wl, seconds):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
     whole Zonneveld ERK attempts (5 full right-hand sides each)."""
     import numpy as np
+    from __graft_entry__ import _ensure_built
+    _ensure_built(need_oracle=True)
     import oracle
     from oracle import integrators as I
     t0 = time.perf_counter()
@@ -303,7 +305,9 @@ def toy_leg(P, torch, np, with_oracle=True):
     res = {"workload": "toy2d: 18x18 square grid, 2 bands, 3 modes, e-ph only; RK4 1 fs x 100",
            "channels": C, "gpu_wall_s": wall, "gpu_sim_ps_per_s": 0.1 / wall,
            "gpu_channels_per_s": 400 * C / wall}
-    if with_oracle:
+    if with_oracle:                               # the CPU baseline of this case
+        from __graft_entry__ import _ensure_built
+        _ensure_built(need_oracle=True)
         import oracle
         from oracle import integrators as I
         o = oracle.Oracle(wl.problem_arrays())
