@@ -189,6 +189,7 @@ def main():
             "workload": f"{args.workload}: {'x'.join([str(wl.grid['L'])] * 2)} k=q grid, 2 bands, 6 branches, "
                         f"FP64, adaptive Zonneveld ERK rtol {args.rtol:g}",
             "channels_eph": counts[0], "channels_phe": counts[1], "channels_phph": counts[2],
+            "stored_channels": list(ctx.stored_counts()),
             "n_y": wl.n_y, "rhs_per_step": leg["rhs_per_step"],
             "rows_per_group_el": ctx.tuning()[0], "rows_per_group_ph": ctx.tuning()[1],
             "channels_per_item": ctx.tuning()[2],

@@ -195,6 +195,13 @@ typedef struct {
                                5), the step ratio after a rejection is also capped by        */
   double eta_fail_repeat;   /* eta_fail_repeat (default 0.3): a rescue for steps the PID
                                history factors keep from shrinking                          */
+  int32_t pp_fold;          /* 1 (default): when an instance's ph-ph list is mirror-symmetric
+                               (every (l; a, b) with a != b has (l; b, a) with the same
+                               |V3|^2, as the sum over ordered partner pairs gives; checked
+                               at create), store the emission channel of each such pair once,
+                               with twice the weight (the emission factor and delta are
+                               symmetric in a and b): a quarter fewer ph-ph channels, the
+                               same sums to rounding order.  0: store every channel.       */
 } rtbte_options;
 
 enum { RTBTE_F64_AUTO = 0, RTBTE_F64_PACKED = 1, RTBTE_F64_PLAIN = 2 };
@@ -226,9 +233,15 @@ int rtbte_layout(const rtbte_ctx *ctx, int32_t inst, int64_t *y_offset, int32_t 
                  int32_t *n_ph);
 /* Total length of y over all instances. */
 int64_t rtbte_ny(const rtbte_ctx *ctx);
-/* Stored channels of instance `inst` (-1: all): counts[0] electron-side e-ph
- * (emission + absorption), counts[1] phonon-side ph-e, counts[2] ph-ph. */
+/* Channels of instance `inst` (-1: all) the right-hand side sums, as the
+ * method defines them (every emission and absorption channel of every entry
+ * kept by the truncation and the cutoff): counts[0] electron-side e-ph,
+ * counts[1] phonon-side ph-e, counts[2] ph-ph. */
 int rtbte_counts(const rtbte_ctx *ctx, int32_t inst, int64_t counts[3]);
+
+/* Channels actually stored and streamed (rtbte_counts less the ph-ph
+ * emission channels carried by their mirrors under pp_fold). */
+int rtbte_stored_counts(const rtbte_ctx *ctx, int32_t inst, int64_t counts[3]);
 
 /* ydot = the parts of f(y) selected by `parts` (Eq. (erk_rhs); parts of
  * Eq. (mri_rhs)).  Rows a part does not touch are written with 0.  y and ydot

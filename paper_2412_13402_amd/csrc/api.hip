@@ -124,6 +124,7 @@ struct rtbte_ctx {
   int f64_m = 0;                  // FP64 packed lists: mantissa bits kept
   bool keep64 = false;            // a mixed context that also holds the FP64 lists
   std::vector<double> err64;      // [n_inst] last mixed-vs-FP64 right-hand-side difference (-1: none)
+  std::vector<int64_t> folded;    // [n_inst] ph-ph emission channels stored in their mirror's weight
   int64_t polls = 0;              // polls since the last periodic FP64 check
   uint64_t* pk = nullptr;         // FP64 packed: 8-byte words
   uint32_t* pkw = nullptr;        // FP64 packed: low weight words
@@ -239,6 +240,7 @@ void rtbte_default_options(rtbte_options* o) {
   o->fp64_check = 0;
   o->small_nef = 5;
   o->eta_fail_repeat = 0.3;
+  o->pp_fold = 1;
 }
 
 const char* rtbte_last_error(const rtbte_ctx* ctx) {
@@ -433,6 +435,50 @@ hipError_t build_items(rtbte_ctx* c, int64_t ich) {
 }  // namespace
 
 // Build a context with the launch shape in `opts` (no tuning).
+namespace {
+
+inline uint64_t mix64(uint64_t z) {   // splitmix64 finaliser (Steele, Lea, Flood, OOPSLA'14)
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Is every ph-ph entry (l; a, b) with a != b matched by (l; b, a) with the
+// same |V3|^2, as in the sum over ordered partner pairs?  Compared as equal
+// multisets through counts and wrapping sums of a 64-bit mix of (l, min,
+// max, |V3|^2 bits) over the a < b and the a > b entries.  *folded receives
+// the number of emission channels the a > b entries would give (they are
+// carried by their mirrors when the list is folded).
+bool pp_mirror_symmetric(const rtbte_problem& p, int64_t* folded) {
+  uint64_t s_lt = 0, s_gt = 0;
+  int64_t n_lt = 0, n_gt = 0, nf = 0;
+  const double cut = p.nsigma * p.sigma_pp;
+#pragma omp parallel for reduction(+ : s_lt, s_gt, n_lt, n_gt, nf) schedule(static)
+  for (int64_t e = 0; e < p.n_pp; ++e) {
+    const int32_t l = p.pp_row[e], a = p.pp_a[e], b = p.pp_b[e];
+    if (a == b) continue;
+    uint64_t vb;
+    std::memcpy(&vb, &p.pp_v2[e], sizeof vb);
+    const uint64_t h = mix64(mix64(mix64((uint64_t)(uint32_t)l + 0x9E3779B97F4A7C15ull) +
+                                   (uint64_t)(uint32_t)std::min(a, b)) +
+                             (uint64_t)(uint32_t)std::max(a, b)) + mix64(vb ^ 0xD1B54A32D192ED03ull);
+    if (a < b) {
+      s_lt += h;
+      ++n_lt;
+    } else {
+      s_gt += h;
+      ++n_gt;
+      // the emission channel of this entry, kept as the preparation keeps it
+      const double w = p.hw[l], wa = p.hw[a], wb = p.hw[b];
+      if (!(w < p.hw_cut || wa < p.hw_cut || wb < p.hw_cut) && std::fabs(-w + wa + wb) <= cut) ++nf;
+    }
+  }
+  *folded = nf;
+  return n_lt > 0 && s_lt == s_gt && n_lt == n_gt;
+}
+
+}  // namespace
+
 static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbte_options* opts,
                        rtbte_ctx** out) {
   if (!out) return fail(nullptr, RTBTE_E_INVAL, "out is NULL");
@@ -453,6 +499,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     return fail(nullptr, RTBTE_E_INVAL, "group_rows_el / group_rows_ph must be 0, 1, 2, 4, 8, 12 or 16");
   if (o.item_channels < 0) return fail(nullptr, RTBTE_E_INVAL, "item_channels must be >= 0");
   if (o.fp64_check < 0) return fail(nullptr, RTBTE_E_INVAL, "fp64_check must be >= 0");
+  if (o.pp_fold != 0 && o.pp_fold != 1) return fail(nullptr, RTBTE_E_INVAL, "pp_fold must be 0 or 1");
   if (o.small_nef < 1 || !(o.eta_fail_repeat > 0.0))
     return fail(nullptr, RTBTE_E_INVAL, "small_nef must be >= 1 and eta_fail_repeat > 0");
   if (!(o.rtol >= 0) || !(o.atol_el >= 0) || !(o.atol_ph >= 0) || o.pid_order <= 0 ||
@@ -534,6 +581,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     c->f64_m = c->keep64 && P <= 19 ? std::min(80 - 2 * P, 52) : 0;
   }
   c->err64.assign((size_t)n_inst, -1.0);
+  c->folded.assign((size_t)n_inst, 0);
   c->counts.assign(3 * (size_t)n_inst, 0);
 
   // Pass 1: upload raw entries and count kept channels per destination group.
@@ -592,6 +640,8 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
       fail(c, RTBTE_E_NOMEM, "count buffers: %s", hipGetErrorString(e));
       return cleanup(RTBTE_E_NOMEM);
     }
+    const bool fold = o.pp_fold && pp_mirror_symmetric(p, &c->folded[(size_t)i]);
+    if (!fold) c->folded[(size_t)i] = 0;
     const double pre_el = (2.0 * kPi / kHbarEvFs) / (double)p.n_q_total;
     const double pre_ph = (4.0 * kPi / kHbarEvFs) / (double)p.n_k_total;
     const double pre_pp = (36.0 * kPi / kHbarEvFs) / (double)p.n_q_total;
@@ -615,7 +665,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     // ph-ph
     a.row = d.pr; a.i0 = d.pa; a.i1 = d.pb; a.val = d.pv; a.perm = d.perm_pp; a.raw_ptr = d.ptr_pp;
     a.n_dest = ngp; a.sigma = p.sigma_pp; a.cut = p.nsigma * p.sigma_pp; a.pre = pre_pp;
-    a.pre2 = 2.0 * pre_pp; a.kind = 2; a.count = d.cnt_pp;
+    a.pre2 = 2.0 * pre_pp; a.kind = 2; a.count = d.cnt_pp; a.fold_em = fold ? 1 : 0;
     ppp[i] = a;
     e = launch_prep_count(pe[i], 0);
     if (e == hipSuccess) e = launch_prep_count(ppe[i], 0);
@@ -854,6 +904,17 @@ extern "C" int rtbte_layout(const rtbte_ctx* c, int32_t inst, int64_t* y_offset,
 extern "C" int64_t rtbte_ny(const rtbte_ctx* c) { return c ? c->ny : -1; }
 
 extern "C" int rtbte_counts(const rtbte_ctx* c, int32_t inst, int64_t counts[3]) {
+  if (!c || !counts || inst < -1 || inst >= c->n_inst) return RTBTE_E_INVAL;
+  counts[0] = counts[1] = counts[2] = 0;
+  for (int i = 0; i < c->n_inst; ++i)
+    if (inst < 0 || inst == i) {
+      for (int k = 0; k < 3; ++k) counts[k] += c->counts[3 * i + k];
+      counts[2] += c->folded[(size_t)i];
+    }
+  return RTBTE_OK;
+}
+
+extern "C" int rtbte_stored_counts(const rtbte_ctx* c, int32_t inst, int64_t counts[3]) {
   if (!c || !counts || inst < -1 || inst >= c->n_inst) return RTBTE_E_INVAL;
   counts[0] = counts[1] = counts[2] = 0;
   for (int i = 0; i < c->n_inst; ++i)

@@ -207,6 +207,8 @@ struct PrepArgs {
   int64_t y_off;            // instance offset in y
   int32_t n_el;
   int32_t kind;             // 0 e-ph electron side, 1 ph-e, 2 ph-ph
+  int32_t fold_em;          // ph-ph: store the emission channel of (l; a, b), a < b, with twice
+                            // its weight for itself and its mirror (l; b, a), which gives none
   int64_t* count;           // [n_dest] kept channels per group (count pass)
   const int64_t* base;      // [n_dest] first output slot of each group (fill pass)
   Channel* out;

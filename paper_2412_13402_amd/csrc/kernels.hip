@@ -1132,7 +1132,10 @@ __device__ __forceinline__ Kept classify(const PrepArgs& p, int64_t j) {
     const double x_ab = w - wa + wb;
     k.em = fabs(x_em) <= p.cut;
     k.ab = fabs(x_ab) <= p.cut;
-    if (k.em) k.wem = p.pre * v * gdelta(x_em, p.sigma);
+    // emission is symmetric in the two partners: with a mirror-symmetric list
+    // one channel of twice the weight stands for (l; a, b) and (l; b, a)
+    if (p.fold_em && a > b) k.em = false;
+    if (k.em) k.wem = (p.fold_em && a < b ? 2.0 : 1.0) * p.pre * v * gdelta(x_em, p.sigma);
     if (k.ab) k.wab = p.pre2 * v * gdelta(x_ab, p.sigma);
     const int64_t base = p.y_off + p.n_el;
     k.o0 = (int32_t)(base + a) | tag;

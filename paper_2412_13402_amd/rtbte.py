@@ -69,6 +69,7 @@ class Options(ctypes.Structure):
         ("fp64_check", ctypes.c_int32),
         ("small_nef", ctypes.c_int32),
         ("eta_fail_repeat", ctypes.c_double),
+        ("pp_fold", ctypes.c_int32),
     ]
 
 
@@ -114,6 +115,7 @@ def load():
     L.rtbte_ny.argtypes = [_vp]
     L.rtbte_ny.restype = i64
     L.rtbte_counts.argtypes = [_vp, i32, ctypes.POINTER(i64)]
+    L.rtbte_stored_counts.argtypes = [_vp, i32, ctypes.POINTER(i64)]
     L.rtbte_rhs.argtypes = [_vp, _vp, _vp, i32, _vp]
     L.rtbte_rates.argtypes = [_vp, _vp, _vp, i32, _vp]
     L.rtbte_check_fp64.argtypes = [_vp, _vp, _vp, _vp]
@@ -229,8 +231,15 @@ class Context:
         return off.value, ne.value, nph.value
 
     def counts(self, inst=-1):
+        """Channels the right-hand side sums (e-ph, ph-e, ph-ph), as the method defines them."""
         c = (ctypes.c_int64 * 3)()
         self._check(load().rtbte_counts(self._h, inst, c))
+        return tuple(c)
+
+    def stored_counts(self, inst=-1):
+        """Channels stored and streamed (fewer ph-ph ones under pp_fold)."""
+        c = (ctypes.c_int64 * 3)()
+        self._check(load().rtbte_stored_counts(self._h, inst, c))
         return tuple(c)
 
     def rhs(self, y, ydot, parts=PART_ALL, stream=None):

@@ -215,3 +215,48 @@ def test_fp64_layouts_agree_and_reject_oversize():
     assert np.all(np.abs(outs[0] - outs[1]) <= 1e-14 * A + 1e-300)
     with pytest.raises(P.RtbteError):
         P.Context(wl.problem_arrays(), fp64_layout=7)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "tiny3d", "medium2d"])
+def test_pp_fold_matches_oracle_and_unfolded(name):
+    """Mirror-symmetric ph-ph lists (as generated) have their emission pairs
+    stored once with twice the weight: fewer stored channels, the method's
+    channel count unchanged, every row still within 1e-12 A_i of the oracle
+    and of the unfolded context.  A list with one mirror weight changed is
+    not folded."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = workload(name)
+    o = oracle.Oracle(wl.problem_arrays())
+    say(f"[rhs] ph-ph fold {name}")
+    y = random_state(wl, 21)
+    ref, S, A = o.rhs(y, scales=True)
+    outs = {}
+    for fold in (1, 0):
+        ctx = P.Context(wl.problem_arrays(), pp_fold=fold)
+        assert ctx.counts() == o.counts()
+        st = ctx.stored_counts()
+        if fold:
+            assert st[:2] == o.counts()[:2] and st[2] < o.counts()[2]
+        else:
+            assert st == o.counts()
+        out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+        ctx.rhs(to_dev(y), out, P.PART_ALL)
+        torch.cuda.synchronize()
+        outs[fold] = out.cpu().numpy()
+        assert np.all(np.abs(outs[fold] - ref) <= 1e-12 * A + 1e-300), fold
+    assert np.all(np.abs(outs[1] - outs[0]) <= 1e-12 * A + 1e-300)
+    # break the symmetry of one pair: no fold, still exact
+    pr = dict(wl.problem_arrays())
+    v2 = pr["pp_v2"].copy()
+    k = int(np.flatnonzero(pr["pp_a"] != pr["pp_b"])[0])
+    v2[k] *= 1.5
+    pr["pp_v2"] = v2
+    ob = oracle.Oracle(pr)
+    ctx = P.Context(pr)
+    assert ctx.stored_counts() == ctx.counts() == ob.counts()
+    out = torch.empty((wl.n_y,), dtype=torch.float64, device="cuda")
+    ctx.rhs(to_dev(y), out, P.PART_ALL)
+    torch.cuda.synchronize()
+    refb, Sb, Ab = ob.rhs(y, scales=True)
+    assert np.all(np.abs(out.cpu().numpy() - refb) <= 1e-12 * Ab + 1e-300)
