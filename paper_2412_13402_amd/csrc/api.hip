@@ -1309,15 +1309,20 @@ int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_ste
   // Graph replay: the same launches as the loop below, captured once per
   // argument set (profiling times individual launches, so it stays eager).
   const bool graph = c->opt.use_graph && !c->prof;
+  // a fixed-step run launches exactly its steps (no attempts that find
+  // every instance done at the end of the last poll interval)
+  int64_t left = fixed_steps;
   while (!done) {
+    const int n = fixed_steps > 0 && left > 0 ? (int)std::min<int64_t>(per_poll, left) : per_poll;
+    if (fixed_steps > 0) left -= n;
     if (graph) {
       hipGraphExec_t ex = nullptr;
-      int rc = step_graph(c, y, parts, forcing, st, ctl, tb, per_poll, &ex);
+      int rc = step_graph(c, y, parts, forcing, st, ctl, tb, n, &ex);
       if (rc) return rc;
       HIPCHK(c, hipGraphLaunch(ex, s));
       c->graph_launches++;
     } else {
-      for (int m = 0; m < per_poll; ++m) {
+      for (int m = 0; m < n; ++m) {
         int rc = enqueue_step(c, y, parts, forcing, st, ctl, tb, s);
         if (rc) return rc;
       }
