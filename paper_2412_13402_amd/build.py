@@ -1,4 +1,5 @@
-"""Build librtbte.so (HIP, gfx950) in-tree with hipcc."""
+"""Build librtbte.so (HIP, gfx950) in-tree with hipcc, and the plain-C example
+program that uses it (build/example_rhs)."""
 import os
 import subprocess
 
@@ -6,6 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librtbte.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "diagnostics.hip", "api.hip")]
+EXAMPLE = os.path.join(HERE, "build", "example_rhs")
 
 
 def hipcc_command(out=LIB, arch="gfx950"):
@@ -16,6 +18,17 @@ def hipcc_command(out=LIB, arch="gfx950"):
             "-o", out] + SOURCES
 
 
+def example_command(out=EXAMPLE):
+    """The C example: a C99 program against include/rtbte.h and the HIP
+    runtime's C API, linked to librtbte.so (found next to it at run time)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    return ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(rocm, "include"),
+            os.path.join(HERE, "csrc", "example_rhs.c"), "-o", out,
+            "-L", HERE, "-lrtbte", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+            "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+
+
 def build(verbose=False) -> str:
     tmp = LIB + ".tmp"
     cmd = hipcc_command(tmp)
@@ -23,6 +36,11 @@ def build(verbose=False) -> str:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    os.makedirs(os.path.dirname(EXAMPLE), exist_ok=True)
+    cmd = example_command()
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
     return LIB
 
 
