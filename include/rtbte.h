@@ -358,7 +358,8 @@ int rtbte_step_multirate_adaptive(rtbte_ctx *ctx, double *y, double *t, double *
 int rtbte_step_split(rtbte_ctx *ctx, double *y, double *t, double h_fast, double h_slow, double t_out,
                      void *stream);
 
-/* Clear the integrator state kept between calls (PID histories, counters). */
+/* Clear the integrator state kept between calls (PID histories, counters,
+ * the last FP64 check and its poll count). */
 int rtbte_reset(rtbte_ctx *ctx);
 int rtbte_get_stats(const rtbte_ctx *ctx, int32_t inst, rtbte_stats *out);
 

@@ -889,6 +889,8 @@ extern "C" int rtbte_reset(rtbte_ctx* c) {
   c->slow_steps = 0;
   c->split_slow_evals = 0;
   c->last_status = 0;
+  c->err64.assign((size_t)c->n_inst, -1.0);
+  c->polls = 0;
   return RTBTE_OK;
 }
 

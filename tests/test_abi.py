@@ -68,6 +68,12 @@ def test_default_options():
     assert (o.rtol, o.atol_el, o.atol_ph) == (1e-6, 1e-9, 1e-12)
     assert o.use_graph == 0 and o.tune == 0 and o.steps_per_poll == 8
     assert o.max_fails == 7 and o.safety == 0.96
+    # the controller the paper names (k1, k2, k3, order of the method), its
+    # printed sign form, and the safeguards chosen where the paper is silent
+    assert (o.pid_k1, o.pid_k2, o.pid_k3, o.pid_order, o.pid_alt_sign) == (0.58, 0.21, 0.1, 4, 0)
+    assert (o.eta_max, o.eta_max_first, o.eta_fail_min, o.eta_fail_max) == (20.0, 1e4, 0.1, 0.9)
+    assert (o.small_nef, o.eta_fail_repeat, o.eps_floor) == (5, 0.3, 1e-10)
+    assert o.pp_fold == 1 and o.fp64_check == 0 and o.fp64_layout == 0
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

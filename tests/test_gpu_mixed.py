@@ -220,6 +220,8 @@ def test_fp64_check_equals_the_two_paths():
     assert st["n_rhs_eph"] == 4 * 8 + 1 and st["n_rhs_phph"] == 4 * 8 + 1   # the eager rhs above counts
     e_end = cm.check_fp64(y2)[0]
     assert st["err_vs_fp64_last"] == e_end and 0 < e_end <= 1e-4
+    cm.reset()
+    assert cm.stats()["err_vs_fp64_last"] == -1.0
 
 
 def test_fp64_check_batched_and_unsupported():
