@@ -117,3 +117,20 @@ def test_header_compiles_as_c_and_matches_the_binding_layout(tmp_path):
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
     d = next(line for line in out if line.startswith("defaults")).split()
     assert d[1:] == ["0", "7", "0.3", "5"]
+
+
+def test_oracle_controls_match_the_library_defaults():
+    """The oracle's integrator defaults and the library's default options are
+    set independently; the step sequences compared in the GPU tests assume
+    they agree."""
+    import oracle.integrators as I
+    from paper_2412_13402_amd import rtbte
+    o, c = rtbte.default_options(), I.Controls()
+    pairs = [("rtol", "rtol"), ("atol_el", "atol_el"), ("atol_ph", "atol_ph"), ("pid_k1", "k1"),
+             ("pid_k2", "k2"), ("pid_k3", "k3"), ("pid_order", "order"), ("safety", "safety"),
+             ("eta_max", "eta_max"), ("eta_max_first", "eta_max_first"), ("eta_fail_min", "eta_fail_min"),
+             ("eta_fail_max", "eta_fail_max"), ("small_nef", "small_nef"),
+             ("eta_fail_repeat", "eta_fail_repeat"), ("eps_floor", "eps_floor"), ("max_fails", "max_fails")]
+    for lib_name, orc_name in pairs:
+        assert getattr(o, lib_name) == getattr(c, orc_name), lib_name
+    assert bool(o.pid_alt_sign) == c.alt_sign
