@@ -222,7 +222,8 @@ void rtbte_default_options(rtbte_options *opts);
  * Computes every channel weight (delta, prefactor, cutoff), derives the
  * I^{ph-e} lists, groups channels by destination row and uploads them.
  * Errors: RTBTE_E_INVAL (index out of range, sigma <= 0, nsigma <= 0,
- * negative counts, n_inst < 1), RTBTE_E_NOMEM, RTBTE_E_HIP. */
+ * negative counts, an instance with no states, n_inst < 1; checked before
+ * any device call), RTBTE_E_NOMEM, RTBTE_E_HIP. */
 int rtbte_create(const rtbte_problem *problems, int32_t n_inst, const rtbte_options *opts,
                  rtbte_ctx **out);
 void rtbte_destroy(rtbte_ctx *ctx);

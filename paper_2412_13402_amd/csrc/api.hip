@@ -312,6 +312,8 @@ void group_entries(int64_t n, const int32_t* dest, int32_t nrows, int G, const i
 int check_problem(const rtbte_problem& p, int inst) {
   if (p.n_el < 0 || p.n_ph < 0 || p.n_eph < 0 || p.n_pp < 0)
     return fail(nullptr, RTBTE_E_INVAL, "instance %d: negative size", inst);
+  if ((int64_t)p.n_el + p.n_ph == 0)
+    return fail(nullptr, RTBTE_E_INVAL, "instance %d: no states (n_el + n_ph must be > 0)", inst);
   if (p.n_k_total <= 0 || p.n_q_total <= 0)
     return fail(nullptr, RTBTE_E_INVAL, "instance %d: n_k_total and n_q_total must be > 0", inst);
   if (!(p.sigma_eph > 0) || !(p.sigma_pp > 0) || !(p.nsigma > 0))

@@ -134,3 +134,43 @@ def test_oracle_controls_match_the_library_defaults():
     for lib_name, orc_name in pairs:
         assert getattr(o, lib_name) == getattr(c, orc_name), lib_name
     assert bool(o.pid_alt_sign) == c.alt_sign
+
+
+@pytest.mark.parametrize("bad", ["row", "partner", "phonon", "sigma", "nsigma", "negative", "empty",
+                                 "group_rows", "pp_fold", "small_nef", "precision"])
+def test_invalid_create_is_rejected_before_any_device_call(bad):
+    """rtbte_create validates every problem and option on the host before it
+    asks for a device, so each of these fails with RTBTE_E_INVAL here, with
+    no GPU."""
+    import numpy as np
+    import synth
+    from paper_2412_13402_amd import rtbte
+    wl = synth.build("tiny2d")
+    Pr = dict(wl.problem_arrays())
+    kw = {}
+    if bad in ("row", "partner", "phonon"):
+        k = {"row": "pp_row", "partner": "eph_partner", "phonon": "eph_phonon"}[bad]
+        Pr[k] = Pr[k].copy()
+        Pr[k][len(Pr[k]) // 2] = wl.n_ph if k != "eph_partner" else wl.n_el
+    elif bad == "sigma":
+        Pr["sigma_pp"] = 0.0
+    elif bad == "nsigma":
+        Pr["nsigma"] = -3.0
+    elif bad == "negative":
+        Pr["n_k_total"] = 0
+    elif bad == "empty":
+        Pr.update(n_el=0, n_ph=0, eps=np.zeros(0), hw=np.zeros(0))
+        for k in ("eph_row", "eph_partner", "eph_phonon", "pp_row", "pp_a", "pp_b"):
+            Pr[k] = np.zeros(0, np.int32)
+        Pr["eph_g2"] = Pr["pp_v2"] = np.zeros(0)
+    elif bad == "group_rows":
+        kw["group_rows_ph"] = 5
+    elif bad == "pp_fold":
+        kw["pp_fold"] = 2
+    elif bad == "small_nef":
+        kw["small_nef"] = 0
+    else:
+        kw["precision"] = 7
+    with pytest.raises(rtbte.RtbteError) as e:
+        rtbte.Context(Pr, **kw)
+    assert e.value.code == rtbte.E_INVAL, str(e.value)

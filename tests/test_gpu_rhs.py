@@ -177,7 +177,7 @@ def test_rhs_is_deterministic():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("bad", ["row", "sigma", "shape"])
+@pytest.mark.parametrize("bad", ["row", "sigma", "shape", "empty"])
 def test_invalid_create_is_rejected(bad):
     torch_cuda()
     import paper_2412_13402_amd as P
@@ -189,6 +189,11 @@ def test_invalid_create_is_rejected(bad):
         Pr["pp_row"][7] = wl.n_ph
     elif bad == "sigma":
         Pr["sigma_eph"] = -1.0
+    elif bad == "empty":
+        Pr.update(n_el=0, n_ph=0, eps=np.zeros(0), hw=np.zeros(0))
+        for k in ("eph_row", "eph_partner", "eph_phonon", "pp_row", "pp_a", "pp_b"):
+            Pr[k] = np.zeros(0, np.int32)
+        Pr["eph_g2"] = Pr["pp_v2"] = np.zeros(0)
     else:
         kw["group_rows_el"] = 3
     with pytest.raises(P.RtbteError) as e:
