@@ -152,3 +152,78 @@ def test_batched_multirate_needs_a_common_time():
     with pytest.raises(P.RtbteError):
         multi.step_split(y, t, 0.5, 20.0, 40.0)
     assert np.array_equal(y.cpu().numpy(), y0)
+
+
+def _phonon_only(w):
+    Pr = dict(w.problem_arrays())
+    Pr.update(n_el=0, eps=np.zeros(0))
+    for k in ("eph_row", "eph_partner", "eph_phonon"):
+        Pr[k] = np.zeros(0, np.int32)
+    Pr["eph_g2"] = np.zeros(0)
+    return Pr, w.y0[w.n_el:].copy()
+
+
+def _electron_only(w):
+    Pr = dict(w.problem_arrays())
+    Pr.update(n_ph=0, hw=np.zeros(0))
+    for k in ("eph_row", "eph_partner", "eph_phonon", "pp_row", "pp_a", "pp_b"):
+        Pr[k] = np.zeros(0, np.int32)
+    Pr["eph_g2"] = Pr["pp_v2"] = np.zeros(0)
+    return Pr, w.y0[:w.n_el].copy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64-plain", "mixed"])
+def test_degenerate_instances_in_a_batch(prec):
+    """A phonon-only instance (no electrons: ph-ph only), an electron-only
+    instance (no phonons, so no channels at all: its right-hand side is 0)
+    and a full one share a context: each computes what it computes alone,
+    bitwise, right-hand side and a whole adaptive run, and the right-hand
+    sides meet the oracle's (FP64 1e-12 A_i; mixed its a priori bound)."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    w2, w3 = synth.build("tiny2d"), synth.build("tiny3d")
+    cases = [_phonon_only(w3), _electron_only(w2), (w2.problem_arrays(), w2.y0.copy())]
+    kw = dict(precision=P.rtbte.MIXED if prec == "mixed" else P.rtbte.FP64,
+              fp64_layout=P.rtbte.F64_PLAIN if prec == "fp64-plain" else P.rtbte.F64_AUTO)
+    say(f"[batched] degenerate instances ({prec}): n_y = "
+        f"{[len(y) for _, y in cases]}")
+    multi = P.Context([p for p, _ in cases], **kw)
+    y = np.concatenate([yc for _, yc in cases])
+    rng = np.random.default_rng(5)
+    yr = y * rng.uniform(0.5, 1.5, len(y))
+    out = torch.full((len(y),), float("nan"), dtype=torch.float64, device="cuda")
+    multi.rhs(to_dev(yr), out, P.PART_ALL)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    yd = to_dev(y)
+    t = torch.zeros(3, dtype=torch.float64, device="cuda")
+    h = torch.zeros(3, dtype=torch.float64, device="cuda")
+    multi.step_adaptive(yd, t, h, 20.0)
+    torch.cuda.synchronize()
+    assert np.all(t.cpu().numpy() == 20.0)
+    run = yd.cpu().numpy()
+    for i, (Pr, yc) in enumerate(cases):
+        off, ne, nph = multi.layout(i)
+        assert (ne, nph) == (Pr["n_el"], Pr["n_ph"])
+        sl = slice(off, off + ne + nph)
+        o = oracle.Oracle(Pr)
+        assert multi.counts(i) == o.counts(), i
+        ref, S, A, M, Q = o.rhs(yr[sl], scales=True, unweighted=True)
+        if prec == "mixed":
+            bound = (weight_u(multi) + 24 * U32) * A + U_SUB * o.max_weight() * M
+            assert np.all(np.abs(g[sl] - ref) <= bound + 1e-300), i
+        else:
+            assert np.all(np.abs(g[sl] - ref) <= 1e-12 * A + 1e-300), i
+        if nph == 0:
+            assert np.all(g[sl] == 0.0) and np.array_equal(run[sl], yc)
+        single = P.Context(Pr, **kw)
+        oi = torch.empty((ne + nph,), dtype=torch.float64, device="cuda")
+        single.rhs(to_dev(yr[sl]), oi, P.PART_ALL)
+        yi = to_dev(yc)
+        ti = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hi = torch.zeros(1, dtype=torch.float64, device="cuda")
+        single.step_adaptive(yi, ti, hi, 20.0)
+        torch.cuda.synchronize()
+        assert np.array_equal(g[sl], oi.cpu().numpy()), i
+        assert np.array_equal(run[sl], yi.cpu().numpy()), i
+        assert multi.stats(i)["n_accept"] == single.stats(0)["n_accept"], i
