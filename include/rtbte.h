@@ -340,12 +340,18 @@ int rtbte_step_multirate(rtbte_ctx *ctx, double *y, double *t, double *h_fast, d
  * rejection, at most max_fails consecutive rejections).  The fast part is
  * integrated as in rtbte_step_multirate (full step, then the two halves, the
  * fast solver's state carried through all three).
- * h_slow[0] (device) holds the first slow step (must be > 0) and receives
- * the next proposed one; t (device) and y are updated after every accepted
- * step, so on an error they hold the last accepted state.  Advances to t_out
- * (the last step shortened to land) or by one accepted step (one_step = 1).
+ * h_slow[inst] (device, one entry per instance) holds the first slow step
+ * (must be > 0) and receives the next proposed one; t (device) and y are
+ * updated after every accepted step, so on an error they hold the last
+ * accepted state.  Advances to t_out (the last step shortened to land) or by
+ * one accepted step (one_step = 1).  In a batched context the slow steps are
+ * common: every instance must be at the same t with the same h_slow
+ * (RTBTE_E_UNSUPPORTED otherwise), a slow step is accepted only when every
+ * instance's WRMS error is at most 1 (the controller takes the largest
+ * instance norm), and each instance integrates its fast part with its own
+ * steps; a batch of identical instances steps exactly as one alone.
  * The first call allocates three state-sized work vectors kept by the
- * context.  Single-instance contexts only (RTBTE_E_UNSUPPORTED otherwise). */
+ * context. */
 int rtbte_step_multirate_adaptive(rtbte_ctx *ctx, double *y, double *t, double *h_fast, double *h_slow,
                                   double t_out, int32_t one_step, void *stream);
 

@@ -11,6 +11,10 @@ Plain numpy, FP64, one vector operation per formula term:
 * ``Adaptive``           the accept/reject loop of the ERK method;
 * ``mis_step``           one slow step of the MRI algorithm with the MIS coupling
                          Eq. (mis_coef) built from the Knoth-Wolke 3-stage ERK.
+* ``MisAdaptive``        MIS with the slow step chosen by step doubling (the
+                         slow-step adaptivity the Discussion leaves open);
+                         ``batch_norm`` and ``SliceFastSolver`` run it on stacked
+                         independent instances that share the slow step.
 
 ``hnw_initial_step`` (the starting-step heuristic, not from the paper) is
 parity unpinned: nothing fixes its value independently; it is only compared
@@ -348,6 +352,7 @@ class MisAdaptive:
     n_accept: int = 0
     n_reject: int = 0
     history: list = field(default_factory=list)   # (t_new, H_used, eps) of accepted steps
+    norm: object = None    # norm(est, y) -> eps; None: the WRMS norm over the whole vector
 
     def attempt(self, y, H):
         """(y_half, eps) of one attempt of size H from y."""
@@ -355,6 +360,8 @@ class MisAdaptive:
         y_half = mis_step(self.fast_rhs, self.slow_rhs, y, H / 2, self.fast_solve)
         y_half = mis_step(self.fast_rhs, self.slow_rhs, y_half, H / 2, self.fast_solve)
         est = (y_half - y_full) / 7.0
+        if self.norm is not None:
+            return y_half, self.norm(est, y)
         return y_half, wrms(est, y, self.c.rtol, self.atol_vec)
 
     def advance(self, y, t, t_out, one_step=False):
@@ -386,3 +393,35 @@ class MisAdaptive:
                 if fails > cs.max_fails:
                     raise StepFailure("too many consecutive error-test failures")
         return y, t
+
+
+# ------------------------------------------- batches with a common slow step
+def batch_norm(slices, rtol, atol_vec):
+    """Error norm of independent instances stacked in one vector that share
+    the slow step: the step passes only if every instance passes its own WRMS
+    test, so the norm is the largest instance norm (each with its own
+    weights)."""
+    def norm(est, y):
+        return max(wrms(est[s], y[s], rtol, atol_vec[s]) for s in slices)
+    return norm
+
+
+class SliceFastSolver:
+    """Fast solver of stacked independent instances: each slice integrated by
+    its own solver (own step size and error history).  The forced right-hand
+    side f of the stacked vector is separable, so a slice's right-hand side is
+    f evaluated with the other slices held at their starting values."""
+
+    def __init__(self, slices, solvers):
+        self.slices = list(slices)
+        self.solvers = list(solvers)
+
+    def __call__(self, v, t0, t1, f):
+        out = v.copy()
+        for s, solve in zip(self.slices, self.solvers):
+            def f_s(u, s=s):
+                w = v.copy()
+                w[s] = u
+                return f(w)[s]
+            out[s] = solve(v[s].copy(), t0, t1, f_s)
+        return out

@@ -26,6 +26,9 @@ namespace rtbte {
 hipError_t launch_diff_norms(const double* a, const double* b, const InstInfo* info, double* partial, int n_inst,
                              int nchunk, hipStream_t s);
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_select_max_norm(const double* partial, const InstInfo* info, int n_inst, int nchunk,
+                                  double* sel_partial, InstInfo* sel_info, hipStream_t s);
+hipError_t launch_broadcast_first(double* p, int64_t n, hipStream_t s);
 }
 
 namespace {
@@ -137,7 +140,8 @@ struct rtbte_ctx {
   InstState* st = nullptr;       // main integrator
   InstState* st_fast = nullptr;  // MIS fast integrator
   InstState* st_slow = nullptr;  // MIS slow-step controller (adaptive multirate; one entry)
-  double* mra = nullptr;         // [3 * ny] adaptive multirate: full-step, half-step and estimate vectors
+  double* mra = nullptr;         // [3 * ny + nchunk + 2] adaptive multirate: full-step, half-step and
+                                 // estimate vectors, then the selected instance's WRMS partials and sizes
   double* kbuf[5] = {};
   double* zb[2] = {};
   double* ynew = nullptr;
@@ -1281,8 +1285,8 @@ int step_graph(rtbte_ctx* c, double* y, int parts, const double* forcing, InstSt
   return RTBTE_OK;
 }
 
-int poll(rtbte_ctx* c, InstState* st, double* t, double* h, hipStream_t s, bool* all_done, int* worst) {
-  HIPCHK(c, launch_finish(st, t, h, c->n_inst, c->summary_d, s));
+int poll(rtbte_ctx* c, InstState* st, int n_st, double* t, double* h, hipStream_t s, bool* all_done, int* worst) {
+  HIPCHK(c, launch_finish(st, t, h, n_st, c->summary_d, s));
   HIPCHK(c, hipMemcpyAsync(c->summary_h, c->summary_d, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (c->prof) HIPCHK(c, harvest(c));
@@ -1331,7 +1335,7 @@ int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_ste
         if (rc) return rc;
       }
     }
-    int rc = poll(c, st, t, h, s, &done, &worst);
+    int rc = poll(c, st, c->n_inst, t, h, s, &done, &worst);
     if (rc) return rc;
     if (c->keep64 && ++c->polls >= c->opt.fp64_check) {
       c->polls = 0;
@@ -1488,8 +1492,6 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
 extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t, double* h_fast, double* h_slow,
                                              double t_out, int32_t one_step, void* stream) {
   if (!c) return RTBTE_E_INVAL;
-  if (c->n_inst != 1)
-    return fail(c, RTBTE_E_UNSUPPORTED, "multirate stepping with an adaptive slow step needs a single instance");
   if (!h_slow) return fail(c, RTBTE_E_INVAL, "step_multirate_adaptive: bad arguments");
   hipStream_t s = (hipStream_t)stream;
   bool fixed = false;
@@ -1498,12 +1500,18 @@ extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t,
   double tc = 0.0;
   int rc = mis_setup(c, y, t, h_fast, t_out, "step_multirate_adaptive", &fixed, &ctl, &tb, &tc, s);
   if (rc) return rc;
-  HIPCHK(c, hipMemcpyAsync(c->scal_h + 5, h_slow, sizeof(double), hipMemcpyDeviceToHost, s));
+  const int n_inst = c->n_inst;
+  std::vector<double> hs((size_t)n_inst);
+  HIPCHK(c, hipMemcpyAsync(hs.data(), h_slow, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  if (!(c->scal_h[5] > 0.0) || !std::isfinite(c->scal_h[5]))
+  if (!(hs[0] > 0.0) || !std::isfinite(hs[0]))
     return fail(c, RTBTE_E_INVAL, "step_multirate_adaptive: the slow step h_slow must be positive");
+  for (double v : hs)
+    if (v != hs[0])
+      return fail(c, RTBTE_E_UNSUPPORTED, "step_multirate_adaptive: every instance must start with the same slow step");
+  static_assert(sizeof(InstInfo) <= 2 * sizeof(double), "selected-instance slot");
   if (!c->mra) {
-    hipError_t e = hipMalloc((void**)&c->mra, 3 * (size_t)c->ny * sizeof(double));
+    hipError_t e = hipMalloc((void**)&c->mra, (3 * (size_t)c->ny + (size_t)c->nchunk + 2) * sizeof(double));
     if (e != hipSuccess) {
       c->mra = nullptr;
       return fail(c, RTBTE_E_NOMEM, "step_multirate_adaptive: %s", hipGetErrorString(e));
@@ -1512,8 +1520,11 @@ extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t,
   double* y_full = c->mra;
   double* y_half = c->mra + c->ny;
   double* est = c->mra + 2 * c->ny;
+  double* sel_partial = c->mra + 3 * c->ny;
+  InstInfo* sel_info = reinterpret_cast<InstInfo*>(sel_partial + c->nchunk);
   // slow controller: I control on the step-doubling estimate of the
-  // third-order MIS step, eta = safety eps^(-1/4), the options' tolerances
+  // third-order MIS step, eta = safety eps^(-1/4), the options' tolerances;
+  // one controller state for the whole context (the slow steps are common)
   Ctl cs = make_ctl(c->opt, false, false);
   cs.k1 = 1.0;
   cs.k2 = 0.0;
@@ -1542,23 +1553,34 @@ extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t,
     const double* ev[1] = {est};
     HIPCHK(c, launch_lincomb(est, dv, one_m, 2, 0, c->ny, s));
     HIPCHK(c, launch_lincomb(est, ev, seventh, 1, 0, c->ny, s));
-    HIPCHK(c, launch_wrms(est, y, c->info_d, c->st_slow, c->partial, 1, c->nchunk, cs, s));
-    HIPCHK(c, launch_control(c->st_slow, c->partial, c->info_d, 1, c->nchunk, cs, s));
-    HIPCHK(c, launch_commit(y, y_half, c->row_inst, c->st_slow, c->ny, s));
+    if (n_inst == 1) {
+      HIPCHK(c, launch_wrms(est, y, c->info_d, c->st_slow, c->partial, 1, c->nchunk, cs, s));
+      HIPCHK(c, launch_control(c->st_slow, c->partial, c->info_d, 1, c->nchunk, cs, s));
+    } else {
+      // every instance's norm, then the controller on the largest
+      HIPCHK(c, launch_wrms(est, y, c->info_d, nullptr, c->partial, n_inst, c->nchunk, cs, s));
+      HIPCHK(c, launch_select_max_norm(c->partial, c->info_d, n_inst, c->nchunk, sel_partial, sel_info, s));
+      HIPCHK(c, launch_control(c->st_slow, sel_partial, sel_info, 1, c->nchunk, cs, s));
+    }
+    HIPCHK(c, launch_commit(y, y_half, nullptr, c->st_slow, c->ny, s));
     bool done = false;
     int worst = 0;
-    rc = poll(c, c->st_slow, t, h_slow, s, &done, &worst);
+    rc = poll(c, c->st_slow, 1, t, h_slow, s, &done, &worst);
     if (rc) return rc;
     if (done) {
       c->last_status = worst;
-      if (worst == RTBTE_E_STEP) return fail(c, RTBTE_E_STEP, "too many consecutive slow-step failures");
-      if (worst == RTBTE_E_NONFINITE) return fail(c, RTBTE_E_NONFINITE, "non-finite slow error estimate");
+      if (worst == RTBTE_E_STEP) rc = fail(c, RTBTE_E_STEP, "too many consecutive slow-step failures");
+      if (worst == RTBTE_E_NONFINITE) rc = fail(c, RTBTE_E_NONFINITE, "non-finite slow error estimate");
       break;
     }
   }
-  if (!fixed) HIPCHK(c, hipMemcpyAsync(h_fast, c->tvec + c->n_inst, sizeof(double), hipMemcpyDeviceToDevice, s));
+  // the common clock and slow step to every instance
+  HIPCHK(c, launch_broadcast_first(t, n_inst, s));
+  HIPCHK(c, launch_broadcast_first(h_slow, n_inst, s));
+  if (!fixed)
+    HIPCHK(c, hipMemcpyAsync(h_fast, c->tvec + n_inst, (size_t)n_inst * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  return RTBTE_OK;
+  return rc;
 }
 
 extern "C" int rtbte_step_split(rtbte_ctx* c, double* y, double* t, double h_fast, double h_slow, double t_out,
@@ -1602,9 +1624,9 @@ extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* ou
       hipMemcpy(&w, c->st_slow, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
     return RTBTE_E_HIP;
   std::memset(out, 0, sizeof *out);
-  // ERK steps, plus MIS slow steps (fixed and adaptive; single-instance contexts)
-  out->n_accept = s.n_accept + c->slow_steps + (c->n_inst == 1 ? w.n_accept : 0);
-  out->n_reject = s.n_reject + (c->n_inst == 1 ? w.n_reject : 0);
+  // ERK steps, plus MIS slow steps (fixed and adaptive; common to a batch)
+  out->n_accept = s.n_accept + c->slow_steps + w.n_accept;
+  out->n_reject = s.n_reject + w.n_reject;
   out->n_fast_accept = f.n_accept;
   out->n_fast_reject = f.n_reject;
   const int64_t main_evals = s.n_evals, fast_evals = f.n_evals;

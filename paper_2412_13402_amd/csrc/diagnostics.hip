@@ -62,3 +62,58 @@ hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t s) {
 }
 
 }  // namespace rtbte
+
+namespace rtbte {
+
+// Batched adaptive slow step of MIS: the instances share the slow step, which
+// is accepted only when every instance's WRMS error is at most 1, so the
+// slow controller is given the largest of the instances' norms.  One thread
+// totals each instance's partial sums in chunk order and takes the root of
+// their mean (as the controller does), picks the first instance with the
+// largest norm (a NaN wins, so a non-finite estimate anywhere fails the
+// step) and copies that instance's partial sums and sizes to a one-instance
+// slot; the controller, run on that slot, then computes bitwise the norm the
+// instance would have alone.
+__global__ void k_select_max_norm(const double* partial, const InstInfo* info, int n_inst, int nchunk,
+                                  double* sel_partial, InstInfo* sel_info) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int best = 0;
+  double best_e = -1.0;
+  for (int i = 0; i < n_inst; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < nchunk; ++j) s += partial[(int64_t)i * nchunk + j];
+    const double e = sqrt(s / (double)((int64_t)info[i].n_el + info[i].n_ph));
+    if (isnan(e)) {
+      best = i;
+      break;
+    }
+    if (e > best_e) {
+      best_e = e;
+      best = i;
+    }
+  }
+  for (int j = 0; j < nchunk; ++j) sel_partial[j] = partial[(int64_t)best * nchunk + j];
+  *sel_info = info[best];
+}
+
+hipError_t launch_select_max_norm(const double* partial, const InstInfo* info, int n_inst, int nchunk,
+                                  double* sel_partial, InstInfo* sel_info, hipStream_t s) {
+  if (n_inst <= 0 || nchunk <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_select_max_norm, dim3(1), dim3(64), 0, s, partial, info, n_inst, nchunk, sel_partial,
+                     sel_info);
+  return hipGetLastError();
+}
+
+// p[i] = p[0] for 0 < i < n (a common value handed to every instance).
+__global__ void k_broadcast_first(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > 0 && i < n) p[i] = p[0];
+}
+
+hipError_t launch_broadcast_first(double* p, int64_t n, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  hipLaunchKernelGGL(k_broadcast_first, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace rtbte

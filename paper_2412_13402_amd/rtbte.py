@@ -298,10 +298,12 @@ class Context:
                                                 int(bool(one_step)), _stream(stream)))
 
     def step_multirate_adaptive(self, y, t, h_fast, h_slow, t_out, one_step=False, stream=None):
-        """MIS with the slow step chosen by step doubling; h_slow (device, 1
-        entry) holds the first slow step and receives the next one."""
-        self._check(load().rtbte_step_multirate_adaptive(self._h, _dptr(y, self.ny, "y"), _dptr(t, 1, "t"),
-                                                         _dptr(h_fast, 1, "h_fast"), _dptr(h_slow, 1, "h_slow"),
+        """MIS with the slow step chosen by step doubling; h_slow (device, one
+        entry per instance, all equal: the slow steps are common) holds the
+        first slow step and receives the next one."""
+        n = self.n_inst
+        self._check(load().rtbte_step_multirate_adaptive(self._h, _dptr(y, self.ny, "y"), _dptr(t, n, "t"),
+                                                         _dptr(h_fast, n, "h_fast"), _dptr(h_slow, n, "h_slow"),
                                                          float(t_out), int(bool(one_step)), _stream(stream)))
 
     def step_split(self, y, t, h_fast, h_slow, t_out, stream=None):

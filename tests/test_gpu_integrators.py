@@ -399,9 +399,15 @@ def test_multirate_adaptive_arguments():
     wl = synth.build("tiny2d")
     batch = P.Context([wl.problem_arrays(), wl.problem_arrays()], fast_mode=1, h_fast=0.5)
     yb = to_dev(np.concatenate([wl.y0, wl.y0]))
-    hs.fill_(1.0)
-    with pytest.raises(P.RtbteError):
-        batch.step_multirate_adaptive(yb, t, hf, hs, 10.0)
+    tb = torch.zeros(2, dtype=torch.float64, device="cuda")
+    hfb = torch.full((2,), 0.1, dtype=torch.float64, device="cuda")
+    for hs_b, t_b in (([1.0, 2.0], [0.0, 0.0]), ([1.0, 1.0], [0.0, 0.5])):
+        tb.copy_(torch.tensor(t_b))
+        hsb = torch.tensor(hs_b, dtype=torch.float64, device="cuda")
+        with pytest.raises(P.RtbteError) as e:   # the slow steps of a batch are common
+            batch.step_multirate_adaptive(yb, tb, hfb, hsb, 10.0)
+        assert e.value.code == P.rtbte.E_UNSUPPORTED
+    assert np.array_equal(yb.cpu().numpy(), np.concatenate([wl.y0, wl.y0]))
 
 
 def test_multirate_adaptive_in_mixed_precision_tracks_fp64():
@@ -423,3 +429,92 @@ def test_multirate_adaptive_in_mixed_precision_tracks_fp64():
         assert t.item() == 40.0
         res[prec] = y.cpu().numpy()
     assert np.max(np.abs(res[P.rtbte.MIXED] - res[P.rtbte.FP64])) <= 1e-5
+
+
+def _batched_mis_adaptive_oracle(cases, solvers, rtol, a_el, a_ph, H0, t_out):
+    """The batched oracle: instances stacked, each with its own fast solver,
+    one slow step for all, the largest instance norm deciding it."""
+    orcs = [oracle.Oracle(Pr) for Pr, _ in cases]
+    sizes = [len(y) for _, y in cases]
+    offs = np.cumsum([0] + sizes)
+    slices = [slice(int(a), int(b)) for a, b in zip(offs[:-1], offs[1:])]
+
+    def part(p):
+        return lambda v: np.concatenate([o.rhs(v[sl], parts=p) for o, sl in zip(orcs, slices)])
+
+    atol = np.concatenate([atol_vec(Pr["n_el"], Pr["n_ph"], a_el, a_ph) for Pr, _ in cases])
+    M = I.MisAdaptive(part(3), part(4), I.SliceFastSolver(slices, solvers), atol,
+                      I.Controls(rtol=rtol, atol_el=a_el, atol_ph=a_ph), H=H0,
+                      norm=I.batch_norm(slices, rtol, atol))
+    y, t = np.concatenate([y for _, y in cases]), 0.0
+    while t < t_out:
+        y, t = M.advance(y, t, t_out, one_step=True)
+    return M, y
+
+
+def _run_batched_mis_adaptive(P, torch, cases, kw, H0, t_out):
+    n = len(cases)
+    ctx = P.Context([Pr for Pr, _ in cases], **kw)
+    y = to_dev(np.concatenate([y for _, y in cases]))
+    t = torch.zeros(n, dtype=torch.float64, device="cuda")
+    hf = torch.full((n,), 0.1, dtype=torch.float64, device="cuda")
+    hs = torch.full((n,), H0, dtype=torch.float64, device="cuda")
+    hist = []
+    while t[0].item() < t_out:
+        ctx.step_multirate_adaptive(y, t, hf, hs, t_out, one_step=True)
+        torch.cuda.synchronize()
+        tt, hh = t.cpu().numpy(), hs.cpu().numpy()
+        assert np.all(tt == tt[0]) and np.all(hh == hh[0])
+        hist.append((float(tt[0]), float(hh[0])))
+    return ctx, y.cpu().numpy(), hist
+
+
+@pytest.mark.parametrize("fast", ["fixed", "adaptive"])
+def test_batched_multirate_adaptive_matches_oracle(fast):
+    """Two different instances sharing the adaptive slow step: the same
+    accepted slow steps, rejections and final states as the batched oracle
+    (each instance with its own fast steps, the step decided by the largest
+    instance norm)."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    cases = [coupled(), coupled(scale_eph=0.05, scale_pp=0.006, seed=23)]
+    rtol, a_el, a_ph, H0, t_out = 1e-6, 1e-9, 1e-11, 8.0, 30.0
+    say(f"[int] batched MIS with adaptive slow step, {fast} fast solver")
+    if fast == "fixed":
+        kw = dict(fast_mode=1, h_fast=0.5)
+        solvers = [I.rk4_fixed_solver(0.5) for _ in cases]
+    else:
+        kw = dict(fast_mode=0, fast_rtol=1e-8, fast_atol_el=1e-11, fast_atol_ph=1e-13)
+        solvers = [I.AdaptiveFastSolver(atol_vec(Pr["n_el"], Pr["n_ph"], 1e-11, 1e-13),
+                                        I.Controls(rtol=1e-8, atol_el=1e-11, atol_ph=1e-13), 0.1)
+                   for Pr, _ in cases]
+    ctx, y, hist = _run_batched_mis_adaptive(P, torch, cases, dict(rtol=rtol, atol_el=a_el, atol_ph=a_ph, **kw),
+                                             H0, t_out)
+    M, yr = _batched_mis_adaptive_oracle(cases, solvers, rtol, a_el, a_ph, H0, t_out)
+    assert len(hist) == M.n_accept >= 3
+    ts = np.array([h[0] for h in hist])
+    tr = np.array([h[0] for h in M.history])
+    assert ts[-1] == t_out and np.allclose(ts, tr, rtol=1e-9, atol=0)
+    assert abs(hist[-1][1] - M.H) <= 1e-6 * M.H
+    assert close(y, yr, 1e-10)
+    for i in range(len(cases)):
+        st = ctx.stats(i)
+        assert st["n_accept"] == M.n_accept and st["n_reject"] == M.n_reject
+
+
+def test_batched_multirate_adaptive_of_identical_instances_is_bitwise_alone():
+    """Identical instances have identical norms, so a batch of them steps
+    exactly as one alone: the same slow steps and bitwise the same states."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    kw = dict(rtol=1e-6, atol_el=1e-9, atol_ph=1e-11, fast_mode=0, fast_rtol=1e-8, fast_atol_el=1e-11,
+              fast_atol_ph=1e-13)
+    say("[int] batched MIS with adaptive slow step, identical instances")
+    _, yb, hb = _run_batched_mis_adaptive(P, torch, [(Pr, y0)] * 3, kw, 8.0, 30.0)
+    _, y1, h1 = _run_batched_mis_adaptive(P, torch, [(Pr, y0)], kw, 8.0, 30.0)
+    assert hb == h1
+    n = len(y0)
+    for i in range(3):
+        assert np.array_equal(yb[i * n:(i + 1) * n], y1), i
+

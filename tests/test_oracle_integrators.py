@@ -432,3 +432,68 @@ def test_slow_controller_is_an_i_controller():
         for e1, e2 in ((1.0, 1.0), (0.2, 3.0)):
             assert abs(I.pid_eta(eps, e1, e2, True, False, c) - min(c.safety * eps ** -0.25, c.eta_max)) < 1e-15
     assert I.pid_eta(50.0, 1.0, 1.0, False, False, c) == max(c.safety * 50.0 ** -0.25, c.eta_fail_min)
+
+
+def _stack_linear(systems):
+    """Independent linear fast/slow systems stacked in one vector: block
+    diagonal operators, the slices, and a per-slice exact fast solver."""
+    from scipy.linalg import block_diag
+    Afb = block_diag(*[s[0] for s in systems])
+    Asb = block_diag(*[s[1] for s in systems])
+    sizes = [len(s[3]) for s in systems]
+    offs = np.cumsum([0] + sizes)
+    slices = [slice(int(a), int(b)) for a, b in zip(offs[:-1], offs[1:])]
+    solver = I.SliceFastSolver(slices, [s[2] for s in systems])
+    return Afb, Asb, slices, solver, np.concatenate([s[3] for s in systems])
+
+
+def test_batched_slow_step_meets_each_instance_tolerance():
+    """Two different instances sharing the slow step: the step passes only if
+    both pass, so each instance ends within the tolerance-sized distance of
+    its own exact solution, and the common clock lands on t_end."""
+    A, B = _linear_fast_slow(seed=1), _linear_fast_slow(seed=2)
+    Afb, Asb, slices, solver, y0 = _stack_linear([A, B])
+    T, rtol = 4.0, 1e-6
+    atol = np.full(len(y0), rtol * 1e-3)
+    M = I.MisAdaptive(lambda v: Afb @ v, lambda v: Asb @ v, solver, atol,
+                      I.Controls(rtol=rtol, atol_el=rtol * 1e-3, atol_ph=rtol * 1e-3), H=0.5,
+                      norm=I.batch_norm(slices, rtol, atol))
+    y, t = M.advance(y0.copy(), 0.0, T)
+    assert t == T and M.n_accept >= 5
+    for s, sys_ in zip(slices, (A, B)):
+        exact = sys_[4](T, sys_[3])
+        assert np.linalg.norm(y[s] - exact) / np.linalg.norm(exact) <= 30 * rtol
+    # the norm is the largest instance norm
+    est = np.random.default_rng(0).standard_normal(len(y0)) * 1e-6
+    per = [I.wrms(est[s], y0[s], rtol, atol[s]) for s in slices]
+    assert I.batch_norm(slices, rtol, atol)(est, y0) == max(per) and per[0] != per[1]
+
+
+def test_batched_slow_step_with_a_quiet_instance_is_the_instance_alone():
+    """An instance whose state never moves (zero solution) has a zero error
+    estimate, so a batch of it with A takes A's accepted and rejected steps,
+    and A's slice ends where A alone ends."""
+    n = 6
+    A = _linear_fast_slow(seed=3, n=n)
+    Z = (-np.eye(n), np.zeros((n, n)), None, np.zeros(n), None)
+    Zf = -np.eye(n)
+
+    def z_fast(v, t0, t1, f):
+        return np.exp(-(t1 - t0)) * v + (1.0 - np.exp(-(t1 - t0))) * f(np.zeros(n))   # exact for v' = -v + r
+
+    Afb, Asb, slices, solver, y0 = _stack_linear([A, (Zf, Z[1], z_fast, Z[3])])
+    rtol = 1e-6
+    atol = np.full(len(y0), 1e-9)
+    Mb = I.MisAdaptive(lambda v: Afb @ v, lambda v: Asb @ v, solver, atol,
+                       I.Controls(rtol=rtol, atol_el=1e-9, atol_ph=1e-9), H=0.5,
+                       norm=I.batch_norm(slices, rtol, atol))
+    yb, tb = Mb.advance(y0.copy(), 0.0, 3.0)
+    Ma = I.MisAdaptive(lambda v: A[0] @ v, lambda v: A[1] @ v, A[2], atol[:n],
+                       I.Controls(rtol=rtol, atol_el=1e-9, atol_ph=1e-9), H=0.5)
+    ya, ta = Ma.advance(A[3].copy(), 0.0, 3.0)
+    assert tb == ta == 3.0 and (Mb.n_accept, Mb.n_reject) == (Ma.n_accept, Ma.n_reject)
+    # the same steps up to rounding (the estimate is a difference of nearly
+    # equal states, so rounding of the stacked products moves H at ~1e-11)
+    assert np.allclose([h[1] for h in Mb.history], [h[1] for h in Ma.history], rtol=1e-8, atol=0)
+    assert np.allclose(yb[slices[0]], ya, rtol=1e-10, atol=1e-15)
+    assert np.all(yb[slices[1]] == 0.0)
