@@ -518,3 +518,20 @@ def test_batched_multirate_adaptive_of_identical_instances_is_bitwise_alone():
     for i in range(3):
         assert np.array_equal(yb[i * n:(i + 1) * n], y1), i
 
+
+
+def test_batched_multirate_adaptive_in_mixed_precision_tracks_fp64():
+    """The batched adaptive slow step on a mixed context: every instance
+    ends within the tolerance-sized distance of the FP64 batch, on the common
+    end time."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    cases = [coupled(), coupled(scale_eph=0.05, scale_pp=0.006, seed=23)]
+    say("[int] batched MIS with adaptive slow step, mixed against FP64")
+    res = {}
+    for prec in (P.rtbte.FP64, P.rtbte.MIXED):
+        kw = dict(precision=prec, rtol=1e-6, atol_el=1e-9, atol_ph=1e-11, fast_mode=1, h_fast=0.5)
+        ctx, y, hist = _run_batched_mis_adaptive(P, torch, cases, kw, 8.0, 30.0)
+        assert hist[-1][0] == 30.0 and len(hist) >= 3
+        res[prec] = y
+    assert np.max(np.abs(res[P.rtbte.MIXED] - res[P.rtbte.FP64])) <= 1e-5
