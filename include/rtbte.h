@@ -22,6 +22,8 @@
  *     buffers of doubles on the context's device.  y holds the instances
  *     back to back at the offsets reported by rtbte_layout; within an
  *     instance it is [f (n_el); N (n_ph)].  t, h hold one entry per instance.
+ *   - A stepping call whose t_out is at or before an instance's t leaves that
+ *     instance (its y, t and step sizes) as it is.
  *   - All device work is enqueued on the HIP stream passed in (NULL: the
  *     null stream).  Calls that return results to the host synchronise that
  *     stream; rtbte_rhs does not.
