@@ -16,9 +16,9 @@ Plain numpy, FP64, one vector operation per formula term:
                          ``batch_norm`` and ``SliceFastSolver`` run it on stacked
                          independent instances that share the slow step.
 
-``hnw_initial_step`` (the starting-step heuristic, not from the paper) is
-parity unpinned: nothing fixes its value independently; it is only compared
-with the GPU's starting step.
+``hnw_initial_step`` (the starting-step heuristic of Hairer, Norsett and
+Wanner, not from the paper) is pinned against SciPy's implementation of the
+same algorithm in each of its branches.
 """
 from __future__ import annotations
 

@@ -497,3 +497,31 @@ def test_batched_slow_step_with_a_quiet_instance_is_the_instance_alone():
     assert np.allclose([h[1] for h in Mb.history], [h[1] for h in Ma.history], rtol=1e-8, atol=0)
     assert np.allclose(yb[slices[0]], ya, rtol=1e-10, atol=1e-15)
     assert np.all(yb[slices[1]] == 0.0)
+
+
+@pytest.mark.parametrize("case", ["tiny2d", "linear", "quiet", "small_state"])
+def test_starting_step_matches_scipy(case):
+    """The Hairer-Norsett-Wanner starting step (Solving ODEs I, II.4) against
+    SciPy's own implementation of the same algorithm (select_initial_step,
+    RMS norm with scale atol + rtol |y0|, no interval or step cap), in each
+    of its branches: a nonlinear collision right-hand side, a linear system,
+    a right-hand side that vanishes (d1 = d2 = 0) and a tiny state
+    (d0 < 1e-5)."""
+    from scipy.integrate._ivp.common import select_initial_step
+    import oracle
+    import synth
+    c = I.Controls(rtol=1e-6, atol_el=1e-9, atol_ph=1e-12)
+    if case == "tiny2d":
+        wl = synth.build("tiny2d")
+        o = oracle.Oracle(wl.problem_arrays())
+        rhs, y0 = (lambda v: o.rhs(v)), wl.y0.copy()
+        atol = np.concatenate([np.full(wl.n_el, c.atol_el), np.full(wl.n_ph, c.atol_ph)])
+    else:
+        rng = np.random.default_rng(4)
+        A = -np.diag(rng.uniform(0.1, 3.0, 8))
+        rhs = (lambda v: np.zeros_like(v)) if case == "quiet" else (lambda v: A @ v)
+        y0 = rng.uniform(0.5, 1.5, 8) * (1e-12 if case == "small_state" else 1.0)
+        atol = np.full(8, c.atol_el)
+    h = I.hnw_initial_step(rhs, y0, c, atol, order=4)
+    ref = select_initial_step(lambda t, v: rhs(v), 0.0, y0, 1e300, np.inf, rhs(y0), 1.0, 4, c.rtol, atol)
+    assert abs(h - ref) <= 1e-13 * ref, (h, ref)
