@@ -323,7 +323,11 @@ int rtbte_step_rk4(rtbte_ctx *ctx, double *y, double *t, double h_step, int64_t 
  * fast step.  In a batched context the slow steps are common: every
  * instance must be at the same t (RTBTE_E_UNSUPPORTED otherwise), and each
  * integrates its fast part with its own adaptive steps; an instance computes
- * exactly what it computes alone. */
+ * exactly what it computes alone.  On an error (a fast solve that fails its
+ * error test max_fails + 1 times in a row, a non-finite value) y and t hold
+ * the state at the start of the slow step that failed; the slow steps before
+ * it are kept.  The first call allocates one state-sized work vector kept by
+ * the context. */
 int rtbte_step_multirate(rtbte_ctx *ctx, double *y, double *t, double *h_fast, double t_out,
                          double h_slow, int32_t one_step, void *stream);
 

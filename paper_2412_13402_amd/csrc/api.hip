@@ -142,6 +142,7 @@ struct rtbte_ctx {
   InstState* st_slow = nullptr;  // MIS slow-step controller (adaptive multirate; one entry)
   double* mra = nullptr;         // [3 * ny + nchunk + 2] adaptive multirate: full-step, half-step and
                                  // estimate vectors, then the selected instance's WRMS partials and sizes
+  double* mis_keep = nullptr;    // [ny] multirate: the state at the start of the current slow step
   double* kbuf[5] = {};
   double* zb[2] = {};
   double* ynew = nullptr;
@@ -372,7 +373,7 @@ void free_ctx(rtbte_ctx* c) {
   if (!c) return;
   void* ps[] = {c->ch, c->groups, c->items, c->order, c->item_ptr, c->row_group, c->partial_items,
                 c->mix_idx, c->mix_wq, c->mix_scale, c->popf, c->pk, c->pkw, c->row_inst, c->info_d, c->st,
-                c->st_fast, c->st_slow, c->mra, c->energy_d,
+                c->st_fast, c->st_slow, c->mra, c->mis_keep, c->energy_d,
                 c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
                 c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
                 c->partial, c->tvec, c->summary_d};
@@ -1471,12 +1472,28 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
   double tc = 0.0;
   int rc = mis_setup(c, y, t, h_fast, t_out, "step_multirate", &fixed, &ctl, &tb, &tc, s);
   if (rc) return rc;
+  if (!c->mis_keep) {
+    hipError_t e = hipMalloc((void**)&c->mis_keep, (size_t)c->ny * sizeof(double));
+    if (e != hipSuccess) {
+      c->mis_keep = nullptr;
+      return fail(c, RTBTE_E_NOMEM, "step_multirate: %s", hipGetErrorString(e));
+    }
+  }
+  const size_t nb = (size_t)c->ny * sizeof(double);
   while (tc < t_out) {
     double hs = h_slow;
     const bool last = tc + hs >= t_out;
     if (last) hs = t_out - tc;
+    // the fast solves advance y in place: keep the step's starting state so
+    // that a failure leaves y and t at the start of the failing slow step
+    HIPCHK(c, hipMemcpyAsync(c->mis_keep, y, nb, hipMemcpyDeviceToDevice, s));
     rc = mis_one(c, y, tc, hs, fixed, ctl, tb, s);
-    if (rc) return rc;
+    if (rc) {
+      (void)hipMemcpyAsync(y, c->mis_keep, nb, hipMemcpyDeviceToDevice, s);
+      (void)launch_fill(t, tc, c->n_inst, s);
+      (void)hipStreamSynchronize(s);
+      return rc;
+    }
     tc = last ? t_out : tc + hs;
     c->slow_steps++;
     if (one_step) break;
@@ -1546,7 +1563,7 @@ extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t,
     rc = mis_one(c, y_full, tc, H, fixed, ctl, tb, s);
     if (rc == RTBTE_OK) rc = mis_one(c, y_half, tc, 0.5 * H, fixed, ctl, tb, s);
     if (rc == RTBTE_OK) rc = mis_one(c, y_half, tc + 0.5 * H, 0.5 * H, fixed, ctl, tb, s);
-    if (rc) return rc;
+    if (rc) break;   // y is still the last accepted state (the attempts ran on copies)
     // estimate (y_half - y_full) / (2^3 - 1); weights from the attempt's start
     const double* dv[2] = {y_half, y_full};
     const double one_m[2] = {1.0, -1.0}, seventh[1] = {1.0 / 7.0};

@@ -557,3 +557,35 @@ def test_zero_length_intervals_leave_the_state_alone():
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy(), y0)
         assert t.item() == 5.0 and h.item() == 0.3 and hs.item() == 8.0
+
+
+def test_multirate_failure_leaves_the_start_of_the_failing_slow_step():
+    """A fast solve that fails (max_fails = 0: the first rejection ends it) in
+    the third slow step, after fast steps of its own: the call reports
+    RTBTE_E_STEP and y and t hold the state after the two completed slow
+    steps, which equals the oracle's."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    hs = 1.0
+    kw = dict(fast_mode=0, fast_rtol=1e-8, fast_atol_el=1e-11, fast_atol_ph=1e-13, max_fails=0)
+    say("[int] MIS fast-solver failure in the third slow step")
+    ctx = P.Context(Pr, **kw)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hf = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.RtbteError) as e:
+        ctx.step_multirate(y, t, hf, 10.0, hs)
+    assert e.value.code == P.rtbte.E_STEP
+    torch.cuda.synchronize()
+    o = oracle.Oracle(Pr)
+    c = I.Controls(rtol=1e-8, atol_el=1e-11, atol_ph=1e-13, max_fails=0)
+    solver = I.AdaptiveFastSolver(atol_vec(Pr["n_el"], Pr["n_ph"], 1e-11, 1e-13), c, 0.1)
+    yr = y0.copy()
+    done = 0
+    with pytest.raises(I.StepFailure):
+        while True:
+            yn = I.mis_step(lambda v: o.rhs(v, parts=3), lambda v: o.rhs(v, parts=4), yr, hs, solver)
+            yr, done = yn, done + 1
+    assert done == 2 and t.item() == done * hs
+    assert close(y.cpu().numpy(), yr, 1e-11)
