@@ -4,14 +4,17 @@
  * GPU and write it back.  Shows the C ABI without any Python or PyTorch: the
  * caller owns the device buffers (hipMalloc) and the library works on them.
  *
- *   example_rhs <dir>
+ *   example_rhs <dir> [t_out]
  *
  * <dir>/meta.txt: n_el n_ph n_k_total n_q_total n_eph n_pp sigma_eph sigma_pp
  *                 nsigma hw_cut
  * <dir>/{eps,hw,eph_g2,pp_v2,y}.f64 and {eph_row,eph_partner,eph_phonon,
  * pp_row,pp_a,pp_b}.i32: the arrays of rtbte_problem and the state y.
- * Writes <dir>/ydot.f64 and prints the channel counts.  Exit status 0 on
- * success, 1 with a message on any failure.
+ * Writes <dir>/ydot.f64 and prints the channel counts.  With t_out (fs), it
+ * then advances y from t = 0 to t_out with the adaptive Zonneveld ERK
+ * (default options, starting step chosen by the library) and writes
+ * <dir>/y_out.f64 and a second line: accepted steps, rejected steps.  Exit
+ * status 0 on success, 1 with a message on any failure.
  */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
@@ -35,8 +38,8 @@ static void *read_file(const char *dir, const char *name, size_t elem, int64_t n
 }
 
 int main(int argc, char **argv) {
-  if (argc != 2) {
-    fprintf(stderr, "usage: %s <dir>\n", argv[0]);
+  if (argc != 2 && argc != 3) {
+    fprintf(stderr, "usage: %s <dir> [t_out]\n", argv[0]);
     return 1;
   }
   const char *dir = argv[1];
@@ -100,6 +103,41 @@ int main(int argc, char **argv) {
   int64_t counts[3];
   rtbte_counts(ctx, -1, counts);
   printf("%lld %lld %lld\n", (long long)counts[0], (long long)counts[1], (long long)counts[2]);
+  if (argc == 3) {
+    const double t_out = atof(argv[2]);
+    const double zero = 0.0;
+    double *t_d = NULL, *h_d = NULL;
+    if (hipMalloc((void **)&t_d, sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&h_d, sizeof(double)) != hipSuccess ||
+        hipMemcpy(t_d, &zero, sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h_d, &zero, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      fprintf(stderr, "device scalars failed\n");
+      return 1;
+    }
+    if (rtbte_step_adaptive(ctx, y_d, t_d, h_d, t_out, 0, NULL) != RTBTE_OK) {
+      fprintf(stderr, "rtbte_step_adaptive: %s\n", rtbte_last_error(ctx));
+      return 1;
+    }
+    if (hipMemcpy(y_h, y_d, (size_t)ny * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+      fprintf(stderr, "copy back failed\n");
+      return 1;
+    }
+    snprintf(path, sizeof path, "%s/y_out.f64", dir);
+    FILE *g = fopen(path, "wb");
+    if (!g || fwrite(y_h, sizeof(double), (size_t)ny, g) != (size_t)ny) {
+      fprintf(stderr, "cannot write %s\n", path);
+      return 1;
+    }
+    fclose(g);
+    rtbte_stats st;
+    if (rtbte_get_stats(ctx, 0, &st) != RTBTE_OK) {
+      fprintf(stderr, "rtbte_get_stats: %s\n", rtbte_last_error(ctx));
+      return 1;
+    }
+    printf("%lld %lld\n", (long long)st.n_accept, (long long)st.n_reject);
+    (void)hipFree(t_d);
+    (void)hipFree(h_d);
+  }
   (void)hipFree(y_d);
   (void)hipFree(ydot_d);
   rtbte_destroy(ctx);

@@ -1,7 +1,8 @@
 """The C ABI used from plain C: the example program (built with the
 library) reads a problem and a state, evaluates the right-hand side on the
 GPU into caller-owned device buffers and writes it back; the result matches
-the oracle on every row (1e-12 A_i) and the channel counts are the oracle's."""
+the oracle on every row (1e-12 A_i) and the channel counts are the oracle's.
+Given an end time it also runs the adaptive ERK, bitwise as the binding does."""
 import os
 import subprocess
 
@@ -10,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import say, torch_cuda
+from tests.gpu_util import say, to_dev, torch_cuda
 from tests.test_gpu_rhs import random_state
 
 pytestmark = pytest.mark.gpu
@@ -46,3 +47,31 @@ def test_c_example_matches_oracle(name, tmp_path):
     ref, S, A = o.rhs(y, scales=True)
     assert g.shape == ref.shape and np.all(np.abs(g - ref) <= 1e-12 * A + 1e-300)
     assert tuple(int(x) for x in r.stdout.split()) == o.counts()
+
+
+def test_c_example_steps_as_the_binding_does(tmp_path):
+    """The C program's adaptive ERK run (default options, library-chosen
+    starting step, 0 -> 5 fs) is bitwise the one the Python binding makes on
+    the same inputs, with the same accepted and rejected steps."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    from paper_2412_13402_amd import build
+    if not os.path.exists(build.EXAMPLE):
+        pytest.fail("the C example is not built (run __graft_entry__.build())")
+    wl = synth.build("tiny2d")
+    prob = wl.problem_arrays()
+    write_problem(str(tmp_path), prob, wl.y0)
+    say("[c] example_rhs tiny2d, ERK to 5 fs")
+    r = subprocess.run([build.EXAMPLE, str(tmp_path), "5.0"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    got = np.fromfile(os.path.join(str(tmp_path), "y_out.f64"), dtype="<f8")
+    acc, rej = (int(v) for v in r.stdout.split("\n")[1].split())
+    ctx = P.Context(prob)
+    y = to_dev(wl.y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.step_adaptive(y, t, h, 5.0)
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    assert np.array_equal(got, y.cpu().numpy())
+    assert (acc, rej) == (st["n_accept"], st["n_reject"]) and acc >= 2
