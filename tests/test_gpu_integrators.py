@@ -589,3 +589,33 @@ def test_multirate_failure_leaves_the_start_of_the_failing_slow_step():
             yr, done = yn, done + 1
     assert done == 2 and t.item() == done * hs
     assert close(y.cpu().numpy(), yr, 1e-11)
+
+
+def test_batched_multirate_adaptive_resume_is_bitwise():
+    """Checkpoint a batched run with the adaptive slow step (the shared slow
+    controller and each instance's fast controller are in the saved state),
+    run on, restore, run again: bitwise the same."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    cases = [coupled(), coupled(scale_eph=0.05, scale_pp=0.006, seed=23)]
+    kw = dict(rtol=1e-6, atol_el=1e-9, atol_ph=1e-11, fast_mode=0, fast_rtol=1e-8, fast_atol_el=1e-11,
+              fast_atol_ph=1e-13)
+    say("[int] batched MIS with adaptive slow step, checkpoint and resume")
+    ctx = P.Context([Pr for Pr, _ in cases], **kw)
+    y = to_dev(np.concatenate([y for _, y in cases]))
+    t = torch.zeros(2, dtype=torch.float64, device="cuda")
+    hf = torch.full((2,), 0.1, dtype=torch.float64, device="cuda")
+    hs = torch.full((2,), 8.0, dtype=torch.float64, device="cuda")
+    ctx.step_multirate_adaptive(y, t, hf, hs, 12.0)
+    state = ctx.get_state()
+    saved = [v.clone() for v in (y, t, hf, hs)]
+    ctx.step_multirate_adaptive(y, t, hf, hs, 30.0)
+    torch.cuda.synchronize()
+    first = [v.cpu().numpy() for v in (y, t, hf, hs)]
+    ctx.set_state(state)
+    y2, t2, hf2, hs2 = saved
+    ctx.step_multirate_adaptive(y2, t2, hf2, hs2, 30.0)
+    torch.cuda.synchronize()
+    for a, b in zip(first, (y2, t2, hf2, hs2)):
+        assert np.array_equal(a, b.cpu().numpy())
+    assert np.all(first[1] == 30.0)
