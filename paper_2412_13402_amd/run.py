@@ -5,12 +5,19 @@ the effective phonon-branch temperatures at the end.
     python -m paper_2412_13402_amd.run --workload graphene2d --method erk --t-end 10000
     python -m paper_2412_13402_amd.run --workload si3d --method mis --h-slow 50 --h-fast 1 --t-end 20000
 
+    python -m paper_2412_13402_amd.run --workload graphene2d --batch 8 --batch-L 24 48 --method mis-adaptive --h-fast 0
+
 Methods: erk (adaptive Zonneveld ERK on the whole right-hand side), rk4
 (fixed steps --h), mis (MRI with MIS coupling, slow step --h-slow; fast part
 by fixed RK4 steps --h-fast, or by the adaptive ERK with --fast-rtol when
 --h-fast is 0), mis-adaptive (the same with the slow step chosen from rtol by
-step doubling, starting from --h-slow).  Progress lines go to stderr at
---checks evenly spaced times; one JSON line goes to stdout at the end.
+step doubling, starting from --h-slow).  With --batch N, N independent
+instances of the workload's model (grid sides and carrier temperatures drawn
+uniformly from --batch-L and --batch-T) advance together in one context:
+each with its own ERK step, or on common slow steps for the multirate
+methods; the history then holds one entry per instance.  Progress lines go
+to stderr at --checks evenly spaced times; one JSON line goes to stdout at
+the end.
 """
 from __future__ import annotations
 
@@ -40,6 +47,10 @@ def main(argv=None):
     ap.add_argument("--graph", type=int, default=1, help="replay step sequences from HIP graphs")
     ap.add_argument("--pid-alt-sign", type=int, default=0,
                     help="1: PID with +k2 on the previous error (ARKODE's form) instead of the printed one")
+    ap.add_argument("--batch", type=int, default=0, help="N > 0: a batch of N instances of the model")
+    ap.add_argument("--batch-L", type=int, nargs=2, default=(24, 72), help="grid side range of a batch")
+    ap.add_argument("--batch-T", type=float, nargs=2, default=(500.0, 3000.0),
+                    help="initial carrier temperature range of a batch (K)")
     a = ap.parse_args(argv)
 
     import torch
@@ -48,35 +59,40 @@ def main(argv=None):
 
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    wl = synth.build(a.workload, **({} if a.L is None else {"L": a.L}))
+    if a.batch > 0:
+        wls = synth.build_batch(a.batch, tuple(a.batch_L), tuple(a.batch_T), recipe=a.workload)
+    else:
+        wls = [synth.build(a.workload, **({} if a.L is None else {"L": a.L}))]
     gen_s = time.perf_counter() - t0
-    log(f"[run] {a.workload}: n_el {wl.n_el} n_ph {wl.n_ph}, generated in {gen_s:.1f} s")
+    n = len(wls)
+    log(f"[run] {a.workload} x {n}: n_el {[w.n_el for w in wls]} n_ph {[w.n_ph for w in wls]}, "
+        f"generated in {gen_s:.1f} s")
     fast_kw = dict(fast_mode=1, h_fast=a.h_fast) if a.h_fast > 0 else \
         dict(fast_mode=0, fast_rtol=a.fast_rtol, fast_atol_el=a.atol_el, fast_atol_ph=a.atol_ph)
     t0 = time.perf_counter()
-    ctx = R.Context(wl.problem_arrays(), precision=R.FP64 if a.precision == "fp64" else R.MIXED,
+    ctx = R.Context([w.problem_arrays() for w in wls], precision=R.FP64 if a.precision == "fp64" else R.MIXED,
                     rtol=a.rtol, atol_el=a.atol_el, atol_ph=a.atol_ph, use_graph=a.graph,
                     pid_alt_sign=a.pid_alt_sign, **fast_kw)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
-    counts = ctx.counts()
-    log(f"[run] context ({a.precision}) in {create_s:.1f} s, channels {counts}")
+    counts = [list(ctx.counts(i)) for i in range(n)]
+    log(f"[run] context ({a.precision}) in {create_s:.1f} s, channels {[sum(c) for c in counts]}")
 
     dev = torch.device("cuda:0")
-    y = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
-    t = torch.zeros(1, dtype=torch.float64, device=dev)
-    h = torch.zeros(1, dtype=torch.float64, device=dev)
-    hs = torch.full((1,), a.h_slow, dtype=torch.float64, device=dev)
-    ne = wl.n_el
-    modes = np.arange(wl.n_ph, dtype=np.int32) % wl.grid["n_modes"]
+    y = torch.tensor(np.concatenate([w.y0 for w in wls]), dtype=torch.float64, device=dev)
+    t = torch.zeros(n, dtype=torch.float64, device=dev)
+    h = torch.zeros(n, dtype=torch.float64, device=dev)
+    hs = torch.full((n,), a.h_slow, dtype=torch.float64, device=dev)
+    layout = [ctx.layout(i) for i in range(n)]
+    modes = [np.arange(w.n_ph, dtype=np.int32) % w.grid["n_modes"] for w in wls]
 
     def advance(tc):
         if a.method == "erk":
             ctx.step_adaptive(y, t, h, tc)
         elif a.method == "rk4":
-            n = int(round((tc - float(t.item())) / a.h))
-            if n > 0:
-                ctx.step_rk4(y, t, a.h, n)
+            k = int(round((tc - float(t[0].item())) / a.h))
+            if k > 0:
+                ctx.step_rk4(y, t, a.h, k)
         elif a.method == "mis":
             ctx.step_multirate(y, t, h, tc, a.h_slow)
         else:
@@ -92,24 +108,36 @@ def main(argv=None):
         torch.cuda.synchronize()
         wall += time.perf_counter() - w0
         yh = y.cpu().numpy()
-        T = ctx.mode_temperatures(y, modes, wl.grid["n_modes"])
-        st = ctx.stats()
-        history.append(dict(t_fs=float(t.item()), wall_s=wall, carriers=float(yh[:ne].sum()),
-                            phonon_T_K=[round(float(x), 3) for x in T], rhs_eph=st["n_rhs_eph"],
-                            rhs_phph=st["n_rhs_phph"]))
-        log(f"[run] t = {t.item():.1f} fs, wall {wall:.2f} s, {st['n_rhs_phph']} ph-ph / {st['n_rhs_eph']} e-ph "
-            f"evaluations, branch T = {', '.join(f'{x:.1f}' for x in T)} K")
-    st = ctx.stats()
-    res = dict(workload=a.workload, n_el=wl.n_el, n_ph=wl.n_ph, channels=list(counts), precision=a.precision,
-               method=a.method, t_end_fs=a.t_end, wall_s=wall, sim_ps_per_s=a.t_end * 1e-3 / wall,
-               generate_s=gen_s, create_s=create_s, steps=st["n_accept"], rejected=st["n_reject"],
-               fast_steps=st["n_fast_accept"], rhs_eph=st["n_rhs_eph"], rhs_phph=st["n_rhs_phph"],
-               h_last=st["h_last"], h_slow_last=float(hs.item()) if a.method == "mis-adaptive" else None,
+        th = t.cpu().numpy()
+        entry = []
+        for i, (w, (off, ne, nph)) in enumerate(zip(wls, layout)):
+            T = ctx.mode_temperatures(y, modes[i], w.grid["n_modes"], inst=i)
+            st = ctx.stats(i)
+            entry.append(dict(t_fs=float(th[i]), carriers=float(yh[off:off + ne].sum()),
+                              phonon_T_K=[round(float(x), 3) for x in T], rhs_eph=st["n_rhs_eph"],
+                              rhs_phph=st["n_rhs_phph"]))
+        e0 = dict(entry[0], wall_s=wall)
+        history.append(e0 if n == 1 else dict(wall_s=wall, instances=entry))
+        log(f"[run] t = {th[0]:.1f} fs, wall {wall:.2f} s, instance 0: {e0['rhs_phph']} ph-ph / "
+            f"{e0['rhs_eph']} e-ph evaluations, branch T = {', '.join(f'{x:.1f}' for x in e0['phonon_T_K'])} K")
+    sts = [ctx.stats(i) for i in range(n)]
+    one = lambda key: sts[0][key] if n == 1 else [s_[key] for s_ in sts]
+    res = dict(workload=a.workload, n_inst=n, n_el=one_or([w.n_el for w in wls]), n_ph=one_or([w.n_ph for w in wls]),
+               channels=counts[0] if n == 1 else counts, precision=a.precision, method=a.method,
+               t_end_fs=a.t_end, wall_s=wall, sim_ps_per_s=n * a.t_end * 1e-3 / wall,
+               generate_s=gen_s, create_s=create_s, steps=one("n_accept"), rejected=one("n_reject"),
+               fast_steps=one("n_fast_accept"), rhs_eph=one("n_rhs_eph"), rhs_phph=one("n_rhs_phph"),
+               h_last=one("h_last"), h_slow_last=float(hs[0].item()) if a.method == "mis-adaptive" else None,
                options=dict(rtol=a.rtol, atol_el=a.atol_el, atol_ph=a.atol_ph, h=a.h, h_slow=a.h_slow,
-                            h_fast=a.h_fast, fast_rtol=a.fast_rtol, pid_alt_sign=a.pid_alt_sign),
+                            h_fast=a.h_fast, fast_rtol=a.fast_rtol, pid_alt_sign=a.pid_alt_sign,
+                            batch=a.batch, batch_L=list(a.batch_L), batch_T=list(a.batch_T)),
                history=history)
     print(json.dumps(res))
     return res
+
+
+def one_or(v):
+    return v[0] if len(v) == 1 else v
 
 
 if __name__ == "__main__":

@@ -31,3 +31,24 @@ def test_run_driver(method, extra, capsys):
     assert abs(res["history"][-1]["carriers"] - n0) <= 1e-9 * n0
     T = res["history"][-1]["phonon_T_K"]
     assert len(T) == wl.grid["n_modes"] and all(np.isfinite(T)) and all(x > 0 for x in T)
+
+
+@pytest.mark.parametrize("method,extra", [("erk", []), ("mis-adaptive", ["--h-slow", "0.5", "--h-fast", "0"])])
+def test_run_driver_batch(method, extra, capsys):
+    """A batch of three small graphene-like instances through the run driver:
+    every instance reaches the end time and keeps its carrier number."""
+    torch_cuda()
+    from paper_2412_13402_amd import run
+    import synth
+    say(f"[cli] run --batch 3 {method}")
+    res = run.main(["--workload", "graphene2d", "--batch", "3", "--batch-L", "8", "12", "--method", method,
+                    "--t-end", "20", "--checks", "2"] + extra)
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert out["n_inst"] == 3 and len(out["steps"]) == 3
+    ws = synth.build_batch(3, (8, 12), (500.0, 3000.0))
+    last = res["history"][-1]["instances"]
+    for w, e in zip(ws, last):
+        assert e["t_fs"] == 20.0
+        n0 = float(w.y0[:w.n_el].sum())
+        assert abs(e["carriers"] - n0) <= 1e-9 * n0
+        assert all(np.isfinite(e["phonon_T_K"])) and all(x > 0 for x in e["phonon_T_K"])
