@@ -32,7 +32,7 @@ import numpy as np
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workload", default="graphene2d")
-    ap.add_argument("--L", type=int, default=None, help="grid side (default: the recipe's)")
+    ap.add_argument("--L", type=int, default=None, help="grid side (default: the recipe's; --batch draws its own)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--method", choices=("erk", "rk4", "mis", "mis-adaptive"), default="erk")
     ap.add_argument("--t-end", type=float, default=10000.0, help="fs")
