@@ -180,6 +180,32 @@ def test_pid_properties():
     assert I.pid_eta(1e12, 1.0, 1.0, False, False, c, fails=c.small_nef + 2) == c.eta_fail_min
 
 
+@pytest.mark.parametrize("accepted", [True, False])
+def test_pid_history_exponents(accepted):
+    """Which gain multiplies which past error (Eq. (pid_controller)): with
+    everything else held, doubling eps_{k-1} scales the ratio by 2^(-k2/p)
+    (printed form; 2^(+k2/p) in the alternating form) and doubling eps_{k-2}
+    by 2^(-k3/p), with the gains and the order the paper states.  The points
+    lie inside the growth and rejection limits."""
+    pp = _paper_params()
+    k1, k2, k3, p = pp["pid_a1"], pp["pid_a2"], pp["pid_a3"], pp["pid_order"]
+    eps = 0.5 if accepted else 8.0
+    e1, e2 = 0.3, 0.4
+    for alt, s2 in ((False, -1.0), (True, 1.0)):
+        c = I.Controls(alt_sign=alt)
+        base = I.pid_eta(eps, e1, e2, accepted, False, c)
+        assert c.eta_fail_min < base < (c.eta_max if accepted else c.eta_fail_max)
+        r1 = I.pid_eta(eps, 2 * e1, e2, accepted, False, c) / base
+        r2 = I.pid_eta(eps, e1, 2 * e2, accepted, False, c) / base
+        r0 = I.pid_eta(2 * eps if accepted else eps / 2, e1, e2, accepted, False, c) / base
+        assert r1 == pytest.approx(2.0 ** (s2 * k2 / p), rel=1e-14)
+        assert r2 == pytest.approx(2.0 ** (-k3 / p), rel=1e-14)
+        assert r0 == pytest.approx(2.0 ** ((-k1 if accepted else k1) / p), rel=1e-14)
+        # the whole ratio at one point, from the equation with the stated gains
+        want = c.safety * eps ** (-k1 / p) * e1 ** (s2 * k2 / p) * e2 ** (-k3 / p)
+        assert base == pytest.approx(want, rel=1e-14)
+
+
 def test_adaptive_meets_tolerance_on_relaxation():
     """Global error of the adaptive ERK on a linear relaxation problem stays
     within a small multiple of the tolerance and shrinks with it."""
