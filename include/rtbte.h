@@ -402,8 +402,12 @@ int rtbte_set_state(rtbte_ctx *ctx, const void *buf, size_t len);
  * enable = 1 every launch is bracketed by HIP events on its own stream.
  * rtbte_profile resets the totals; rtbte_profile_read synchronises the device
  * and returns the summed kernel time (ms), the number of launches and their
- * summed algorithmic bytes (every stored channel of the evaluated parts once,
- * 16 B each, plus row bookkeeping and each state vector read or written once). */
+ * summed algorithmic bytes: every stored channel of the evaluated parts once
+ * at its storage size (FP64: 12 B packed, 16 B plain; mixed: 8 B packed
+ * words, 10 B for the 16-bit-head formats, plus 4 B per 512 channels for
+ * the block scales), the state read once (8 B per state; mixed: its 4-byte
+ * population code), and the group and item tables (40 B per group; 24 B
+ * item record, 4 B order entry and 128 B of row sums per item). */
 int rtbte_profile(rtbte_ctx *ctx, int32_t enable);
 int rtbte_profile_read(rtbte_ctx *ctx, double *total_ms, int64_t *launches, double *bytes);
 

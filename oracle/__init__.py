@@ -26,16 +26,29 @@ _LIB = None
 PART_EPH, PART_PHE, PART_PHPH, PART_ALL = 1, 2, 4, 7
 
 
-def lib_path() -> str:
-    return os.path.join(_HERE, "liboracle.so")
+# RTBTE_HOST_SANITIZE=1 selects a build of the same source under
+# AddressSanitizer and UndefinedBehaviorSanitizer (host code only; the
+# process must preload the sanitizer runtimes).
+_SANITIZE = os.environ.get("RTBTE_HOST_SANITIZE") == "1"
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                  "-fno-omit-frame-pointer", "-g"]
 
 
-def build_lib() -> str:
-    """Compile rtbte_oracle.c (plain C, OpenMP, no fast-math, no FMA contraction)."""
+def lib_path(sanitized=None) -> str:
+    san = _SANITIZE if sanitized is None else sanitized
+    return os.path.join(_HERE, "liboracle_san.so" if san else "liboracle.so")
+
+
+def build_lib(sanitized=None) -> str:
+    """Compile rtbte_oracle.c (plain C, OpenMP, no fast-math, no FMA
+    contraction); with sanitized (default: RTBTE_HOST_SANITIZE) into
+    liboracle_san.so under ASan and UBSan."""
     import subprocess
-    out = lib_path()
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", out + ".tmp", os.path.join(_HERE, "rtbte_oracle.c"), "-lm"]
+    san = _SANITIZE if sanitized is None else sanitized
+    out = lib_path(san)
+    cmd = (["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+            "-fno-fast-math", "-Wall"] + (SANITIZE_FLAGS if san else []) +
+           ["-o", out + ".tmp", os.path.join(_HERE, "rtbte_oracle.c"), "-lm"])
     subprocess.check_call(cmd)
     os.replace(out + ".tmp", out)
     return out

@@ -1302,11 +1302,14 @@ int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_ste
         int64_t fixed_steps, double fixed_h, hipStream_t s) {
   HIPCHK(c, launch_begin(st, t, h, c->n_inst, t_out, one_step, h_cap, fixed_steps, fixed_h, s));
   if (h && fixed_steps <= 0) {
-    std::vector<double> hh((size_t)c->n_inst);
+    // the starting-step estimate (two right-hand sides) only when an
+    // instance that still has to move asks for it
+    std::vector<double> hh((size_t)c->n_inst), tt((size_t)c->n_inst);
     HIPCHK(c, hipMemcpyAsync(hh.data(), h, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(tt.data(), t, tt.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     bool need = false;
-    for (double v : hh) need |= !(v > 0.0);
+    for (size_t i = 0; i < hh.size(); ++i) need |= !(hh[i] > 0.0) && tt[i] < t_out;
     if (need) {
       int rc = enqueue_h0(c, y, parts, forcing, st, ctl, s);
       if (rc) return rc;

@@ -966,11 +966,13 @@ __global__ void k_begin(InstState* st, const double* t_in, const double* h_in, i
     s.last = fixed_steps == 1;
   } else {
     s.t_out = t_out;
+    if (!(s.t < s.t_out)) s.done = 1;
     if (h_in) {
-      if (h_in[inst] > 0.0) s.h = h_in[inst];
+      // h <= 0 asks for the starting-step estimate; an instance already at
+      // or past t_out keeps the h it was given (written back unchanged)
+      if (h_in[inst] > 0.0 || s.done) s.h = h_in[inst];
       else s.need_h0 = 1;
     }
-    if (!(s.t < s.t_out)) s.done = 1;
     if (!s.need_h0) plan_next(s);
   }
   st[inst] = s;

@@ -28,16 +28,27 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 
-def lib_path() -> str:
-    return os.path.join(_HERE, "libsynth.so")
+# RTBTE_HOST_SANITIZE=1 selects a build of the same source under
+# AddressSanitizer and UndefinedBehaviorSanitizer (host code only; the
+# process must preload the sanitizer runtimes).
+_SANITIZE = os.environ.get("RTBTE_HOST_SANITIZE") == "1"
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                  "-fno-omit-frame-pointer", "-g"]
 
 
-def build_lib() -> str:
-    """Compile gen.cpp into libsynth.so (host g++, OpenMP)."""
+def lib_path(sanitized=None) -> str:
+    san = _SANITIZE if sanitized is None else sanitized
+    return os.path.join(_HERE, "libsynth_san.so" if san else "libsynth.so")
+
+
+def build_lib(sanitized=None) -> str:
+    """Compile gen.cpp into libsynth.so (host g++, OpenMP); with sanitized
+    (default: RTBTE_HOST_SANITIZE) into libsynth_san.so under ASan and UBSan."""
     import subprocess
-    out = lib_path()
-    cmd = ["g++", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c++17", "-Wall",
-           "-o", out + ".tmp", os.path.join(_HERE, "gen.cpp")]
+    san = _SANITIZE if sanitized is None else sanitized
+    out = lib_path(san)
+    cmd = (["g++", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c++17", "-Wall"] +
+           (SANITIZE_FLAGS if san else []) + ["-o", out + ".tmp", os.path.join(_HERE, "gen.cpp")])
     subprocess.check_call(cmd)
     os.replace(out + ".tmp", out)
     return out

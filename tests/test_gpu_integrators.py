@@ -107,11 +107,18 @@ def test_starting_step_matches_oracle():
     h = torch.zeros(1, dtype=torch.float64, device="cuda")
     ctx.step_adaptive(y, t, h, 1e9, one_step=True)
     torch.cuda.synchronize()
-    # the first attempt uses the estimate; its size is the first accepted step
-    # unless that attempt was rejected
+    # the first attempt uses the estimate; on this state the oracle's error
+    # test at that step is ~3e-5, far below 1, so it is accepted and its size
+    # is the first step taken
+    yr, lte = I.erk_attempt(o.rhs, y0.copy(), h_ref)
+    eps = I.wrms(lte, y0, c.rtol, av)
+    assert eps < 1e-3
     st = ctx.stats()
-    if st["n_reject"] == 0:
-        assert abs(t.item() - h_ref) <= 1e-12 * h_ref
+    assert st["n_reject"] == 0 and st["n_accept"] == 1
+    assert abs(t.item() - h_ref) <= 1e-12 * h_ref
+    # and the next step is the controller's first-step growth of it
+    h_next = h_ref * I.pid_eta(eps, 1.0, 1.0, True, True, c)
+    assert abs(h.item() - h_next) <= 1e-6 * h_next
 
 
 @pytest.mark.parametrize("name,alt", [("toy2d", 0), ("coupled", 0), ("coupled", 1)])
@@ -557,6 +564,37 @@ def test_zero_length_intervals_leave_the_state_alone():
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy(), y0)
         assert t.item() == 5.0 and h.item() == 0.3 and hs.item() == 8.0
+    # h = 0 asks for the starting-step estimate, but not for an instance that
+    # does not move: no right-hand side is evaluated and h comes back as 0
+    for t_out in (5.0, 4.0):
+        y = to_dev(y0)
+        t = torch.full((1,), 5.0, dtype=torch.float64, device="cuda")
+        h = torch.zeros(1, dtype=torch.float64, device="cuda")
+        n0 = ctx.stats()["n_rhs_eph"]
+        ctx.step_adaptive(y, t, h, t_out)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), y0)
+        assert t.item() == 5.0 and h.item() == 0.0
+        assert ctx.stats()["n_rhs_eph"] == n0
+    # batched: instance 0 already at t_out, instance 1 starting from 0, both
+    # with h = 0; instance 1 takes the step it takes alone, instance 0 stays
+    ctxb = P.Context([Pr, Pr])
+    y = to_dev(np.concatenate([y0, y0]))
+    t = torch.tensor([5.0, 0.0], dtype=torch.float64, device="cuda")
+    h = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ctxb.step_adaptive(y, t, h, 5.0, one_step=True)
+    ctx1 = P.Context(Pr)
+    y1 = to_dev(y0)
+    t1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    h1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx1.step_adaptive(y1, t1, h1, 5.0, one_step=True)
+    torch.cuda.synchronize()
+    yb = y.cpu().numpy()
+    n = len(y0)
+    assert np.array_equal(yb[:n], y0) and t[0].item() == 5.0 and h[0].item() == 0.0
+    assert 0.0 < t1.item() < 5.0 and h1.item() > 0.0
+    assert np.array_equal(yb[n:], y1.cpu().numpy())
+    assert t[1].item() == t1.item() and h[1].item() == h1.item()
 
 
 def test_multirate_failure_leaves_the_start_of_the_failing_slow_step():
