@@ -251,6 +251,25 @@ int rtbte_stored_counts(const rtbte_ctx *ctx, int32_t inst, int64_t counts[3]);
  * are device arrays of rtbte_ny() doubles and must not overlap. */
 int rtbte_rhs(rtbte_ctx *ctx, const double *y, double *ydot, int32_t parts, void *stream);
 
+/* rtbte_rhs for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results as rtbte_rhs (bitwise),
+ * but the call allocates nothing: its scratch (the per-work-item row sums,
+ * and in mixed precision the FP32 population codes) lives in one static
+ * device buffer of rtbte_noalloc_scratch_limit() bytes (32 MiB), which each
+ * device the library runs on holds until the process ends.  A context whose
+ * shape needs more (rtbte_noalloc_scratch_bytes) gets RTBTE_E_INVAL and must
+ * use rtbte_rhs.  Every context on a device shares that device's buffer:
+ * calls that can overlap in time (different streams, or different host
+ * threads, without ordering between them) race and give wrong results; calls
+ * on one stream are ordered and safe.  The kernel launches of this call are
+ * not timed by rtbte_profile. */
+int rtbte_rhs_noalloc(rtbte_ctx *ctx, const double *y, double *ydot, int32_t parts, void *stream);
+/* Static scratch bytes rtbte_rhs_noalloc needs for this context (-1: ctx
+ * NULL), and the size of the static buffer. */
+int64_t rtbte_noalloc_scratch_bytes(const rtbte_ctx *ctx);
+int64_t rtbte_noalloc_scratch_limit(void);
+
 /* Linearized (relaxation-time) rates of the parts in `parts` at the state y:
  * rates[i] = -d(ydot_i)/d(y_i) with every partner population held fixed,
  * i.e. the sum over row i's channels of W times the derivative of the

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -93,6 +94,40 @@ T* dalloc(size_t n, hipError_t* err) {
   void* p = nullptr;
   *err = hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
   return static_cast<T*>(p);
+}
+
+// Scratch of the allocation-free right-hand side (rtbte_rhs_noalloc): the
+// per-item row sums of one evaluation and, in mixed precision, the
+// population codes after them.  Every device the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device memory: its device address is taken once per
+// device with hipGetSymbolAddress (scratch_setup) and only that address is
+// passed to kernels.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;   // device address of `scratch`, per device (null: not taken yet)
+
+// With `device` current: its address of `scratch` (taken on first use).
+hipError_t scratch_setup(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize((size_t)device + 1, nullptr);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
+
+// Bytes of static scratch one right-hand side of this shape needs: the item
+// row sums (rounded up to 256 B), then the FP32 population codes (mixed).
+size_t noalloc_scratch_bytes(int64_t n_items, int64_t ny, bool mixed) {
+  const size_t sums = (((size_t)std::max<int64_t>(n_items, 1) * kMaxGroupRows * sizeof(double)) + 255) & ~(size_t)255;
+  return sums + (mixed ? (size_t)ny * sizeof(float) : 0);
 }
 
 }  // namespace
@@ -186,6 +221,8 @@ struct rtbte_ctx {
   // launch-shape tuning: source of the shape and the time it measured
   int tuned = 0;                   // 0 given/default, 1 measured at create, 2 from the cache
   double tuned_ms = 0.0;
+  // this device's address of the static scratch (rtbte_rhs_noalloc)
+  void* scratch_dev = nullptr;
 };
 
 static int fail(rtbte_ctx* c, int code, const char* fmt, ...) {
@@ -522,9 +559,17 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   if (o.device < 0 || o.device >= ndev) return fail(nullptr, RTBTE_E_INVAL, "device %d out of range", o.device);
   if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, RTBTE_E_HIP, "hipSetDevice failed");
 
+  void* scratch_dev = nullptr;
+  {
+    const hipError_t e = scratch_setup(o.device, &scratch_dev);
+    if (e != hipSuccess)
+      return fail(nullptr, RTBTE_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  }
+
   const int GE = o.group_rows_el, GP = o.group_rows_ph;
   rtbte_ctx* c = new rtbte_ctx();
   c->device = o.device;
+  c->scratch_dev = scratch_dev;
   c->opt = o;
   c->n_inst = n_inst;
   c->info.resize(n_inst);
@@ -1006,9 +1051,17 @@ hipError_t harvest(rtbte_ctx* c) {
 // kernel, the one that streams the channels and is timed when profiling),
 // then the per-row sums of items with the plain or stage epilogue.
 // fp64: use the FP64 lists of a mixed context that keeps them (not timed).
+// partial, popf: scratch to use instead of the context's own (the
+// allocation-free entry point; its launches are never timed).
 hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState* st, const FinishArgs& f,
-                      bool stage, hipStream_t s, bool deriv = false, bool fp64 = false) {
+                      bool stage, hipStream_t s, bool deriv = false, bool fp64 = false,
+                      double* partial = nullptr, float* popf = nullptr) {
   const bool use_mixed = c->mixed && !fp64;
+  const bool own = partial == nullptr;
+  if (own) {
+    partial = c->partial_items;
+    popf = c->popf;
+  }
   RowArgs a{};
   a.deriv = deriv ? 1 : 0;
   a.ch = c->ch;
@@ -1023,7 +1076,7 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
   a.n_items = c->n_items;
   a.parts = parts;
   a.z = z;
-  a.partial = c->partial_items;
+  a.partial = partial;
   a.st = st;
   MixArgs m{};
   if (use_mixed) {
@@ -1031,7 +1084,7 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
     m.wq = c->mix_wq;
     m.scale = c->mix_scale;
     m.n_scale = (c->n_ch + kMixBlock - 1) / kMixBlock;
-    m.pop = c->popf;
+    m.pop = popf;
     m.groups = c->groups;
     m.items = c->items;
     m.order = c->order;
@@ -1041,16 +1094,16 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
     m.pack_p = c->pack_p;
     m.pack_m = c->pack_m;
     m.info = c->info_d;
-    m.partial = c->partial_items;
+    m.partial = partial;
     m.st = st;
   }
   auto launch = [&]() {
     if (!use_mixed) return launch_items(a, c->slots, s);
-    hipError_t e2 = launch_popf(c->popf, z, c->row_group, c->groups, c->ny, s);
+    hipError_t e2 = launch_popf(popf, z, c->row_group, c->groups, c->ny, s);
     return e2 == hipSuccess ? launch_items_mixed(m, c->slots, s) : e2;
   };
   hipError_t e;
-  if (!c->prof || fp64) {
+  if (!c->prof || fp64 || !own) {
     e = launch();
   } else {
     std::pair<hipEvent_t, hipEvent_t> ev;
@@ -1072,7 +1125,7 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
   fa.groups = c->groups;
   fa.row_group = c->row_group;
   fa.item_ptr = c->item_ptr;
-  fa.partial = c->partial_items;
+  fa.partial = partial;
   fa.n_rows = c->ny;
   return launch_finish_rows(fa, stage, s);
 }
@@ -1143,6 +1196,41 @@ extern "C" int rtbte_rhs(rtbte_ctx* c, const double* y, double* ydot, int32_t pa
     if (parts & (1 << k)) c->extra_rhs[k]++;
   return RTBTE_OK;
 }
+
+// rtbte_rhs with its scratch in the static device buffer: the same kernels,
+// no allocation of any kind.  Nothing in the scratch has to start at zero:
+// every item row sum and population code a call reads is written earlier in
+// the same call.
+extern "C" int rtbte_rhs_noalloc(rtbte_ctx* c, const double* y, double* ydot, int32_t parts, void* stream) {
+  if (!c) return RTBTE_E_INVAL;
+  if (!y || !ydot || parts < 1 || parts > 7) return fail(c, RTBTE_E_INVAL, "rtbte_rhs_noalloc: bad arguments");
+  if (y == ydot) return fail(c, RTBTE_E_INVAL, "rtbte_rhs_noalloc: y and ydot must not overlap");
+  const size_t need = noalloc_scratch_bytes(c->n_items, c->ny, c->mixed);
+  if (need > kStaticScratchBytes)
+    return fail(c, RTBTE_E_INVAL,
+                "rtbte_rhs_noalloc: this context needs %zu bytes of scratch, more than the static %zu "
+                "(%lld work items, %lld states); use rtbte_rhs", need, kStaticScratchBytes,
+                (long long)c->n_items, (long long)c->ny);
+  if (!c->scratch_dev) return fail(c, RTBTE_E_HIP, "rtbte_rhs_noalloc: static scratch not set up");
+  HIPCHK(c, hipSetDevice(c->device));
+  unsigned char* base = static_cast<unsigned char*>(c->scratch_dev);
+  double* sums = reinterpret_cast<double*>(base);
+  float* codes = c->mixed ? reinterpret_cast<float*>(base + noalloc_scratch_bytes(c->n_items, c->ny, false))
+                          : nullptr;
+  FinishArgs f{};
+  f.out = ydot;
+  HIPCHK(c, rhs_launch(c, y, parts, nullptr, f, false, (hipStream_t)stream, false, false, sums, codes));
+  for (int k = 0; k < 3; ++k)
+    if (parts & (1 << k)) c->extra_rhs[k]++;
+  return RTBTE_OK;
+}
+
+extern "C" int64_t rtbte_noalloc_scratch_bytes(const rtbte_ctx* c) {
+  if (!c) return -1;
+  return (int64_t)noalloc_scratch_bytes(c->n_items, c->ny, c->mixed);
+}
+
+extern "C" int64_t rtbte_noalloc_scratch_limit(void) { return (int64_t)kStaticScratchBytes; }
 
 // ---------------------------------------------------------------- integrators
 namespace {

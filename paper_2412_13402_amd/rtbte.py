@@ -117,6 +117,11 @@ def load():
     L.rtbte_counts.argtypes = [_vp, i32, ctypes.POINTER(i64)]
     L.rtbte_stored_counts.argtypes = [_vp, i32, ctypes.POINTER(i64)]
     L.rtbte_rhs.argtypes = [_vp, _vp, _vp, i32, _vp]
+    L.rtbte_rhs_noalloc.argtypes = [_vp, _vp, _vp, i32, _vp]
+    L.rtbte_noalloc_scratch_bytes.argtypes = [_vp]
+    L.rtbte_noalloc_scratch_bytes.restype = i64
+    L.rtbte_noalloc_scratch_limit.argtypes = []
+    L.rtbte_noalloc_scratch_limit.restype = i64
     L.rtbte_rates.argtypes = [_vp, _vp, _vp, i32, _vp]
     L.rtbte_check_fp64.argtypes = [_vp, _vp, _vp, _vp]
     L.rtbte_energy_average.argtypes = [_vp, _vp, _vp, i32, i32, dbl, dbl, i32, _vp, _vp]
@@ -139,6 +144,11 @@ def load():
     L.rtbte_profile_read.argtypes = [_vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     _LIB = L
     return L
+
+
+def noalloc_scratch_limit() -> int:
+    """Size of the static device buffer of rhs_noalloc (bytes)."""
+    return int(load().rtbte_noalloc_scratch_limit())
 
 
 def default_options(**kw) -> Options:
@@ -245,6 +255,16 @@ class Context:
     def rhs(self, y, ydot, parts=PART_ALL, stream=None):
         self._check(load().rtbte_rhs(self._h, _dptr(y, self.ny, "y"), _dptr(ydot, self.ny, "ydot"),
                                      int(parts), _stream(stream)))
+
+    def rhs_noalloc(self, y, ydot, parts=PART_ALL, stream=None):
+        """rhs() with its scratch in the library's static device buffer (no
+        allocation; calls that overlap in time on one device race)."""
+        self._check(load().rtbte_rhs_noalloc(self._h, _dptr(y, self.ny, "y"), _dptr(ydot, self.ny, "ydot"),
+                                             int(parts), _stream(stream)))
+
+    def noalloc_scratch_bytes(self) -> int:
+        """Static scratch bytes rhs_noalloc needs for this context."""
+        return int(load().rtbte_noalloc_scratch_bytes(self._h))
 
     def rates(self, y, out, parts=PART_ALL, stream=None):
         """Linearized rates -d(ydot_i)/d(y_i), partners held fixed (FP64 contexts)."""

@@ -1,0 +1,71 @@
+"""The allocation-free right-hand side (rtbte_rhs_noalloc) against rtbte_rhs.
+
+Both run the same kernels; the allocation-free call keeps its scratch (item
+row sums, mixed population codes) in the library's static device buffer.
+Two calls in a row on different contexts, the second smaller, so the second
+reads a buffer that still holds the first call's contents.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import assert_rows_close, say, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(wl, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.uniform(0.05, 0.95, wl.n_el), rng.uniform(0.0, 2.0, wl.n_ph)])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_noalloc_rhs_equals_rhs(precision):
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    prec = P.rtbte.FP64 if precision == "fp64" else P.rtbte.MIXED
+    limit = P.rtbte.noalloc_scratch_limit()
+    assert limit == 32 << 20
+    for name, kw in (("graphene2d", dict(L=24)), ("tiny2d", {})):   # the second call is smaller
+        wl = synth.build(name, **kw)
+        say(f"[noalloc] {precision} {name} {kw}")
+        ctx = P.Context(wl.problem_arrays(), precision=prec)
+        assert 0 < ctx.noalloc_scratch_bytes() <= limit
+        orc = oracle.Oracle(wl.problem_arrays()) if prec == P.rtbte.FP64 else None
+        for seed, y0 in ((None, wl.y0), (7, _state(wl, 7))):
+            y = to_dev(y0)
+            for parts in (P.PART_ALL, P.PART_EPH, P.PART_PHE | P.PART_PHPH):
+                a = torch.full_like(y, float("nan"))
+                b = torch.full_like(y, float("nan"))
+                ctx.rhs(y, a, parts)
+                ctx.rhs_noalloc(y, b, parts)
+                torch.cuda.synchronize()
+                ga, gb = a.cpu().numpy(), b.cpu().numpy()
+                assert np.all(np.isfinite(gb))
+                assert np.array_equal(ga, gb), f"{name} seed {seed} parts {parts}"
+                if orc is not None:
+                    ref, _, A = orc.rhs(y0, parts=parts, scales=True)
+                    assert_rows_close(gb, ref, A, 1e-12, f"noalloc {name} parts {parts}")
+        del ctx
+
+
+def test_noalloc_rejects_a_shape_beyond_the_static_buffer():
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl = synth.build("graphene2d", L=36)
+    say("[noalloc] over the limit: graphene2d L=36, 16 channels per item")
+    ctx = P.Context(wl.problem_arrays(), item_channels=16)
+    assert ctx.noalloc_scratch_bytes() > P.rtbte.noalloc_scratch_limit()
+    y = to_dev(wl.y0)
+    out = torch.zeros_like(y)
+    with pytest.raises(P.RtbteError) as e:
+        ctx.rhs_noalloc(y, out, P.PART_ALL)
+    assert e.value.code == P.rtbte.E_INVAL
+    assert "static" in str(e.value)
+    torch.cuda.synchronize()
+    assert float(out.abs().max().item()) == 0.0      # nothing was launched
+    # the allocating entry point still serves this context
+    ctx.rhs(y, out, P.PART_ALL)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(out.cpu().numpy()))
