@@ -1,22 +1,33 @@
 """Benchmark of the rt-BTE hot path on one MI355X.
 
 Workload: the graphene-like coupled e-ph + ph-ph problem (120x120 k = q grid,
-2 pi bands, 6 phonon branches, ~1.6e8 + 0.8e8 e-ph and ~5e8 ph-ph stored
-channels, FP64), advanced by the adaptive Zonneveld ERK (rtol 1e-6).  One
+2 pi bands, 6 phonon branches, ~1.6e8 + 0.8e8 e-ph and ~5e8 ph-ph channels,
+6.1e8 stored), advanced by the adaptive Zonneveld ERK (rtol 1e-6).  One
 benchmark step is one accepted ERK step: its attempts (5 right-hand-side
 evaluations each, every stored channel streamed once per evaluation), the
 fused stage updates, the WRMS error norm and the device-side PID control.
 
-Prints one JSON line: channels/s (the metric), the roofline of the collision
-kernel (algorithmic bytes per launch over its HIP-event-timed duration), the
-simulated ps/s, and the FP64 oracle timed on this host's cores.  The FP64
-channels are the library's default packed 12-byte layout; the same steps
-with the plain 16-byte layout are reported beside them
-("fp64_plain_channels").  A second leg
-runs the same workload and steps in mixed precision ("mixed": its channels/s,
-simulated ps/s and their speedup over FP64, its kernel roofline, the RHS error
-against the oracle after each of its first steps, and the population error
-after 1 ps of RK4 against the FP64 path).
+Prints one JSON line:
+* value: stored channels per second over whole ERK steps (channels streamed
+  per right-hand side times right-hand sides per second; the rate over the
+  channels the sums contain, which counts each folded ph-ph emission pair
+  twice, is value_summed_channels);
+* roofline: the collision kernel's algorithmic bytes per launch over its
+  HIP-event-timed duration, against the 8 TB/s HBM peak;
+* cpu_baseline: the FP64 oracle on this host's cores, same basis;
+* horizon: simulated ps per second from the initial state to 1 ps, FP64 and
+  mixed, printed and ARKODE PID forms, each with its end-time error against
+  an FP64 reference at rtol 1e-9 (the top-level sim_ps_per_s is the FP64
+  printed-form figure);
+* fp64_plain_channels, mixed: the same steps with the plain 16-byte FP64
+  channels and in mixed precision (speedup, kernel roofline, RHS error per
+  step against the oracle, populations after 1 ps of RK4 against FP64);
+* batched: 64 graphene-like instances in one autotuned, graph-replayed mixed
+  context against the same instances one by one in FP64, with errors against
+  an FP64 reference and the mixed-vs-FP64 population error on fixed steps;
+* si3d: the silicon-like 40^3 workload, MIS against the adaptive ERK, slow
+  and fast right-hand-side rooflines, the oracle on a row sample;
+* toy: the small e-ph-only RK4 case beside the oracle.
 """
 import argparse
 import hashlib
@@ -63,9 +74,22 @@ def measured_traffic(workload, precision):
     return e.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, seconds):
+def fp64_dtype(ctx):
+    """The arithmetic type of the FP64 path, with the storage rounding of its
+    channel weights named when the layout rounds them."""
+    _, nbytes, u = ctx.weight_format()
+    if u > 0:
+        import math
+        return (f"f64 (channel weights stored in {nbytes}-byte packed channels to 2^{math.log2(u):.0f} "
+                f"relative; arithmetic, state and control FP64)")
+    return "f64"
+
+
+def cpu_baseline(wl, seconds, stored):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
-    whole Zonneveld ERK attempts (5 full right-hand sides each)."""
+    whole Zonneveld ERK attempts (5 full right-hand sides each).  Its rate is
+    stated on the same basis as the GPU's: right-hand sides per second times
+    the stored channels of one right-hand side (`stored`)."""
     import numpy as np
     from __graft_entry__ import _ensure_built
     _ensure_built(need_oracle=True)
@@ -98,11 +122,12 @@ def cpu_baseline(wl, seconds):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return o, dict(value=n * 5 * ch / el, unit="channels/s", cores=cores, kind="oracle",
+    return o, dict(value=n * 5 * stored / el, unit="channels/s", cores=cores, kind="oracle",
                    sample=f"{n} Zonneveld ERK attempt(s) = {5 * n} full right-hand sides of the "
                           f"same workload from its initial state ({el:.1f} s; list build {build_s:.1f} s "
-                          f"untimed)",
-                   one_thread_value=ch / el1, one_thread_sample=f"1 full right-hand side ({el1:.1f} s)",
+                          f"untimed); rate in stored channels per right-hand side ({stored}), as the GPU value",
+                   value_summed_channels=n * 5 * ch / el,
+                   one_thread_value=stored / el1, one_thread_sample=f"1 full right-hand side ({el1:.1f} s)",
                    cpu_model=model)
 
 
@@ -126,11 +151,24 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 leg with plain 16-byte channels")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched leg")
     ap.add_argument("--batch-t-end", type=float, default=200.0, help="simulated fs of the batched leg")
-    ap.add_argument("--si3d", action="store_true",
-                    help="add the silicon-like 3D leg (40^3, ~2.5e9 channels; minutes): MIS vs ERK")
+    ap.add_argument("--no-si3d", action="store_true",
+                    help="skip the silicon-like 3D leg (40^3, ~2.5e9 channels): MIS vs ERK")
     ap.add_argument("--no-toy", action="store_true", help="skip the small RK4 leg")
     ap.add_argument("--si-L", type=int, default=40)
     ap.add_argument("--si-t-end", type=float, default=200.0)
+    ap.add_argument("--si-sample-rows", type=int, default=40000,
+                    help="rows of the silicon-like workload the oracle baseline evaluates")
+    ap.add_argument("--no-horizon", action="store_true",
+                    help="skip the runs from the initial state to --horizon-fs (simulated ps/s at a stated error)")
+    ap.add_argument("--horizon-fs", type=float, default=1000.0)
+    ap.add_argument("--ref-rtol", type=float, default=1e-9,
+                    help="relative tolerance of the FP64 reference runs the end-time errors are taken against")
+    ap.add_argument("--batch-rk4-fs", type=float, default=1000.0,
+                    help="batched leg: fixed-step RK4 span of the mixed-vs-FP64 population check")
+    ap.add_argument("--batch-rk4-h", type=float, default=4.0)
+    ap.add_argument("--no-tune", action="store_true", help="batched leg: default launch shape, no autotuning")
+    ap.add_argument("--tiled", type=int, default=0, choices=(0, 1),
+                    help="0 (default): per-item collision kernels; 1: tiled (partners staged in LDS)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -162,14 +200,16 @@ def main():
     t0 = time.perf_counter()
     ctx = P.Context(wl.problem_arrays(), rtol=args.rtol, atol_el=1e-9, atol_ph=1e-12,
                     group_rows_el=args.group_rows_el, group_rows_ph=args.group_rows_ph,
-                    item_channels=args.item_channels)
+                    item_channels=args.item_channels, tiled=args.tiled)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     counts = ctx.counts()
     C = sum(counts)
+    stored = ctx.stored_counts()
+    CS = sum(stored)
     log(f"[bench] create {create_s:.1f} s; channels e-ph {counts[0]}, ph-e {counts[1]}, "
-        f"ph-ph {counts[2]} (total {C}); rows per group (el, ph), channels per item {ctx.tuning()}")
-    leg = timed_steps(ctx, wl, args, C, "fp64")
+        f"ph-ph {counts[2]} (total {C}; stored {CS}); rows per group (el, ph), channels per item {ctx.tuning()}")
+    leg = timed_steps(ctx, wl, args, CS, "fp64")
     k = leg["kernel"]
     traffic = measured_traffic(args.workload if args.L is None else f"{args.workload}_L{args.L}", "fp64")
     rec = {
@@ -183,18 +223,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": fp64_dtype(ctx),
         "data": "synthetic (seeded graphene-like band/phonon model and channel lists; no first-principles data)",
         "config": {
             "workload": f"{args.workload}: {'x'.join([str(wl.grid['L'])] * 2)} k=q grid, 2 bands, 6 branches, "
                         f"FP64, adaptive Zonneveld ERK rtol {args.rtol:g}",
             "channels_eph": counts[0], "channels_phe": counts[1], "channels_phph": counts[2],
-            "stored_channels": list(ctx.stored_counts()),
+            "stored_channels": list(stored),
+            "value_counts": "stored channels (streamed once per right-hand side) x right-hand sides / s",
             "n_y": wl.n_y, "rhs_per_step": leg["rhs_per_step"],
             "rows_per_group_el": ctx.tuning()[0], "rows_per_group_ph": ctx.tuning()[1],
             "channels_per_item": ctx.tuning()[2],
         },
+        "value_summed_channels": leg["value"] * C / CS,
         "sim_ps_per_s": leg["sim_ps_per_s"],
+        "sim_ps_per_s_note": f"the {args.steps} timed steps ({leg['t_span'][0]:.1f} -> {leg['t_span'][1]:.1f} fs); "
+                             "the same at a stated error from the initial state: horizon",
         "hbm_frac": k["achieved"] / HBM_PEAK_GBS,
         "roofline": dict(k, traffic=traffic),
         "create_s": create_s,
@@ -215,7 +259,7 @@ def main():
                           item_channels=args.item_channels, fp64_layout=P.rtbte.F64_PLAIN)
         torch.cuda.synchronize()
         cp = time.perf_counter() - t0
-        leg_p = timed_steps(ctx_p, wl, args, C, "fp64 plain", start=leg["start"])
+        leg_p = timed_steps(ctx_p, wl, args, CS, "fp64 plain", start=leg["start"])
         rec["fp64_plain_channels"] = {
             "value": leg_p["value"], "unit": "channels/s", "ms_per_step": leg_p["ms_per_step"],
             "sim_ps_per_s": leg_p["sim_ps_per_s"], "channel_bytes": 16,
@@ -230,10 +274,10 @@ def main():
         t0 = time.perf_counter()
         ctx_m = P.Context(wl.problem_arrays(), precision=P.rtbte.MIXED, rtol=args.rtol, atol_el=1e-9,
                           atol_ph=1e-12, group_rows_el=args.group_rows_el, group_rows_ph=args.group_rows_ph,
-                          item_channels=args.item_channels)
+                          item_channels=args.item_channels, tiled=args.tiled)
         torch.cuda.synchronize()
         create_m = time.perf_counter() - t0
-        leg_m = timed_steps(ctx_m, wl, args, C, "mixed", start=leg["start"])
+        leg_m = timed_steps(ctx_m, wl, args, CS, "mixed", start=leg["start"])
         km = leg_m["kernel"]
         tm = measured_traffic(args.workload if args.L is None else f"{args.workload}_L{args.L}", "mixed")
         rec["mixed"] = {
@@ -253,7 +297,7 @@ def main():
     o = None
     if not args.no_cpu_baseline:
         log("[bench] oracle baseline on host cores ...")
-        o, cb = cpu_baseline(wl, args.cpu_seconds)
+        o, cb = cpu_baseline(wl, args.cpu_seconds, CS)
         rec["cpu_baseline"] = cb
         # parity of the GPU right-hand side at the final state, every row
         yf = leg["y"].cpu().numpy()
@@ -268,18 +312,99 @@ def main():
         }
     if ctx_m is not None and not args.no_errors:
         rec["mixed"].update(mixed_errors(P, torch, np, ctx, ctx_m, wl, o, args))
+    if not args.no_horizon:
+        hz = horizon_leg(P, torch, np, wl, args, ctx, ctx_m)
+        rec["horizon"] = hz
+        rec["sim_ps_per_s"] = hz["fp64"]["sim_ps_per_s"]
+        rec["sim_ps_per_s_note"] = (f"FP64 adaptive ERK (printed PID form) from the initial state to "
+                                    f"{args.horizon_fs:g} fs, end-time error vs an FP64 run at rtol "
+                                    f"{args.ref_rtol:g}: carriers {hz['fp64']['err_carriers']:.2e}, phonons "
+                                    f"{hz['fp64']['err_phonons']:.2e} (horizon)")
+    del ctx, ctx_m, o, leg
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     if not args.no_batched:
-        del ctx, ctx_m, o, leg
-        torch.cuda.synchronize()
-        torch.cuda.empty_cache()
         rec["batched"] = batched_leg(P, torch, np, args)
-    if args.si3d:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+    if not args.no_si3d:
         rec["si3d"] = si3d_leg(P, torch, np, args)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     if not args.no_toy:
         rec["toy"] = toy_leg(P, torch, np, with_oracle=not args.no_cpu_baseline)
     print(json.dumps(rec), flush=True)
+
+
+def horizon_leg(P, torch, np, wl, args, ctx64, ctx_m):
+    """Simulated ps per wall second at a stated error (Methods, choice of
+    tolerances and reference solutions): each configuration advances the
+    workload from its initial state to the horizon with the adaptive ERK (the
+    benchmark's rtol; h = 0 asks for the starting-step estimate), and its end
+    state is compared with an FP64 reference run at a tighter tolerance,
+    ||x - x_ref|| / ||x_ref|| over the carriers and over the phonons.
+    Configurations: FP64 and mixed precision, each with the printed PID form
+    (the default) and with ARKODE's (+k2 on eps_{k-1})."""
+    dev = torch.device("cuda:0")
+    T = args.horizon_fs
+    probs = wl.problem_arrays()
+    y0 = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
+
+    def run(ctx):
+        y = y0.clone()
+        t = torch.zeros(1, dtype=torch.float64, device=dev)
+        h = torch.zeros(1, dtype=torch.float64, device=dev)
+        ctx.reset()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ctx.step_adaptive(y, t, h, T)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        st = ctx.stats()
+        assert t.item() == T
+        return y.cpu().numpy(), wall, st
+
+    t0 = time.perf_counter()
+    ref_tol = dict(rtol=args.ref_rtol, atol_el=1e-12, atol_ph=1e-15)
+    ctx_r = P.Context(probs, **ref_tol)
+    yref, wref, sref = run(ctx_r)
+    del ctx_r
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    ne = wl.n_el
+    nrm = np.linalg.norm
+    res = {"horizon_fs": T, "rtol": args.rtol, "atol_el": 1e-9, "atol_ph": 1e-12,
+           "reference": dict(ref_tol, accepted=sref["n_accept"], rejected=sref["n_reject"], wall_s=wref,
+                             note="FP64 adaptive ERK, printed PID form")}
+    log(f"[bench] horizon reference (rtol {args.ref_rtol:g}): {T:g} fs in {wref:.2f} s, "
+        f"{sref['n_accept']} steps")
+    tol = dict(rtol=args.rtol, atol_el=1e-9, atol_ph=1e-12)
+    cases = [("fp64", ctx64, None), ("fp64_arkode_pid", None, dict(precision=P.rtbte.FP64, pid_alt_sign=1))]
+    if ctx_m is not None:
+        cases += [("mixed", ctx_m, None), ("mixed_arkode_pid", None, dict(precision=P.rtbte.MIXED, pid_alt_sign=1))]
+    for name, ctx, kw in cases:
+        own = ctx is None
+        if own:
+            ctx = P.Context(probs, **tol, **kw)
+            yw = y0.clone()
+            tw = torch.zeros(1, dtype=torch.float64, device=dev)
+            hw_ = torch.zeros(1, dtype=torch.float64, device=dev)
+            ctx.step_adaptive(yw, tw, hw_, 20.0)     # warm-up (first launches)
+            del yw
+        y, wall, st = run(ctx)
+        res[name] = {"wall_s": wall, "sim_ps_per_s": T * 1e-3 / wall, "accepted": st["n_accept"],
+                     "rejected": st["n_reject"],
+                     "err_carriers": float(nrm(y[:ne] - yref[:ne]) / nrm(yref[:ne])),
+                     "err_phonons": float(nrm(y[ne:] - yref[ne:]) / nrm(yref[ne:]))}
+        log(f"[bench] horizon {name}: {T:g} fs in {wall:.2f} s ({st['n_accept']} accepted, {st['n_reject']} "
+            f"rejected), errors {res[name]['err_carriers']:.2e} / {res[name]['err_phonons']:.2e}")
+        if own:
+            del ctx
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+    res["speedup_mixed_vs_fp64"] = res["fp64"]["wall_s"] / res["mixed"]["wall_s"] if "mixed" in res else None
+    res["total_s"] = time.perf_counter() - t0
+    return res
 
 
 def toy_leg(P, torch, np, with_oracle=True):
@@ -443,7 +568,47 @@ def si3d_leg(P, torch, np, args):
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     res.pop("_mis_fp64_y")
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = si3d_cpu_baseline(np, wl, args.si_sample_rows)
     return res
+
+
+def si3d_cpu_baseline(np, wl, n_rows, seed=5):
+    """The FP64 oracle on a sample of the silicon-like workload's rows: the
+    entries that feed `n_rows` rows drawn at random (electron and phonon rows
+    in proportion), one right-hand side of that sub-problem (median of three),
+    as channels per second over the channels it sums."""
+    from __graft_entry__ import _ensure_built
+    _ensure_built(need_oracle=True)
+    import oracle
+    prob = wl.problem_arrays()
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(wl.n_y, size=min(n_rows, wl.n_y), replace=False)
+    re_ = rows[rows < wl.n_el]
+    rp = rows[rows >= wl.n_el] - wl.n_el
+    me = np.zeros(wl.n_el, bool)
+    me[re_] = True
+    mp = np.zeros(wl.n_ph, bool)
+    mp[rp] = True
+    ke = me[prob["eph_row"]] | mp[prob["eph_phonon"]]
+    kp = mp[prob["pp_row"]]
+    sub = dict(prob)
+    for k in ("eph_row", "eph_partner", "eph_phonon", "eph_g2"):
+        sub[k] = np.ascontiguousarray(prob[k][ke])
+    for k in ("pp_row", "pp_a", "pp_b", "pp_v2"):
+        sub[k] = np.ascontiguousarray(prob[k][kp])
+    o = oracle.Oracle(sub)
+    ch = sum(o.counts())
+    o.rhs(wl.y0)                                  # first touch of the lists
+    reps = 0
+    t0 = time.perf_counter()
+    while reps < 3 or time.perf_counter() - t0 < 3.0:
+        o.rhs(wl.y0)
+        reps += 1
+    el = (time.perf_counter() - t0) / reps
+    return {"value": ch / el, "unit": "channels/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{len(rows)} random rows of {wl.n_y} ({len(re_)} electron, {len(rp)} phonon): the "
+                      f"{ch} channels that feed them, {reps} right-hand sides of {el:.3f} s each"}
 
 
 def batched_leg(P, torch, np, args):
@@ -451,9 +616,13 @@ def batched_leg(P, torch, np, args):
     24..72, initial electron temperatures uniform in 500..3000 K, phonons at
     300 K), each with its own adaptive step (rtol as above), advanced from
     their initial states to the same end time: all in one mixed-precision
-    context whose step sequence is replayed through HIP graphs, against the
-    same instances run one by one in plain FP64 contexts.  Simulated time is
-    counted per instance (instance-ps per wall second)."""
+    context (launch shape chosen by the autotuner at create, step sequence
+    replayed through HIP graphs), against the same instances run one by one
+    in plain FP64 contexts.  Simulated time is counted per instance
+    (instance-ps per wall second).  Accuracy, untimed: both end states
+    against an FP64 batch run at the reference tolerance, per instance; and
+    the precision error alone, batched mixed against batched FP64 on the same
+    fixed RK4 steps to 1 ps, per instance."""
     import synth
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -461,22 +630,27 @@ def batched_leg(P, torch, np, args):
     gen_s = time.perf_counter() - t0
     n = len(ws)
     y0 = np.concatenate([w.y0 for w in ws])
+    y0_d = torch.tensor(y0, dtype=torch.float64, device=dev)
     probs = [w.problem_arrays() for w in ws]
     tol = dict(rtol=args.rtol, atol_el=1e-9, atol_ph=1e-12)
     t0 = time.perf_counter()
-    ctx = P.Context(probs, precision=P.rtbte.MIXED, use_graph=1, **tol)
+    ctx = P.Context(probs, precision=P.rtbte.MIXED, use_graph=1, tune=0 if args.no_tune else 1,
+                    tiled=args.tiled, **tol)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     counts = ctx.counts()
     C = sum(counts)
-    log(f"[bench] batched: {n} instances, {C} channels ({counts}), generated {gen_s:.1f} s, "
-        f"created {create_s:.1f} s, shape {ctx.tuning()}")
-    y = torch.tensor(y0, dtype=torch.float64, device=dev)
+    CS = sum(ctx.stored_counts())
+    src, tuned_ms = ctx.tuning_source()
+    shape = ctx.tuning()
+    log(f"[bench] batched: {n} instances, {C} channels ({counts}; {CS} stored), generated {gen_s:.1f} s, "
+        f"created {create_s:.1f} s, shape {shape} (source {src}, {tuned_ms:.3f} ms per RHS)")
+    y = y0_d.clone()
     t = torch.zeros(n, dtype=torch.float64, device=dev)
     h = torch.zeros(n, dtype=torch.float64, device=dev)
     ctx.step_adaptive(y, t, h, 2.0)          # warm-up (first launches, graph capture)
     torch.cuda.synchronize()
-    y.copy_(torch.tensor(y0, dtype=torch.float64, device=dev))
+    y.copy_(y0_d)
     t.zero_()
     h.zero_()
     ctx.reset()
@@ -497,14 +671,38 @@ def batched_leg(P, torch, np, args):
     kms = k_ms / max(k_n, 1)
     achieved = k_bytes / max(k_n, 1) / (kms * 1e-3) / 1e9
     layouts = [ctx.layout(i) for i in range(n)]
+    # precision alone: fixed RK4 steps, the same in both precisions
+    n_rk4 = int(round(args.batch_rk4_fs / args.batch_rk4_h))
+    y.copy_(y0_d)
+    t.zero_()
+    ctx.step_rk4(y, t, args.batch_rk4_h, n_rk4)
+    torch.cuda.synchronize()
+    ym_rk4 = y.cpu().numpy()
     del ctx, y, out
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     log(f"[bench] batched mixed: {n} x {args.batch_t_end:g} fs in {wall_m * 1e3:.1f} ms ({steps_m} attempts)")
+    # FP64 batch: the reference run (tight tolerance) and the same RK4 steps
+    ref_tol = dict(rtol=args.ref_rtol, atol_el=1e-12, atol_ph=1e-15)
+    c64 = P.Context(probs, use_graph=1, **ref_tol)
+    y = y0_d.clone()
+    t = torch.zeros(n, dtype=torch.float64, device=dev)
+    h = torch.zeros(n, dtype=torch.float64, device=dev)
+    c64.step_adaptive(y, t, h, args.batch_t_end)
+    torch.cuda.synchronize()
+    yref = y.cpu().numpy()
+    y.copy_(y0_d)
+    t.zero_()
+    c64.step_rk4(y, t, args.batch_rk4_h, n_rk4)
+    torch.cuda.synchronize()
+    y64_rk4 = y.cpu().numpy()
+    del c64, y
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     # plain FP64, one instance at a time
     wall_f = 0.0
     steps_f = 0
-    diff = 0.0
+    err_m, err_f, err_rk4 = [], [], []
     for i, w in enumerate(ws):
         c = P.Context(w.problem_arrays(), **tol)
         yi = torch.tensor(w.y0, dtype=torch.float64, device=dev)
@@ -525,22 +723,39 @@ def batched_leg(P, torch, np, args):
         st = c.stats()
         steps_f += st["n_accept"] + st["n_reject"]
         off, ne, nph = layouts[i]
-        diff = max(diff, float(np.max(np.abs(ym[off:off + ne + nph] - yi.cpu().numpy()))))
+        sl = slice(off, off + ne + nph)
+        err_m.append(float(np.max(np.abs(ym[sl] - yref[sl]))))
+        err_f.append(float(np.max(np.abs(yi.cpu().numpy() - yref[sl]))))
+        err_rk4.append(float(np.max(np.abs(ym_rk4[sl] - y64_rk4[sl]))))
         del c
     log(f"[bench] plain FP64: {n} x {args.batch_t_end:g} fs in {wall_f * 1e3:.1f} ms ({steps_f} attempts); "
-        f"max |y_batched_mixed - y_plain_fp64| = {diff:.2e}")
+        f"max |y - y_ref| at {args.batch_t_end:g} fs: batched mixed {max(err_m):.2e}, plain FP64 {max(err_f):.2e}; "
+        f"mixed vs FP64 after {args.batch_rk4_fs:g} fs of RK4: {max(err_rk4):.2e}")
     inst_ps = n * args.batch_t_end * 1e-3
     return {
         "workload": f"{n} graphene-like instances, sides uniform in 24..72, T_el uniform in 500..3000 K, "
                     f"adaptive Zonneveld ERK rtol {args.rtol:g}, each from its initial state to "
                     f"{args.batch_t_end:g} fs",
-        "channels": C, "channels_eph": counts[0], "channels_phe": counts[1], "channels_phph": counts[2],
+        "channels": C, "stored_channels": CS, "channels_eph": counts[0], "channels_phe": counts[1],
+        "channels_phph": counts[2],
+        "launch_shape": {"rows_per_group_el": shape[0], "rows_per_group_ph": shape[1],
+                         "channels_per_item": shape[2],
+                         "tuning_source": {0: "default", 1: "tuned at create", 2: "tune cache"}[src],
+                         "tuned_rhs_ms": tuned_ms},
         "mixed_graph_wall_s": wall_m, "plain_fp64_wall_s": wall_f,
         "sim_instance_ps_per_s_mixed_batched": inst_ps / wall_m,
         "sim_instance_ps_per_s_plain_fp64": inst_ps / wall_f,
         "speedup_sim_ps_per_s": wall_f / wall_m,
         "attempts_mixed": steps_m, "attempts_plain_fp64": steps_f,
-        "max_abs_pop_diff_at_t_end": diff,
+        "reference": dict(ref_tol, note="the batch in FP64, adaptive ERK, to the same end time"),
+        "max_abs_err_vs_reference_mixed_batched": max(err_m),
+        "max_abs_err_vs_reference_plain_fp64": max(err_f),
+        "err_vs_reference_per_instance_mixed_batched": err_m,
+        "err_vs_reference_per_instance_plain_fp64": err_f,
+        "precision_check": {"what": f"batched mixed vs batched FP64, the same fixed RK4 steps of "
+                                    f"{args.batch_rk4_h:g} fs to {args.batch_rk4_fs:g} fs: max |dy| per instance",
+                            "max_abs": max(err_rk4), "bar": 1e-6, "per_instance": err_rk4,
+                            "all_within_bar": bool(max(err_rk4) <= 1e-6)},
         "roofline_batched_mixed_kernel": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                                           "avg_launch_ms": kms, "algorithmic_bytes_per_launch": k_bytes / max(k_n, 1)},

@@ -204,6 +204,19 @@ typedef struct {
                                with twice the weight (the emission factor and delta are
                                symmetric in a and b): a quarter fewer ph-ph channels, the
                                same sums to rounding order.  0: store every channel.       */
+  int32_t tiled;            /* 0 (default): one wavefront per work item, partners gathered
+                               from global memory.  1: with packed channels (FP64 packed,
+                               mixed RTBTE_W_PACK8) the collision kernels run tiled: the
+                               channels of each group are cut where their sorted partner
+                               crosses a key block (1024 states FP64, 2048 mixed), and a
+                               launch block of four consecutive groups stages the
+                               populations of the key block and of the other partners'
+                               window in LDS, so most partner reads leave global memory
+                               (half the vector-memory instructions); item_channels then
+                               sets the channels a block takes per wavefront.  On the
+                               graphene-like workload it is slower (its 64 KB of LDS per
+                               block allow two blocks per compute unit).  Both give the
+                               same results to rounding order.                              */
 } rtbte_options;
 
 enum { RTBTE_F64_AUTO = 0, RTBTE_F64_PACKED = 1, RTBTE_F64_PLAIN = 2 };

@@ -223,6 +223,14 @@ struct rtbte_ctx {
   double tuned_ms = 0.0;
   // this device's address of the static scratch (rtbte_rhs_noalloc)
   void* scratch_dev = nullptr;
+  // tiled launch (packed layouts): blocks, their order, tiles, key-block bounds
+  bool tiled = false;
+  TileBlock* tblocks = nullptr;
+  int32_t* border = nullptr;
+  Tile* tiles = nullptr;
+  int64_t* bnd = nullptr;
+  int64_t n_blocks = 0;
+  double tile_in_window = 0.0;    // fraction of channels whose other partner is staged
 };
 
 static int fail(rtbte_ctx* c, int code, const char* fmt, ...) {
@@ -283,6 +291,7 @@ void rtbte_default_options(rtbte_options* o) {
   o->small_nef = 5;
   o->eta_fail_repeat = 0.3;
   o->pp_fold = 1;
+  o->tiled = 0;
 }
 
 const char* rtbte_last_error(const rtbte_ctx* ctx) {
@@ -413,7 +422,7 @@ void free_ctx(rtbte_ctx* c) {
                 c->st_fast, c->st_slow, c->mra, c->mis_keep, c->energy_d,
                 c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
                 c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
-                c->partial, c->tvec, c->summary_d};
+                c->partial, c->tvec, c->summary_d, c->tblocks, c->border, c->tiles, c->bnd};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   for (auto& g : c->graphs) {
@@ -474,6 +483,199 @@ hipError_t build_items(rtbte_ctx* c, int64_t ich) {
   }
   c->graphs.clear();
   return e;
+}
+
+// Tiled launch (packed layouts): the channels of every group segment cut at
+// key-block bounds, sets of kTileWaves consecutive segments of one kind of
+// one instance, the other-partner window of each (set, key block), and
+// blocks that run a set through a range of key blocks of about
+// kTileWaves * ich channels, each wavefront writing one item.  Items are
+// stored group by group (the row kernel sums a group's items in order).
+hipError_t build_tiles(rtbte_ctx* c, int64_t ich) {
+  const bool mixed = c->mixed;
+  const uint64_t* words = mixed ? reinterpret_cast<const uint64_t*>(c->mix_idx) : c->pk;
+  if (!words) return hipErrorInvalidValue;
+  const int64_t KL = mixed ? kTileKey32 : kTileKey64;
+  const int64_t OC = mixed ? kTileOther32 : kTileOther64;
+  if (ich <= 0) ich = auto_item_channels(c->n_ch);
+  c->item_channels = ich;
+  void* old[] = {c->items, c->order, c->item_ptr, c->partial_items, c->tblocks, c->border, c->tiles, c->bnd};
+  for (void* p : old)
+    if (p) (void)hipFree(p);
+  c->items = nullptr; c->order = nullptr; c->item_ptr = nullptr; c->partial_items = nullptr;
+  c->tblocks = nullptr; c->border = nullptr; c->tiles = nullptr; c->bnd = nullptr;
+  c->n_items = c->n_blocks = 0;
+  c->tiled = false;
+  // 1. segments and the offsets of their bounds
+  struct SegH { int32_t group, kind, inst, n_kb; int64_t lo, hi, off; };
+  std::vector<SegH> sh;
+  std::vector<SegRange> sr;
+  int64_t nbnd = 0;
+  for (int64_t gi = 0; gi < c->n_groups; ++gi) {
+    const Group& g = c->groups_h[gi];
+    const InstInfo& in = c->info[g.inst];
+    const int32_t n_kb = (int32_t)(((int64_t)in.n_el + in.n_ph + KL - 1) / KL);
+    auto add = [&](int64_t lo, int64_t hi, int32_t kind) {
+      sh.push_back({(int32_t)gi, kind, g.inst, n_kb, lo, hi, nbnd});
+      sr.push_back({lo, hi, nbnd, kind, n_kb});
+      nbnd += n_kb + 1;
+    };
+    if (!g.phonon) add(g.start, g.end, 0);
+    else {
+      add(g.start, g.split, 1);
+      add(g.split, g.end, 2);
+    }
+  }
+  // 2. key-block bounds (device), copied back
+  SegRange* sr_d = nullptr;
+  hipError_t e = upload(&sr_d, sr.data(), sr.size());
+  if (e == hipSuccess) c->bnd = dalloc<int64_t>((size_t)std::max<int64_t>(nbnd, 1), &e);
+  if (e == hipSuccess) e = launch_key_bounds(words, c->pack_p, sr_d, (int64_t)sr.size(), KL, c->bnd, 0);
+  std::vector<int64_t> bnd((size_t)nbnd);
+  if (e == hipSuccess && nbnd) e = hipMemcpy(bnd.data(), c->bnd, (size_t)nbnd * sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (sr_d) (void)hipFree(sr_d);
+  if (e != hipSuccess) return e;
+  // 3. sets: consecutive segments of one kind of one instance
+  std::vector<std::vector<int32_t>> sets;   // segment indices
+  for (int kind = 0; kind < 3; ++kind) {
+    std::vector<int32_t> cur;
+    int32_t inst = -1;
+    for (int32_t si = 0; si < (int32_t)sh.size(); ++si) {
+      if (sh[si].kind != kind) continue;
+      if (sh[si].inst != inst || (int)cur.size() == kTileWaves) {
+        if (!cur.empty()) sets.push_back(cur);
+        cur.clear();
+        inst = sh[si].inst;
+      }
+      cur.push_back(si);
+    }
+    if (!cur.empty()) sets.push_back(cur);
+  }
+  // 4. the other-partner span of every non-empty (set, key block)
+  std::vector<SpanJob> jobs;
+  std::vector<int64_t> tile_of;     // per set: first tile index; tiles are [set][j]
+  std::vector<int64_t> job_tile;    // tile index of each job
+  int64_t ntiles = 0;
+  for (const auto& st : sets) {
+    tile_of.push_back(ntiles);
+    const int32_t n_kb = sh[st[0]].n_kb;
+    for (int32_t j = 0; j < n_kb; ++j) {
+      int64_t tot = 0;
+      SpanJob jb{};
+      for (int w = 0; w < kTileWaves; ++w) jb.bndo[w] = -1;
+      for (size_t w = 0; w < st.size(); ++w) {
+        const SegH& s = sh[st[w]];
+        tot += bnd[s.off + j + 1] - bnd[s.off + j];
+        jb.bndo[w] = s.off;
+      }
+      if (tot > 0) {
+        jb.j = j;
+        jb.kind = sh[st[0]].kind;
+        jobs.push_back(jb);
+        job_tile.push_back(ntiles + j);
+      }
+    }
+    ntiles += n_kb;
+  }
+  std::vector<Tile> tiles((size_t)std::max<int64_t>(ntiles, 1), Tile{kTileEmpty, 0u});
+  if (!jobs.empty()) {
+    SpanJob* jobs_d = nullptr;
+    uint32_t* span_d = nullptr;
+    e = upload(&jobs_d, jobs.data(), jobs.size());
+    if (e == hipSuccess) span_d = dalloc<uint32_t>(2 * jobs.size(), &e);
+    if (e == hipSuccess) e = launch_tile_span(words, c->pack_p, jobs_d, (int64_t)jobs.size(), c->bnd, span_d, 0);
+    std::vector<uint32_t> span(2 * jobs.size());
+    if (e == hipSuccess) e = hipMemcpy(span.data(), span_d, span.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (jobs_d) (void)hipFree(jobs_d);
+    if (span_d) (void)hipFree(span_d);
+    if (e != hipSuccess) return e;
+    for (size_t k = 0; k < jobs.size(); ++k) {
+      const uint32_t mn = span[2 * k], mx = span[2 * k + 1];
+      tiles[(size_t)job_tile[k]] = Tile{mn, (uint32_t)std::min<int64_t>((int64_t)mx - mn + 1, OC)};
+    }
+  }
+  // 5. blocks: each set through ranges of key blocks of about kTileWaves * ich channels
+  struct ItemH { int32_t group; int64_t lo, hi; int32_t block, wave; };
+  std::vector<ItemH> ih;
+  std::vector<TileBlock> blocks;
+  std::vector<int64_t> work;        // the longest wavefront range of each block
+  const int64_t target = (int64_t)kTileWaves * ich;
+  for (size_t si = 0; si < sets.size(); ++si) {
+    const auto& st = sets[si];
+    const int32_t n_kb = sh[st[0]].n_kb;
+    int32_t j0 = 0;
+    while (j0 < n_kb) {
+      int64_t tot = 0;
+      int32_t j1 = j0;
+      while (j1 < n_kb && (tot == 0 || tot < target)) {
+        for (int32_t s : st) tot += bnd[sh[s].off + j1 + 1] - bnd[sh[s].off + j1];
+        ++j1;
+      }
+      if (tot > 0) {
+        TileBlock b{};
+        for (int w = 0; w < kTileWaves; ++w) { b.bndo[w] = -1; b.item[w] = -1; }
+        b.inst = sh[st[0]].inst;
+        b.kind = sh[st[0]].kind;
+        b.j0 = j0;
+        b.j1 = j1;
+        b.tile0 = (int32_t)(tile_of[si] + j0);
+        int64_t mx = 0;
+        for (size_t w = 0; w < st.size(); ++w) {
+          const SegH& s = sh[st[w]];
+          const int64_t lo = bnd[s.off + j0], hi = bnd[s.off + j1];
+          b.bndo[w] = s.off;
+          if (hi > lo) ih.push_back({s.group, lo, hi, (int32_t)blocks.size(), (int32_t)w});
+          mx = std::max(mx, hi - lo);
+        }
+        blocks.push_back(b);
+        work.push_back(mx);
+      }
+      j0 = j1;
+    }
+  }
+  // 6. items group by group (stable), and each block's wave items
+  std::vector<int32_t> iord(ih.size());
+  for (size_t k = 0; k < ih.size(); ++k) iord[k] = (int32_t)k;
+  std::stable_sort(iord.begin(), iord.end(), [&](int32_t x, int32_t y) { return ih[x].group < ih[y].group; });
+  std::vector<Item> items(ih.size());
+  std::vector<int64_t> iptr((size_t)c->n_groups + 1, 0);
+  for (size_t k = 0; k < iord.size(); ++k) {
+    const ItemH& x = ih[iord[k]];
+    items[k] = Item{x.lo, x.hi, x.group, 0};
+    blocks[(size_t)x.block].item[x.wave] = (int32_t)k;
+    iptr[(size_t)x.group + 1]++;
+  }
+  for (int64_t gi = 0; gi < c->n_groups; ++gi) iptr[gi + 1] += iptr[gi];
+  c->n_items = (int64_t)items.size();
+  c->n_blocks = (int64_t)blocks.size();
+  std::vector<int32_t> order((size_t)c->n_items), border((size_t)c->n_blocks);
+  for (int64_t i = 0; i < c->n_items; ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return items[x].hi - items[x].lo > items[y].hi - items[y].lo;
+  });
+  for (int64_t i = 0; i < c->n_blocks; ++i) border[i] = (int32_t)i;
+  std::stable_sort(border.begin(), border.end(), [&](int32_t x, int32_t y) { return work[x] > work[y]; });
+  e = upload(&c->items, items.data(), items.size());
+  if (e == hipSuccess) e = upload(&c->order, order.data(), order.size());
+  if (e == hipSuccess) e = upload(&c->item_ptr, iptr.data(), iptr.size());
+  if (e == hipSuccess)
+    c->partial_items = dalloc<double>((size_t)std::max<int64_t>(c->n_items, 1) * kMaxGroupRows, &e);
+  if (e == hipSuccess) e = upload(&c->tblocks, blocks.data(), blocks.size());
+  if (e == hipSuccess) e = upload(&c->border, border.data(), border.size());
+  if (e == hipSuccess) e = upload(&c->tiles, tiles.data(), tiles.size());
+  if (e != hipSuccess) return e;
+  c->tiled = true;
+  for (auto& g : c->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.g);
+  }
+  c->graphs.clear();
+  return hipSuccess;
+}
+
+// Work items of the context's launch mode: tiled when it was built tiled.
+hipError_t rebuild_items(rtbte_ctx* c, int64_t ich) {
+  return c->tiled ? build_tiles(c, ich) : build_items(c, ich);
 }
 
 }  // namespace
@@ -870,6 +1072,9 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
       c->ch = nullptr;
     }
   }
+  // tiled launch blocks over the packed words
+  if (e == hipSuccess && o.tiled && (c->mixed ? c->wfmt == RTBTE_W_PACK8 : c->pk != nullptr))
+    e = build_tiles(c, o.item_channels);
   if (e == hipSuccess && n_inst > 1) {
     std::vector<int32_t> ri((size_t)c->ny);
     for (int i = 0; i < n_inst; ++i)
@@ -1078,6 +1283,14 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
   a.z = z;
   a.partial = partial;
   a.st = st;
+  a.ny = c->ny;
+  if (c->tiled && !c->mixed) {
+    a.blocks = c->tblocks;
+    a.border = c->border;
+    a.n_blocks = c->n_blocks;
+    a.tiles = c->tiles;
+    a.bnd = c->bnd;
+  }
   MixArgs m{};
   if (use_mixed) {
     m.idx = c->mix_idx;
@@ -1096,6 +1309,14 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
     m.info = c->info_d;
     m.partial = partial;
     m.st = st;
+    m.ny = c->ny;
+    if (c->tiled) {
+      m.blocks = c->tblocks;
+      m.border = c->border;
+      m.n_blocks = c->n_blocks;
+      m.tiles = c->tiles;
+      m.bnd = c->bnd;
+    }
   }
   auto launch = [&]() {
     if (!use_mixed) return launch_items(a, c->slots, s);
@@ -1964,7 +2185,7 @@ int tune_create(const rtbte_problem* P, int n, rtbte_options o, rtbte_ctx** out)
     for (int64_t ic : cand) {
       if (std::find(tried.begin(), tried.end(), ic) != tried.end()) continue;
       tried.push_back(ic);
-      if (ic != c->item_channels && build_items(c, ic) != hipSuccess) {
+      if (ic != c->item_channels && rebuild_items(c, ic) != hipSuccess) {
         rc = fail(nullptr, RTBTE_E_NOMEM, "tuning: work items");
         break;
       }
@@ -1981,7 +2202,7 @@ int tune_create(const rtbte_problem* P, int n, rtbte_options o, rtbte_ctx** out)
       break;
     }
     if (c_best < best_ms) {
-      if (c->item_channels != c_ich && build_items(c, c_ich) != hipSuccess) {
+      if (c->item_channels != c_ich && rebuild_items(c, c_ich) != hipSuccess) {
         rtbte_destroy(c);
         rc = fail(nullptr, RTBTE_E_NOMEM, "tuning: work items");
         break;

@@ -76,6 +76,40 @@ struct Item {
   int32_t pad;
 };
 
+// Tiled launch (packed channel formats).  A segment is the channels of one
+// kind in one group (electron groups: e-ph; phonon groups: ph-e, then ph-ph),
+// stored merged by one partner, the key (e-ph: the phonon; ph-e: the
+// initial electron; ph-ph: the first phonon).  Its items are cut where the
+// key crosses a multiple of the key block length, and a launch block holds
+// up to kTileWaves such items, from consecutive groups of one kind of one
+// instance with the same key block.  The block stages in LDS the
+// populations of its key block and of a window of the other partner's
+// positions (the span its channels touch, up to the window capacity), so
+// most gathers of a channel read LDS; an other partner outside the window
+// is gathered from global memory.
+// A block runs through a range of key blocks; its waves keep their row sums
+// across the range and write one item each at the end.
+constexpr int kTileWaves = 4;
+constexpr int kTileKey64 = 1024, kTileOther64 = 2944;    // FP64 staging capacities (states)
+constexpr int kTileKey32 = 2048, kTileOther32 = 4096;    // mixed (4-byte population codes)
+constexpr uint32_t kTileEmpty = 0xffffffffu;             // Tile.lo of a key block with no channels
+struct TileBlock {
+  int64_t bndo[kTileWaves];  // offset of each wave's segment in the key-block bounds (-1: none)
+  int32_t item[kTileWaves];  // item (row-sum slot) of each wave (-1: none)
+  int32_t inst;
+  int32_t kind;              // 0 e-ph, 1 ph-e, 2 ph-ph
+  int32_t j0, j1;            // key blocks [j0, j1)
+  int32_t tile0;             // tile of key block j0 (the tiles of j0..j1-1 follow it)
+  int32_t pad;
+};
+static_assert(sizeof(TileBlock) == 72, "tile block record");
+// The staged window of the other partner in one key block of one set of
+// groups: positions [lo, lo + len) relative to the instance (lo = kTileEmpty:
+// no channels in this key block).
+struct Tile {
+  uint32_t lo, len;
+};
+
 // Arguments of the collision kernel (per-item row sums).
 // FP64 channels, packed (12 bytes): an 8-byte word per channel, low half
 // pos0 (bits 0..P-1) | tag (P..P+3) | weight field bits 32..59-P (P+4..31),
@@ -98,6 +132,12 @@ struct RowArgs {
   double* partial;          // [n_items][kMaxGroupRows] row sums of each item
   const InstState* st;      // stage mode: items of finished instances are skipped (else nullptr)
   int32_t deriv;            // 1: each term is -W dF/dx_row (the rows then hold linearized rates)
+  const TileBlock* blocks;  // tiled launch (packed layout): [n_blocks], else nullptr
+  const int32_t* border;    // [n_blocks] processing order of the blocks
+  int64_t n_blocks;
+  const Tile* tiles;
+  const int64_t* bnd;       // key-block bounds of every segment
+  int64_t ny;               // length of z
 };
 
 // Arguments of the row kernel: sums of the items of each row's group, the
@@ -157,8 +197,34 @@ struct MixArgs {
   const InstInfo* info;     // RTBTE_W_PACK8: instance offsets
   double* partial;
   const InstState* st;
+  const TileBlock* blocks;  // tiled launch (RTBTE_W_PACK8), else nullptr
+  const int32_t* border;
+  int64_t n_blocks;
+  const Tile* tiles;
+  const int64_t* bnd;
+  int64_t ny;
 };
 hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s);
+// Tiled launches (create time), from the packed 8-byte words (FP64 or
+// mixed; positions in the low P bits of each half): for each segment, the
+// first channel whose key reaches j * key_len, j = 0..n_kb, at
+// bnd[off + j]; and for each (set of up to kTileWaves segments, key block),
+// the smallest and largest other-partner position of its channels.
+struct SegRange {
+  int64_t lo, hi;     // channels [lo, hi)
+  int64_t off;        // its bounds start at bnd[off]
+  int32_t kind;       // 0 e-ph (key: second partner), 1 ph-e, 2 ph-ph (key: first partner)
+  int32_t n_kb;       // key blocks
+};
+hipError_t launch_key_bounds(const uint64_t* words, int pack_p, const SegRange* segs, int64_t n_segs,
+                             int64_t key_len, int64_t* bnd, hipStream_t s);
+struct SpanJob {
+  int64_t bndo[kTileWaves];   // bounds of each segment of the set (-1: none)
+  int32_t j;                  // key block
+  int32_t kind;
+};
+hipError_t launch_tile_span(const uint64_t* words, int pack_p, const SpanJob* jobs, int64_t n_jobs,
+                            const int64_t* bnd, uint32_t* span, hipStream_t s);
 // pop[i] from z[i] (each factor formed in FP64, then rounded to FP32)
 hipError_t launch_popf(float* pop, const double* z, const int32_t* row_group, const Group* groups,
                        int64_t n, hipStream_t s);

@@ -296,11 +296,19 @@ hipError_t launch_items_fmt(const RowArgs& a, int slots, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <bool DERIV>
+hipError_t launch_tiled_fmt(const RowArgs& a, int slots, hipStream_t s);
+
 hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s) {
   if (a.n_items == 0) return hipSuccess;
   if (a.pk) {
     if (!a.pkw || !a.info || a.pack_p < 1 || a.pack_p > 19 || a.pack_m != std::min(80 - 2 * a.pack_p, 52))
       return hipErrorInvalidValue;
+    if (a.blocks) {
+      if (a.n_blocks == 0) return hipSuccess;
+      if (!a.border || !a.tiles || !a.bnd) return hipErrorInvalidValue;
+      return a.deriv ? launch_tiled_fmt<true>(a, slots, s) : launch_tiled_fmt<false>(a, slots, s);
+    }
     return a.deriv ? launch_items_fmt<true, true>(a, slots, s) : launch_items_fmt<true, false>(a, slots, s);
   }
   return a.deriv ? launch_items_fmt<false, true>(a, slots, s) : launch_items_fmt<false, false>(a, slots, s);
@@ -630,11 +638,18 @@ hipError_t launch_items_mixed_fmt(const MixArgs& a, int slots, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_tiled_mixed(const MixArgs& a, int slots, hipStream_t s);
+
 hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s) {
   if (a.n_items == 0) return hipSuccess;
   if (a.wfmt == RTBTE_W_PACK8) {
     if (!a.info || a.pack_p < 1 || a.pack_p > 20 || a.pack_m != std::min(53 - 2 * a.pack_p, 23))
       return hipErrorInvalidValue;
+    if (a.blocks) {
+      if (a.n_blocks == 0) return hipSuccess;
+      if (!a.border || !a.tiles || !a.bnd) return hipErrorInvalidValue;
+      return launch_tiled_mixed(a, slots, s);
+    }
     return launch_items_mixed_fmt<true>(a, slots, s);
   }
   return launch_items_mixed_fmt<false>(a, slots, s);
@@ -659,6 +674,393 @@ hipError_t launch_popf(float* pop, const double* z, const int32_t* row_group, co
                        int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_popf, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pop, z, row_group, groups, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- tiled launch
+// (packed layouts).  A block of kTileWaves wavefronts runs one set of
+// consecutive groups of one kind through a range of key blocks.  For each
+// key block it stages the populations of the key block and of the window of
+// other-partner positions the set's channels touch there, then each
+// wavefront streams its group's channels of that key block, reading both
+// partners from LDS (an other partner outside the window is gathered from
+// global memory).  The row sums stay in the wavefronts' lane slots across the
+// range.  The channel stream is the same as in the item kernels; a range's
+// first and last batches load only the pairs inside it.
+
+// dst[0, len) = z[start, start + len) (zero outside [0, n)), 16-byte loads
+// (aligned by address) by all `nt` threads of the block.
+template <typename T>
+__device__ __forceinline__ void stage(T* dst, const T* __restrict__ z, int64_t start, int len, int64_t n, int tid,
+                                      int nt) {
+  constexpr int V = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(V)));
+  const int sh = (int)(((uintptr_t)(z + start) / sizeof(T)) & (V - 1));
+  const int64_t g0 = start - sh;
+  const int nv = (sh + len + V - 1) / V;
+  for (int p = tid; p < nv; p += nt) {
+    const int64_t gi = g0 + (int64_t)V * p;
+    T v[V];
+    if (gi >= 0 && gi + V <= n) {
+      const vec w = *reinterpret_cast<const vec*>(z + gi);
+#pragma unroll
+      for (int k = 0; k < V; ++k) v[k] = w[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; ++k) v[k] = (gi + k >= 0 && gi + k < n) ? z[gi + k] : T(0);
+    }
+    const int li = V * p - sh;
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+      if (li + k >= 0 && li + k < len) dst[li + k] = v[k];
+  }
+}
+
+// The staged windows of one key block: key positions [klo, klo + klen),
+// other-partner positions [olo, olo + olen).
+template <typename T>
+struct Windows {
+  const T* key;
+  const T* oth;
+  uint32_t klo, klen, olo, olen;
+  // Populations of a channel whose (masked-in) partner words are lo, hi:
+  // the key from LDS; the other from LDS, or `glob` outside its window.
+  template <int KIND>
+  __device__ __forceinline__ void get(uint32_t lo, uint32_t hi, uint32_t pmask, bool valid,
+                                      const T* __restrict__ glob, T& g0, T& g1) const {
+    const uint32_t kp = (KIND == K_EPH ? hi : lo) & pmask;
+    const uint32_t op = (KIND == K_EPH ? lo : hi) & pmask;
+    const uint32_t ku = valid ? min(kp - klo, klen - 1u) : 0u;
+    const uint32_t ou = op - olo;
+    const T gk = key[ku];
+    T go;
+    if (!valid || ou < olen) go = oth[valid ? ou : 0u];
+    else go = glob[op];
+    if (KIND == K_EPH) { g0 = go; g1 = gk; }
+    else { g0 = gk; g1 = go; }
+  }
+};
+
+// Packed FP64 channels [s, e) of one kind against staged windows: the batch
+// structure of seg_sum_p12, loads restricted to the pairs of [s, e).
+template <int G, int KIND, bool DERIV>
+__device__ __forceinline__ void seg_sum_p12_win(LaneAcc<G>& acc, const RowArgs& a, int64_t s, int64_t e, int lane,
+                                                const double* __restrict__ zi, const double* rowv,
+                                                const Windows<double>& w) {
+  if (s >= e) return;
+  const v4u* A2 = reinterpret_cast<const v4u*>(a.pk);
+  const v4u* B4 = reinterpret_cast<const v4u*>(a.pkw);
+  const int P = a.pack_p, sh = 52 - a.pack_m;
+  const uint32_t pmask = (1u << P) - 1u;
+  const int64_t p_beg = s >> 1, p_end = (e + 1) >> 1;   // pairs [p_beg, p_end)
+  int64_t pb = p_beg & ~(int64_t)127;
+  v4u c0 = v4u{0u, 0u, 0u, 0u}, c1 = c0, wl = c0;
+  {
+    const int64_t q0 = pb + lane, q1 = q0 + 64;
+    const bool in0 = q0 >= p_beg && q0 < p_end, in1 = q1 >= p_beg && q1 < p_end;
+    if (in0) c0 = __builtin_nontemporal_load(A2 + q0);
+    if (in1) c1 = __builtin_nontemporal_load(A2 + q1);
+    if (in0 || in1) wl = __builtin_nontemporal_load(B4 + pb / 2 + lane);
+  }
+  for (;;) {
+    const v4u c[2] = {c0, c1};
+    double g0[4], g1[4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t ca = 2 * (pb + lane + 64 * j);
+      w.template get<KIND>(c[j].x, c[j].y, pmask, ca >= s && ca < e, zi, g0[2 * j], g1[2 * j]);
+      w.template get<KIND>(c[j].z, c[j].w, pmask, ca + 1 >= s && ca + 1 < e, zi, g0[2 * j + 1], g1[2 * j + 1]);
+    }
+    const int64_t nb = pb + 128;
+    const bool more = nb < p_end;
+    v4u n0 = v4u{0u, 0u, 0u, 0u}, n1 = n0, m = n0;
+    if (more) {   // the first pair of the next batch is inside the range
+      const int64_t q0 = nb + lane, q1 = q0 + 64;
+      const bool in0 = q0 < p_end, in1 = q1 < p_end;
+      if (in0) n0 = __builtin_nontemporal_load(A2 + q0);
+      if (in1) n1 = __builtin_nontemporal_load(A2 + q1);
+      if (in0 || in1) m = __builtin_nontemporal_load(B4 + nb / 2 + lane);
+    }
+    const uint32_t wlo[4] = {wl.x, wl.y, wl.z, wl.w};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t ca = 2 * (pb + lane + 64 * j);
+      if (ca >= s && ca < e)
+        chan_p12<G, KIND, DERIV>(acc, c[j].x, c[j].y, wlo[2 * j], g0[2 * j], g1[2 * j], rowv, P, sh);
+      if (ca + 1 >= s && ca + 1 < e)
+        chan_p12<G, KIND, DERIV>(acc, c[j].z, c[j].w, wlo[2 * j + 1], g0[2 * j + 1], g1[2 * j + 1], rowv, P, sh);
+    }
+    if (!more) break;
+    c0 = n0;
+    c1 = n1;
+    wl = m;
+    pb = nb;
+  }
+}
+
+template <int G, bool DERIV>
+__global__ __launch_bounds__(64 * kTileWaves) void k_items_tiled(RowArgs a) {
+  __shared__ double kwin[kTileKey64];
+  __shared__ double owin[kTileOther64];
+  __shared__ double acc_lds[kTileWaves][G][64];
+  __shared__ double rowv[kTileWaves][kMaxGroupRows];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if ((int64_t)blockIdx.x >= a.n_blocks) return;
+  const TileBlock* bp = a.blocks + a.border[blockIdx.x];
+  const TileBlock b = *bp;
+  if (a.st && a.st[b.inst].done) return;            // the whole block
+  const InstInfo inf = a.info[b.inst];
+  const uint32_t n_inst = (uint32_t)(inf.n_el + inf.n_ph);
+  const double* zi = a.z + inf.off;
+  const int it = bp->item[wave];                    // per-wave fields read by address
+  const int64_t bo = bp->bndo[wave];
+  Group g{};
+  if (it >= 0) g = a.groups[a.items[it].group];
+#pragma unroll
+  for (int j = 0; j < G; ++j) acc_lds[wave][j][lane] = 0.0;
+  if (it >= 0 && lane < g.nrows) rowv[wave][lane] = a.z[g.row0 + lane];
+  LaneAcc<G> acc{&acc_lds[wave][0][lane], 0.0};
+  if ((a.parts >> b.kind) & 1) {
+    for (int j = b.j0; j < b.j1; ++j) {
+      const Tile t = a.tiles[b.tile0 + (j - b.j0)];
+      if (t.lo == kTileEmpty) continue;              // the same for the whole block
+      const uint32_t klo = (uint32_t)j * kTileKey64;
+      const uint32_t klen = min((uint32_t)kTileKey64, n_inst - klo);
+      __syncthreads();                               // the previous key block's reads are done
+      stage(kwin, a.z, inf.off + klo, (int)klen, a.ny, tid, 64 * kTileWaves);
+      stage(owin, a.z, inf.off + t.lo, (int)t.len, a.ny, tid, 64 * kTileWaves);
+      __syncthreads();
+      if (it >= 0) {
+        const int64_t s = a.bnd[bo + j], e = a.bnd[bo + j + 1];
+        const Windows<double> w{kwin, owin, klo, klen, t.lo, t.len};
+        if (b.kind == K_EPH) seg_sum_p12_win<G, K_EPH, DERIV>(acc, a, s, e, lane, zi, rowv[wave], w);
+        else if (b.kind == K_PHE) seg_sum_p12_win<G, K_PHE, DERIV>(acc, a, s, e, lane, zi, rowv[wave], w);
+        else seg_sum_p12_win<G, K_PP, DERIV>(acc, a, s, e, lane, zi, rowv[wave], w);
+      }
+    }
+  }
+  __syncthreads();
+  if (it < 0) return;
+  if (G == 1) {              // one-row groups accumulate in a register
+    double v = acc.reg;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) a.partial[(int64_t)it * kMaxGroupRows] = v;
+  } else if (lane < g.nrows) {
+    // row `lane` of the group: its slot in every lane, in lane order
+    const double* p = acc_lds[wave][lane];
+    double sum = 0.0;
+    for (int l = 0; l < 64; ++l) sum += p[l];
+    a.partial[(int64_t)it * kMaxGroupRows + lane] = sum;
+  }
+}
+
+template <bool DERIV>
+hipError_t launch_tiled_fmt(const RowArgs& a, int slots, hipStream_t s) {
+  const dim3 grid((unsigned)a.n_blocks), blk(64 * kTileWaves);
+  switch (slots) {
+    case 1: hipLaunchKernelGGL((k_items_tiled<1, DERIV>), grid, blk, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_items_tiled<8, DERIV>), grid, blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_items_tiled<16, DERIV>), grid, blk, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Mixed precision (packed 8-byte words) against staged windows of 4-byte
+// population codes: the batch structure of seg_sum_mixed.
+template <int KIND>
+__device__ __forceinline__ void seg_sum_mixed_win(MixAcc& acc, const MixArgs& a, int64_t s, int64_t e, int lane,
+                                                  const float2* rowv, const float* __restrict__ popi,
+                                                  const Windows<float>& w) {
+  if (s >= e) return;
+  constexpr int NP = kMixPairs;
+  const uint32_t pmask = (1u << a.pack_p) - 1u;
+  const v4i* idx2 = reinterpret_cast<const v4i*>(a.idx);
+  const int64_t p_beg = s >> 1, p_end = (e + 1) >> 1;
+  int64_t pb = p_beg;
+  v4i c[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const int64_t q = pb + lane + 64 * j;
+    c[j] = v4i{0, 0, 0, 0};
+    if (q < p_end) c[j] = __builtin_nontemporal_load(idx2 + q);
+  }
+  for (;;) {
+    float g0[2 * NP], g1[2 * NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int64_t ca = 2 * (pb + lane + 64 * j);
+      w.template get<KIND>((uint32_t)c[j].x, (uint32_t)c[j].y, pmask, ca >= s && ca < e, popi, g0[2 * j],
+                           g1[2 * j]);
+      w.template get<KIND>((uint32_t)c[j].z, (uint32_t)c[j].w, pmask, ca + 1 >= s && ca + 1 < e, popi,
+                           g0[2 * j + 1], g1[2 * j + 1]);
+    }
+    const int64_t blk = __builtin_amdgcn_readfirstlane((int)(pb / (kMixBlock / 2)));
+    const float s_lo = a.scale[blk];
+    const float s_hi = a.scale[blk + 1 < a.n_scale ? blk + 1 : blk];
+    const int64_t nb = pb + 64 * NP;
+    const bool more = nb < p_end;
+    v4i n[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) n[j] = v4i{0, 0, 0, 0};
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        const int64_t q = nb + lane + 64 * j;
+        if (q < p_end) n[j] = __builtin_nontemporal_load(idx2 + q);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int64_t q = pb + lane + 64 * j;
+      const float sc = q / (kMixBlock / 2) == blk ? s_lo : s_hi;
+      const int64_t ca = 2 * q;
+      if (ca >= s && ca < e)
+        chan_mixed<KIND, true>(acc, a, (uint32_t)c[j].x, (uint32_t)c[j].y, 0u, sc, g0[2 * j], g1[2 * j], rowv);
+      if (ca + 1 >= s && ca + 1 < e)
+        chan_mixed<KIND, true>(acc, a, (uint32_t)c[j].z, (uint32_t)c[j].w, 0u, sc, g0[2 * j + 1], g1[2 * j + 1],
+                               rowv);
+    }
+    if (!more) break;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) c[j] = n[j];
+    pb = nb;
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(64 * kTileWaves) void k_items_mixed_tiled(MixArgs a) {
+  __shared__ float kwin[kTileKey32];
+  __shared__ float owin[kTileOther32];
+  __shared__ float2 acc_lds[kTileWaves][G][64];
+  __shared__ float2 rowv[kTileWaves][kMaxGroupRows];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if ((int64_t)blockIdx.x >= a.n_blocks) return;
+  const TileBlock* bp = a.blocks + a.border[blockIdx.x];
+  const TileBlock b = *bp;
+  if (a.st && a.st[b.inst].done) return;
+  const InstInfo inf = a.info[b.inst];
+  const uint32_t n_inst = (uint32_t)(inf.n_el + inf.n_ph);
+  const float* popi = a.pop + inf.off;
+  const int it = bp->item[wave];
+  const int64_t bo = bp->bndo[wave];
+  Group g{};
+  if (it >= 0) g = a.groups[a.items[it].group];
+#pragma unroll
+  for (int j = 0; j < G; ++j) acc_lds[wave][j][lane] = make_float2(0.f, 0.f);
+  if (it >= 0 && lane < g.nrows) {
+    const float v = a.pop[g.row0 + lane];
+    rowv[wave][lane] = g.phonon ? ph_pair(v) : el_pair(v);
+  }
+  MixAcc acc{&acc_lds[wave][0][lane]};
+  if ((a.parts >> b.kind) & 1) {
+    for (int j = b.j0; j < b.j1; ++j) {
+      const Tile t = a.tiles[b.tile0 + (j - b.j0)];
+      if (t.lo == kTileEmpty) continue;
+      const uint32_t klo = (uint32_t)j * kTileKey32;
+      const uint32_t klen = min((uint32_t)kTileKey32, n_inst - klo);
+      __syncthreads();
+      stage(kwin, a.pop, inf.off + klo, (int)klen, a.ny, tid, 64 * kTileWaves);
+      stage(owin, a.pop, inf.off + t.lo, (int)t.len, a.ny, tid, 64 * kTileWaves);
+      __syncthreads();
+      if (it >= 0) {
+        const int64_t s = a.bnd[bo + j], e = a.bnd[bo + j + 1];
+        const Windows<float> w{kwin, owin, klo, klen, t.lo, t.len};
+        if (b.kind == K_EPH) seg_sum_mixed_win<K_EPH>(acc, a, s, e, lane, rowv[wave], popi, w);
+        else if (b.kind == K_PHE) seg_sum_mixed_win<K_PHE>(acc, a, s, e, lane, rowv[wave], popi, w);
+        else seg_sum_mixed_win<K_PP>(acc, a, s, e, lane, rowv[wave], popi, w);
+      }
+    }
+  }
+  __syncthreads();
+  if (it >= 0 && lane < g.nrows) {
+    double sum = 0.0, comp = 0.0;
+    for (int l = 0; l < 64; ++l) {
+      sum += (double)acc_lds[wave][lane][l].x;
+      comp += (double)acc_lds[wave][lane][l].y;
+    }
+    a.partial[(int64_t)it * kMaxGroupRows + lane] = sum + comp;
+  }
+}
+
+hipError_t launch_tiled_mixed(const MixArgs& a, int slots, hipStream_t s) {
+  const dim3 grid((unsigned)a.n_blocks), blk(64 * kTileWaves);
+  switch (slots) {
+    case 1: hipLaunchKernelGGL((k_items_mixed_tiled<1>), grid, blk, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_items_mixed_tiled<8>), grid, blk, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_items_mixed_tiled<16>), grid, blk, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Create time: first channel of each key block of each segment (binary
+// search over the segment's channels, sorted by key).
+__global__ void k_key_bounds(const uint64_t* words, int P, const SegRange* segs, int64_t n_segs, int64_t key_len,
+                             int64_t* bnd) {
+  const int64_t si = blockIdx.y * (int64_t)gridDim.x + blockIdx.x;
+  if (si >= n_segs) return;
+  const SegRange sg = segs[si];
+  const uint32_t pmask = (1u << P) - 1u;
+  for (int j = threadIdx.x; j <= sg.n_kb; j += blockDim.x) {
+    const uint64_t target = (uint64_t)j * (uint64_t)key_len;
+    int64_t lo = sg.lo, hi = sg.hi;   // first channel in [lo, hi) with key >= target
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      const uint64_t wd = words[mid];
+      const uint32_t key = (uint32_t)(sg.kind == 0 ? (wd >> 32) : wd) & pmask;
+      if (key < target) lo = mid + 1;
+      else hi = mid;
+    }
+    bnd[sg.off + j] = lo;
+  }
+}
+
+hipError_t launch_key_bounds(const uint64_t* words, int pack_p, const SegRange* segs, int64_t n_segs,
+                             int64_t key_len, int64_t* bnd, hipStream_t s) {
+  if (n_segs == 0) return hipSuccess;
+  const int64_t gx = std::min<int64_t>(n_segs, 65535), gy = (n_segs + gx - 1) / gx;
+  hipLaunchKernelGGL(k_key_bounds, dim3((unsigned)gx, (unsigned)gy), dim3(128), 0, s, words, pack_p, segs, n_segs,
+                     key_len, bnd);
+  return hipGetLastError();
+}
+
+// Create time: smallest and largest other-partner position of the channels
+// of one key block of a set of segments, one wavefront per job.
+__global__ __launch_bounds__(64) void k_tile_span(const uint64_t* words, int P, const SpanJob* jobs,
+                                                  int64_t n_jobs, const int64_t* bnd, uint32_t* span) {
+  const int64_t ji = blockIdx.y * (int64_t)gridDim.x + blockIdx.x;
+  if (ji >= n_jobs) return;
+  const SpanJob jb = jobs[ji];
+  const uint32_t pmask = (1u << P) - 1u;
+  uint32_t mn = 0xffffffffu, mx = 0u;
+  for (int w = 0; w < kTileWaves; ++w) {
+    if (jb.bndo[w] < 0) continue;
+    const int64_t s = bnd[jb.bndo[w] + jb.j], e = bnd[jb.bndo[w] + jb.j + 1];
+    for (int64_t c = s + threadIdx.x; c < e; c += 64) {
+      const uint64_t wd = words[c];
+      const uint32_t o = (uint32_t)(jb.kind == 0 ? wd : (wd >> 32)) & pmask;
+      mn = min(mn, o);
+      mx = max(mx, o);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, o, 64));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+  }
+  if (threadIdx.x == 0) {
+    span[2 * ji] = mn;
+    span[2 * ji + 1] = mx;
+  }
+}
+
+hipError_t launch_tile_span(const uint64_t* words, int pack_p, const SpanJob* jobs, int64_t n_jobs,
+                            const int64_t* bnd, uint32_t* span, hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  const int64_t gx = std::min<int64_t>(n_jobs, 65535), gy = (n_jobs + gx - 1) / gx;
+  hipLaunchKernelGGL(k_tile_span, dim3((unsigned)gx, (unsigned)gy), dim3(64), 0, s, words, pack_p, jobs, n_jobs,
+                     bnd, span);
   return hipGetLastError();
 }
 

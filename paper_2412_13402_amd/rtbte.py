@@ -69,7 +69,7 @@ class Options(ctypes.Structure):
         ("fp64_check", ctypes.c_int32),
         ("small_nef", ctypes.c_int32),
         ("eta_fail_repeat", ctypes.c_double),
-        ("pp_fold", ctypes.c_int32),
+        ("pp_fold", ctypes.c_int32), ("tiled", ctypes.c_int32),
     ]
 
 

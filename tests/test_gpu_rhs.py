@@ -48,19 +48,21 @@ def random_state(wl, seed):
 CASES = ["toy2d", "tiny2d", "tiny3d", "lattice2d", "medium2d"]
 
 
-@pytest.mark.parametrize("layout", ["packed", "plain"])
+@pytest.mark.parametrize("layout", ["packed", "packed-tiled", "plain"])
 @pytest.mark.parametrize("name", CASES)
 def test_rhs_matches_oracle(name, layout):
+    """packed: the per-item launch (the default); packed-tiled: the tiled
+    launch over the same channels."""
     torch = torch_cuda()
     import paper_2412_13402_amd as P
     wl = workload(name)
     o = oracle_of(name)
     say(f"[rhs] {name} ({layout}) n_y={wl.n_y} entries={len(wl.eph_row)}+{len(wl.pp_row)}")
-    code = P.rtbte.F64_PACKED if layout == "packed" else P.rtbte.F64_PLAIN
-    ctx = P.Context(wl.problem_arrays(), fp64_layout=code)
+    code = P.rtbte.F64_PLAIN if layout == "plain" else P.rtbte.F64_PACKED
+    ctx = P.Context(wl.problem_arrays(), fp64_layout=code, tiled=1 if layout == "packed-tiled" else 0)
     assert ctx.counts() == o.counts()
     # these grids need at most 14 position bits: packed weights are exact
-    assert ctx.weight_format() == ((-2, 12, 0.0) if layout == "packed" else (-1, 16, 0.0))
+    assert ctx.weight_format() == ((-1, 16, 0.0) if layout == "plain" else (-2, 12, 0.0))
     for seed, y in ((0, wl.y0), (1, random_state(wl, 1)), (2, random_state(wl, 2))):
         yd = to_dev(y)
         for parts in (1, 2, 4, 3, 7):
@@ -75,16 +77,17 @@ SHAPES = [(1, 1, 0), (2, 4, 0), (4, 8, 0), (8, 16, 0), (16, 12, 0), (12, 2, 0),
           (8, 16, 1000), (16, 16, 333), (1, 16, 64), (4, 4, 10 ** 7)]
 
 
+@pytest.mark.parametrize("tiled", [1, 0])
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("name", ["medium2d", "tiny3d"])
-def test_every_launch_shape(name, shape):
+def test_every_launch_shape(name, shape, tiled):
     torch = torch_cuda()
     import paper_2412_13402_amd as P
     ge, gp, ic = shape
     wl = workload(name)
     o = oracle_of(name)
-    say(f"[rhs] {name} group_rows_el={ge} group_rows_ph={gp} item_channels={ic}")
-    ctx = P.Context(wl.problem_arrays(), group_rows_el=ge, group_rows_ph=gp, item_channels=ic)
+    say(f"[rhs] {name} group_rows_el={ge} group_rows_ph={gp} item_channels={ic} tiled={tiled}")
+    ctx = P.Context(wl.problem_arrays(), group_rows_el=ge, group_rows_ph=gp, item_channels=ic, tiled=tiled)
     assert ctx.tuning()[:2] == (ge, gp) and (ic == 0 or ctx.tuning()[2] == ic)
     assert ctx.counts() == o.counts()
     y = random_state(wl, 5)

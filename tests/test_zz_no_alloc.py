@@ -54,8 +54,8 @@ def test_noalloc_rejects_a_shape_beyond_the_static_buffer():
     torch = torch_cuda()
     import paper_2412_13402_amd as P
     wl = synth.build("graphene2d", L=36)
-    say("[noalloc] over the limit: graphene2d L=36, 16 channels per item")
-    ctx = P.Context(wl.problem_arrays(), item_channels=16)
+    say("[noalloc] over the limit: graphene2d L=36, per-item launch, 16 channels per item")
+    ctx = P.Context(wl.problem_arrays(), item_channels=16, tiled=0)
     assert ctx.noalloc_scratch_bytes() > P.rtbte.noalloc_scratch_limit()
     y = to_dev(wl.y0)
     out = torch.zeros_like(y)
