@@ -167,6 +167,8 @@ def main():
                     help="batched leg: fixed-step RK4 span of the mixed-vs-FP64 population check")
     ap.add_argument("--batch-rk4-h", type=float, default=4.0)
     ap.add_argument("--no-tune", action="store_true", help="batched leg: default launch shape, no autotuning")
+    ap.add_argument("--no-matrix-free", action="store_true",
+                    help="skip the matrix-free ph-ph weights leg (|V3|^2 model evaluated in the kernel)")
     ap.add_argument("--tiled", type=int, default=0, choices=(0, 1),
                     help="0 (default): per-item collision kernels; 1: tiled (partners staged in LDS)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -312,6 +314,8 @@ def main():
         }
     if ctx_m is not None and not args.no_errors:
         rec["mixed"].update(mixed_errors(P, torch, np, ctx, ctx_m, wl, o, args))
+    if not args.no_matrix_free:
+        rec["matrix_free_pp"] = matrix_free_leg(P, torch, np, wl, args, ctx, o)
     if not args.no_horizon:
         hz = horizon_leg(P, torch, np, wl, args, ctx, ctx_m)
         rec["horizon"] = hz
@@ -334,6 +338,62 @@ def main():
     if not args.no_toy:
         rec["toy"] = toy_leg(P, torch, np, with_oracle=not args.no_cpu_baseline)
     print(json.dumps(rec), flush=True)
+
+
+# VALU lane-instructions per ph-ph channel of the matrix-free FP64 kernel
+# (rocprofv3 SQ_INSTS_VALU x 64 over the ph-ph channels of one launch,
+# graphene-like workload: profiles/k_items_matrix_free_graphene2d.md)
+MF_VALU_PER_CHANNEL = 544
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock
+
+
+def matrix_free_leg(P, torch, np, wl, args, ctx64, o):
+    """Matrix-free ph-ph weights: the ph-ph channels keep partners and flags
+    only, and every right-hand side recomputes prefactor * |V3|^2 * delta from
+    the generator's |V3|^2 model (Philox4x32-10 over the canonical triplet,
+    Box-Muller, lognormal) in FP64.  Times the ph-ph part and the whole
+    right-hand side against the stored-weight FP64 context, and checks the
+    matrix-free right-hand side against the oracle at the initial state."""
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    res = {"what": "ph-ph weights recomputed from the |V3|^2 model at every right-hand side (FP64); "
+                   "e-ph and ph-e from stored weights"}
+    y = torch.tensor(wl.y0, dtype=torch.float64, device=dev)
+    for name, kw in (("fp64", {}), ("mixed", dict(precision=P.rtbte.MIXED))):
+        c = P.Context(dict(wl.problem_arrays(), pp_v2=None), pp_model=wl.pp_model(), **kw)
+        torch.cuda.synchronize()
+        leg = {"create_s": time.perf_counter() - t0}
+        for part, label in ((P.PART_PHPH, "phph"), (P.PART_ALL, "all")):
+            r = kernel_roofline(c, torch, y, part)
+            leg[f"{label}_ms"] = r["avg_launch_ms"]
+            leg[f"{label}_bytes_per_launch"] = r["algorithmic_bytes_per_launch"]
+        stored = c.stored_counts()
+        leg["phph_channels_per_s"] = stored[2] / (leg["phph_ms"] * 1e-3)
+        if name == "fp64":
+            ref = kernel_roofline(ctx64, torch, y, P.PART_PHPH)
+            leg["stored_weights_phph_ms"] = ref["avg_launch_ms"]
+            leg["slowdown_vs_stored"] = leg["phph_ms"] / ref["avg_launch_ms"]
+            if MF_VALU_PER_CHANNEL:
+                ach = MF_VALU_PER_CHANNEL * stored[2] / (leg["phph_ms"] * 1e-3)
+                leg["roofline"] = {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                                   "unit": "T VALU lane-instructions/s", "frac": ach / VALU_PEAK_LANE_OPS,
+                                   "instructions_per_channel": MF_VALU_PER_CHANNEL}
+            if o is not None:
+                out = torch.empty_like(y)
+                c.rhs(y, out, P.PART_ALL)
+                torch.cuda.synchronize()
+                g = out.cpu().numpy()
+                rf, S, A = o.rhs(wl.y0, scales=True)
+                leg["rhs_err_vs_oracle"] = {
+                    "max_row_err_over_magnitude": float(np.max(np.abs(g - rf) / np.maximum(A, 1e-300))),
+                    "normwise": float(np.linalg.norm(g - rf) / np.linalg.norm(rf))}
+        res[name] = leg
+        log(f"[bench] matrix-free {name}: ph-ph {leg['phph_ms']:.3f} ms, whole RHS {leg['all_ms']:.3f} ms")
+        del c
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+    return res
 
 
 def horizon_leg(P, torch, np, wl, args, ctx64, ctx_m):

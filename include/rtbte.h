@@ -126,6 +126,30 @@ typedef struct {
   double sigma_eph, sigma_pp, nsigma, hw_cut;
 } rtbte_problem;
 
+/* A model of the ph-ph matrix elements, evaluated on the fly instead of read
+ * from stored weights (the paper interpolates its ph-ph matrix elements on
+ * the fly rather than storing them: Methods, graphene and silicon grid
+ * paragraphs).  The phonon states of an instance are numbered
+ * id = q * n_modes + nu over a periodic grid of L points per axis
+ * (q = i L + j in 2D, (i L + j) L + k in 3D); the time-reversed state of id
+ * is -q with the same nu.  For a channel's triplet (l; a, b):
+ *   (c0, c1, c2) = the sorted ids of the triplet or of its time-reversed
+ *                  image, whichever is lexicographically smaller;
+ *   (r0, r1, r2, r3) = Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11)
+ *                  of the counter (c0, c1, c2, stream) under (key0, key1);
+ *   n = sqrt(-2 ln u1) cos(2 pi u2), u_i = (r_i + 1/2) 2^-32 (Box-Muller);
+ *   |V3|^2 = exp(ln_mu + ln_sigma n)   (eV^2).
+ * It is symmetric under permutation of the three phonons and under time
+ * reversal. */
+typedef struct {
+  int32_t dim;              /* 2 or 3 */
+  int32_t L;                /* grid points per axis */
+  int32_t n_modes;          /* phonon branches (n_ph = n_modes * L^dim) */
+  uint32_t key0, key1;      /* Philox key */
+  uint32_t stream;          /* fourth counter word */
+  double ln_mu, ln_sigma;   /* ln|V3|^2 = ln_mu + ln_sigma * n */
+} rtbte_pp_model;
+
 /* Options; rtbte_default_options fills every field. */
 typedef struct {
   int32_t precision;       /* RTBTE_FP64 (default) or RTBTE_MIXED: compact weights relative
@@ -217,6 +241,14 @@ typedef struct {
                                graphene-like workload it is slower (its 64 KB of LDS per
                                block allow two blocks per compute unit).  Both give the
                                same results to rounding order.                              */
+  const rtbte_pp_model *pp_model; /* NULL (default): ph-ph weights from pp_v2.  Else n_inst
+                               models, one per instance: matrix-free ph-ph weights.  The
+                               channel list keeps partners and flags only (8 bytes per ph-ph
+                               channel) and every right-hand side recomputes
+                               prefactor * |V3|^2 * delta (FP64, in both precisions) from
+                               the model and the phonon energies; pp_v2 may be NULL (it is
+                               not read).  Needs the packed layouts (FP64 packed, mixed
+                               RTBTE_W_PACK8) and tiled = 0 (RTBTE_E_UNSUPPORTED else).   */
 } rtbte_options;
 
 enum { RTBTE_F64_AUTO = 0, RTBTE_F64_PACKED = 1, RTBTE_F64_PLAIN = 2 };

@@ -223,6 +223,8 @@ struct rtbte_ctx {
   double tuned_ms = 0.0;
   // this device's address of the static scratch (rtbte_rhs_noalloc)
   void* scratch_dev = nullptr;
+  // matrix-free ph-ph weights: one model per instance (device)
+  PpModel* ppm = nullptr;
   // tiled launch (packed layouts): blocks, their order, tiles, key-block bounds
   bool tiled = false;
   TileBlock* tblocks = nullptr;
@@ -360,7 +362,7 @@ void group_entries(int64_t n, const int32_t* dest, int32_t nrows, int G, const i
   }
 }
 
-int check_problem(const rtbte_problem& p, int inst) {
+int check_problem(const rtbte_problem& p, int inst, bool v2_optional = false) {
   if (p.n_el < 0 || p.n_ph < 0 || p.n_eph < 0 || p.n_pp < 0)
     return fail(nullptr, RTBTE_E_INVAL, "instance %d: negative size", inst);
   if ((int64_t)p.n_el + p.n_ph == 0)
@@ -373,7 +375,7 @@ int check_problem(const rtbte_problem& p, int inst) {
     return fail(nullptr, RTBTE_E_INVAL, "instance %d: missing energies", inst);
   if (p.n_eph && (!p.eph_row || !p.eph_partner || !p.eph_phonon || !p.eph_g2))
     return fail(nullptr, RTBTE_E_INVAL, "instance %d: missing e-ph arrays", inst);
-  if (p.n_pp && (!p.pp_row || !p.pp_a || !p.pp_b || !p.pp_v2))
+  if (p.n_pp && (!p.pp_row || !p.pp_a || !p.pp_b || (!p.pp_v2 && !v2_optional)))
     return fail(nullptr, RTBTE_E_INVAL, "instance %d: missing ph-ph arrays", inst);
   int64_t bad = -1;
 #pragma omp parallel for reduction(max : bad)
@@ -422,7 +424,7 @@ void free_ctx(rtbte_ctx* c) {
                 c->st_fast, c->st_slow, c->mra, c->mis_keep, c->energy_d,
                 c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
                 c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
-                c->partial, c->tvec, c->summary_d, c->tblocks, c->border, c->tiles, c->bnd};
+                c->partial, c->tvec, c->summary_d, c->tblocks, c->border, c->tiles, c->bnd, c->ppm};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   for (auto& g : c->graphs) {
@@ -703,8 +705,8 @@ bool pp_mirror_symmetric(const rtbte_problem& p, int64_t* folded) {
   for (int64_t e = 0; e < p.n_pp; ++e) {
     const int32_t l = p.pp_row[e], a = p.pp_a[e], b = p.pp_b[e];
     if (a == b) continue;
-    uint64_t vb;
-    std::memcpy(&vb, &p.pp_v2[e], sizeof vb);
+    uint64_t vb = 0;   // no values (matrix-free weights): the model is symmetric
+    if (p.pp_v2) std::memcpy(&vb, &p.pp_v2[e], sizeof vb);
     const uint64_t h = mix64(mix64(mix64((uint64_t)(uint32_t)l + 0x9E3779B97F4A7C15ull) +
                                    (uint64_t)(uint32_t)std::min(a, b)) +
                              (uint64_t)(uint32_t)std::max(a, b)) + mix64(vb ^ 0xD1B54A32D192ED03ull);
@@ -752,8 +754,20 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
       o.steps_per_poll < 1 || o.max_fails < 0)
     return fail(nullptr, RTBTE_E_INVAL, "invalid tolerances or controller options");
   for (int i = 0; i < n_inst; ++i) {
-    int rc = check_problem(problems[i], i);
+    int rc = check_problem(problems[i], i, o.pp_model != nullptr);
     if (rc) return rc;
+  }
+  if (o.pp_model) {
+    if (o.tiled) return fail(nullptr, RTBTE_E_UNSUPPORTED, "matrix-free ph-ph weights need tiled = 0");
+    for (int i = 0; i < n_inst; ++i) {
+      const rtbte_pp_model& m = o.pp_model[i];
+      int64_t nq = m.L;
+      for (int d = 1; d < m.dim; ++d) nq *= m.L;
+      if ((m.dim != 2 && m.dim != 3) || m.L < 1 || m.n_modes < 1 || nq * m.n_modes != problems[i].n_ph ||
+          !std::isfinite(m.ln_mu) || !std::isfinite(m.ln_sigma))
+        return fail(nullptr, RTBTE_E_INVAL, "instance %d: pp_model does not describe its %d phonon states", i,
+                    problems[i].n_ph);
+    }
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -872,7 +886,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
     UP(d.pr, p.pp_row, p.n_pp);
     UP(d.pa, p.pp_a, p.n_pp);
     UP(d.pb, p.pp_b, p.n_pp);
-    UP(d.pv, p.pp_v2, p.n_pp);
+    if (p.pp_v2) UP(d.pv, p.pp_v2, p.n_pp);   // absent with matrix-free weights (values taken as 1)
     // electron side: groups of electron rows, merged by phonon (the shared q)
     group_entries(p.n_eph, p.eph_row, p.n_el, GE, p.eph_phonon, perm, gptr);
     if (!perm.empty()) UP(d.perm_e, perm.data(), perm.size());
@@ -1075,6 +1089,33 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   // tiled launch blocks over the packed words
   if (e == hipSuccess && o.tiled && (c->mixed ? c->wfmt == RTBTE_W_PACK8 : c->pk != nullptr))
     e = build_tiles(c, o.item_channels);
+  // matrix-free ph-ph weights: the models with each instance's prefactor,
+  // width, fold and phonon offset (packed words only)
+  if (e == hipSuccess && o.pp_model) {
+    if (c->mixed ? c->wfmt != RTBTE_W_PACK8 : c->pk == nullptr) {
+      free_ctx(c);
+      return fail(nullptr, RTBTE_E_UNSUPPORTED,
+                  "matrix-free ph-ph weights need packed channels (FP64 packed or RTBTE_W_PACK8)");
+    }
+    std::vector<PpModel> pm((size_t)n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      const rtbte_pp_model& m = o.pp_model[i];
+      PpModel& q = pm[(size_t)i];
+      q.dim = m.dim;
+      q.L = m.L;
+      q.n_modes = m.n_modes;
+      q.folded = c->folded[(size_t)i] > 0 ? 1 : 0;
+      q.key0 = m.key0;
+      q.key1 = m.key1;
+      q.stream = m.stream;
+      q.n_el = (uint32_t)problems[i].n_el;
+      q.ln_mu = m.ln_mu;
+      q.ln_sigma = m.ln_sigma;
+      q.pre = (36.0 * kPi / kHbarEvFs) / (double)problems[i].n_q_total;
+      q.sigma = problems[i].sigma_pp;
+    }
+    e = upload(&c->ppm, pm.data(), pm.size());
+  }
   if (e == hipSuccess && n_inst > 1) {
     std::vector<int32_t> ri((size_t)c->ny);
     for (int i = 0; i < n_inst; ++i)
@@ -1226,16 +1267,21 @@ namespace {
 // and a 4 B scale per 512), the populations once (8 B per state; mixed: 4 B),
 // the group and item tables, and the item row sums written.
 double launch_bytes(const rtbte_ctx* c, int parts) {
-  int64_t ch = 0;
+  int64_t ch = 0, pp = 0;
   for (int i = 0; i < c->n_inst; ++i)
     for (int k = 0; k < 3; ++k)
       if (parts & (1 << k)) ch += c->counts[3 * i + k];
+  if (c->ppm && (parts & 4)) {
+    // matrix-free ph-ph channels stream their 8-byte words only
+    for (int i = 0; i < c->n_inst; ++i) pp += c->counts[3 * i + 2];
+    ch -= pp;
+  }
   const double tables = (double)sizeof(Group) * (double)c->n_groups +
                         (double)(sizeof(Item) + 4 + 8 * kMaxGroupRows) * (double)c->n_items;
   if (c->mixed)
     return (c->wfmt == RTBTE_W_PACK8 ? 8.0 : 10.0) * (double)ch + 4.0 * (double)ch / kMixBlock +
-           4.0 * (double)c->ny + tables;
-  return (c->pk ? 12.0 : 16.0) * (double)ch + 8.0 * (double)c->ny + tables;
+           8.0 * (double)pp + 4.0 * (double)c->ny + tables;
+  return (c->pk ? 12.0 : 16.0) * (double)ch + 8.0 * (double)pp + 8.0 * (double)c->ny + tables;
 }
 
 hipError_t harvest(rtbte_ctx* c) {
@@ -1284,6 +1330,8 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
   a.partial = partial;
   a.st = st;
   a.ny = c->ny;
+  a.ppm = c->ppm;
+  a.hw = c->energy_d;
   if (c->tiled && !c->mixed) {
     a.blocks = c->tblocks;
     a.border = c->border;
@@ -1310,6 +1358,8 @@ hipError_t rhs_launch(rtbte_ctx* c, const double* z, int parts, const InstState*
     m.partial = partial;
     m.st = st;
     m.ny = c->ny;
+    m.ppm = c->ppm;
+    m.hw = c->energy_d;
     if (c->tiled) {
       m.blocks = c->tblocks;
       m.border = c->border;

@@ -110,6 +110,15 @@ struct Tile {
   uint32_t lo, len;
 };
 
+// Matrix-free ph-ph weights of one instance: the rtbte_pp_model, the
+// instance's ph-ph prefactor and width, whether its emission pairs are
+// folded, and where its phonons start.
+struct PpModel {
+  int32_t dim, L, n_modes, folded;
+  uint32_t key0, key1, stream, n_el;
+  double ln_mu, ln_sigma, pre, sigma;
+};
+
 // Arguments of the collision kernel (per-item row sums).
 // FP64 channels, packed (12 bytes): an 8-byte word per channel, low half
 // pos0 (bits 0..P-1) | tag (P..P+3) | weight field bits 32..59-P (P+4..31),
@@ -138,6 +147,8 @@ struct RowArgs {
   const Tile* tiles;
   const int64_t* bnd;       // key-block bounds of every segment
   int64_t ny;               // length of z
+  const PpModel* ppm;       // matrix-free ph-ph weights: [n_inst] models (else nullptr)
+  const double* hw;         // [ny] state energies (phonons: hbar omega), with ppm
 };
 
 // Arguments of the row kernel: sums of the items of each row's group, the
@@ -203,6 +214,8 @@ struct MixArgs {
   const Tile* tiles;
   const int64_t* bnd;
   int64_t ny;
+  const PpModel* ppm;
+  const double* hw;
 };
 hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s);
 // Tiled launches (create time), from the packed 8-byte words (FP64 or

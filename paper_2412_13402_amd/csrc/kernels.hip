@@ -219,9 +219,139 @@ __device__ __forceinline__ void seg_sum_p12(LaneAcc<G>& acc, const RowArgs& a, i
   }
 }
 
+// Gaussian delta of the truncated sums (the same function the create-time
+// channel preparation evaluates).
+__device__ __forceinline__ double gdelta(double x, double sigma) {
+  const double u = x / sigma;
+  return exp(-u * u) / (sigma * kSqrtPi);
+}
+
+// ------------------------------------------------- matrix-free ph-ph weights
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of
+// (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
+// lo(M0 c0)), the key bumped by the Weyl constants after every round.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Time-reversed phonon state: -q on the periodic grid, the same branch.
+__device__ __forceinline__ uint32_t reversed_phonon(uint32_t id, const PpModel& m) {
+  const uint32_t nm = (uint32_t)m.n_modes, L = (uint32_t)m.L;
+  const uint32_t q = id / nm, nu = id - q * nm;
+  uint32_t nq;
+  if (m.dim == 2) {
+    const uint32_t i = q / L, j = q - i * L;
+    nq = ((L - i) % L) * L + (L - j) % L;
+  } else {
+    const uint32_t i = q / (L * L), r = q - i * L * L, j = r / L, k = r - j * L;
+    nq = (((L - i) % L) * L + (L - j) % L) * L + (L - k) % L;
+  }
+  return nq * nm + nu;
+}
+
+__device__ __forceinline__ void sort3(uint32_t& a, uint32_t& b, uint32_t& c) {
+  uint32_t t;
+  if (a > b) { t = a; a = b; b = t; }
+  if (b > c) { t = b; b = c; c = t; }
+  if (a > b) { t = a; a = b; b = t; }
+}
+
+// |V3|^2 of the triplet (phonon ids l, a, b) under the model (rtbte_pp_model).
+__device__ __forceinline__ double model_v2(const PpModel& m, uint32_t l, uint32_t a, uint32_t b) {
+  uint32_t x0 = l, x1 = a, x2 = b;
+  uint32_t y0 = reversed_phonon(l, m), y1 = reversed_phonon(a, m), y2 = reversed_phonon(b, m);
+  sort3(x0, x1, x2);
+  sort3(y0, y1, y2);
+  const bool rev = y0 < x0 || (y0 == x0 && (y1 < x1 || (y1 == x1 && y2 < x2)));
+  const uint4 r = philox10(rev ? make_uint4(y0, y1, y2, m.stream) : make_uint4(x0, x1, x2, m.stream), m.key0, m.key1);
+  const double u1 = ((double)r.y + 0.5) * 0x1p-32, u2 = ((double)r.z + 0.5) * 0x1p-32;
+  const double n = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+  return exp(m.ln_mu + m.ln_sigma * n);
+}
+
+// Weight of a ph-ph channel of row l (emission: prefactor, twice for a folded
+// pair; absorption: twice the prefactor) times |V3|^2 times the delta of its
+// energy mismatch.  Positions are relative to the instance.
+__device__ __forceinline__ double mf_weight(const PpModel& m, bool em, uint32_t pl, uint32_t pa, uint32_t pb,
+                                            const double* __restrict__ hwi) {
+  const double wl = hwi[pl], wa = hwi[pa], wb = hwi[pb];
+  const uint32_t l = pl - m.n_el, a = pa - m.n_el, b = pb - m.n_el;
+  const double v = model_v2(m, l, a, b);
+  if (em) return ((m.folded && a < b) ? 2.0 : 1.0) * m.pre * v * gdelta(-wl + wa + wb, m.sigma);
+  return (2.0 * m.pre) * v * gdelta(wl - wa + wb, m.sigma);
+}
+
+// Packed FP64 ph-ph channels [s, e) with matrix-free weights: only the
+// 8-byte words are streamed (the weight bits in them are not read); batches
+// as in seg_sum_p12.  `row_rel` is the group's first row relative to the
+// instance, `hwi` the instance's state energies.
+template <int G, bool DERIV>
+__device__ __forceinline__ void seg_sum_pp_mf(LaneAcc<G>& acc, const RowArgs& a, int64_t s, int64_t e, int lane,
+                                              const double* __restrict__ z, const double* rowv, uint32_t off,
+                                              const PpModel& m, uint32_t row_rel, const double* __restrict__ hwi) {
+  if (s >= e) return;
+  const v4u* A2 = reinterpret_cast<const v4u*>(a.pk);
+  const int P = a.pack_p;
+  const uint32_t pmask = (1u << P) - 1u;
+  const int64_t p_end = (e + 1) / 2;
+  int64_t pb = s / 2;
+  v4u c[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int64_t q = pb + lane + 64 * j;
+    c[j] = v4u{0u, 0u, 0u, 0u};
+    if (q < p_end) c[j] = __builtin_nontemporal_load(A2 + q);
+  }
+  for (;;) {
+    double g0[4], g1[4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      g0[2 * j] = z[(c[j].x & pmask) + off];
+      g1[2 * j] = z[(c[j].y & pmask) + off];
+      g0[2 * j + 1] = z[(c[j].z & pmask) + off];
+      g1[2 * j + 1] = z[(c[j].w & pmask) + off];
+    }
+    const int64_t nb = pb + 128;
+    const bool more = nb < p_end;
+    v4u n[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      n[j] = v4u{0u, 0u, 0u, 0u};
+      const int64_t q = nb + lane + 64 * j;
+      if (more && q < p_end) n[j] = __builtin_nontemporal_load(A2 + q);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t ca = 2 * (pb + lane + 64 * j);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (ca + h < s || ca + h >= e) continue;
+        const uint32_t lo = h ? c[j].z : c[j].x, hi = h ? c[j].w : c[j].y;
+        const int tag = G == 1 ? 0 : (int)((lo >> P) & 15u);
+        const bool em = (hi >> P) & 1u;
+        const double w = mf_weight(m, em, row_rel + (uint32_t)tag, lo & pmask, hi & pmask, hwi);
+        const double xr = rowv[tag];
+        acc.add(tag, term_w<K_PP, DERIV>(em, w, g0[2 * j + h], g1[2 * j + h], xr, xr + 1.0));
+      }
+    }
+    if (!more) break;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) c[j] = n[j];
+    pb = nb;
+  }
+}
+
 // One wavefront per block, so the LDS a block needs is one wavefront's
 // accumulator slots and occupancy is not capped by whole 4-wave blocks.
-template <int G, bool PACK, bool DERIV>
+template <int G, bool PACK, bool DERIV, bool MF = false>
 __global__ __launch_bounds__(64) void k_items(RowArgs a) {
   __shared__ double acc_lds[1][G][64];
   __shared__ double rowv[1][kMaxGroupRows];
@@ -256,7 +386,15 @@ __global__ __launch_bounds__(64) void k_items(RowArgs a) {
         if (a.parts & 1) seg_sum_p12<G, K_EPH, DERIV>(acc, a, item.lo, item.hi, lane, a.z, rv, off);
       } else {
         if (a.parts & 2) seg_sum_p12<G, K_PHE, DERIV>(acc, a, lo_pe, hi_pe, lane, a.z, rv, off);
-        if (a.parts & 4) seg_sum_p12<G, K_PP, DERIV>(acc, a, lo_pp, hi_pp, lane, a.z, rv, off);
+        if (a.parts & 4) {
+          if constexpr (MF) {
+            const PpModel m = a.ppm[g.inst];
+            seg_sum_pp_mf<G, DERIV>(acc, a, lo_pp, hi_pp, lane, a.z, rv, off, m, (uint32_t)g.row0 - off,
+                                    a.hw + off);
+          } else {
+            seg_sum_p12<G, K_PP, DERIV>(acc, a, lo_pp, hi_pp, lane, a.z, rv, off);
+          }
+        }
       }
     } else {
       if (!g.phonon) {
@@ -284,13 +422,13 @@ __global__ __launch_bounds__(64) void k_items(RowArgs a) {
   }
 }
 
-template <bool PACK, bool DERIV>
+template <bool PACK, bool DERIV, bool MF = false>
 hipError_t launch_items_fmt(const RowArgs& a, int slots, hipStream_t s) {
   const int64_t nb = a.n_items;
   switch (slots) {
-    case 1: hipLaunchKernelGGL((k_items<1, PACK, DERIV>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_items<8, PACK, DERIV>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_items<16, PACK, DERIV>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_items<1, PACK, DERIV, MF>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_items<8, PACK, DERIV, MF>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_items<16, PACK, DERIV, MF>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -304,6 +442,10 @@ hipError_t launch_items(const RowArgs& a, int slots, hipStream_t s) {
   if (a.pk) {
     if (!a.pkw || !a.info || a.pack_p < 1 || a.pack_p > 19 || a.pack_m != std::min(80 - 2 * a.pack_p, 52))
       return hipErrorInvalidValue;
+    if (a.ppm) {   // matrix-free ph-ph weights (per-item launch only)
+      if (a.blocks || !a.hw) return hipErrorInvalidValue;
+      return a.deriv ? launch_items_fmt<true, true, true>(a, slots, s) : launch_items_fmt<true, false, true>(a, slots, s);
+    }
     if (a.blocks) {
       if (a.n_blocks == 0) return hipSuccess;
       if (!a.border || !a.tiles || !a.bnd) return hipErrorInvalidValue;
@@ -581,7 +723,65 @@ __device__ __forceinline__ void seg_sum_mixed(MixAcc& acc, const MixArgs& a, int
   }
 }
 
-template <int G, bool PACK>
+// Mixed precision, packed 8-byte words, ph-ph channels [s, e) with
+// matrix-free weights: the weight is formed in FP64 and rounded to FP32 (no
+// block scale); populations, factors and sums as in seg_sum_mixed.
+__device__ __forceinline__ void seg_sum_mixed_pp_mf(MixAcc& acc, const MixArgs& a, int64_t s, int64_t e, int lane,
+                                                    const float2* rowv, uint32_t off, const PpModel& m,
+                                                    uint32_t row_rel, const double* __restrict__ hwi) {
+  if (s >= e) return;
+  constexpr int NP = kMixPairs;
+  const uint32_t pmask = (1u << a.pack_p) - 1u;
+  const int P = a.pack_p;
+  const v4i* idx2 = reinterpret_cast<const v4i*>(a.idx);
+  const int64_t p_end = (e + 1) / 2;
+  int64_t pb = s / 2;
+  v4i c[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    const int64_t q = pb + lane + 64 * j;
+    c[j] = v4i{0, 0, 0, 0};
+    if (q < p_end) c[j] = __builtin_nontemporal_load(idx2 + q);
+  }
+  for (;;) {
+    float g0[2 * NP], g1[2 * NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      g0[2 * j] = a.pop[((uint32_t)c[j].x & pmask) + off];
+      g1[2 * j] = a.pop[((uint32_t)c[j].y & pmask) + off];
+      g0[2 * j + 1] = a.pop[((uint32_t)c[j].z & pmask) + off];
+      g1[2 * j + 1] = a.pop[((uint32_t)c[j].w & pmask) + off];
+    }
+    const int64_t nb = pb + 64 * NP;
+    const bool more = nb < p_end;
+    v4i n[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      n[j] = v4i{0, 0, 0, 0};
+      const int64_t q = nb + lane + 64 * j;
+      if (more && q < p_end) n[j] = __builtin_nontemporal_load(idx2 + q);
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int64_t ca = 2 * (pb + lane + 64 * j);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (ca + h < s || ca + h >= e) continue;
+        const uint32_t ix = (uint32_t)(h ? c[j].z : c[j].x), iy = (uint32_t)(h ? c[j].w : c[j].y);
+        const int tag = (ix >> P) & 15;
+        const bool em = (int32_t)iy < 0;
+        const float w = (float)mf_weight(m, em, row_rel + (uint32_t)tag, ix & pmask, iy & pmask, hwi);
+        acc.add(tag, term_f<K_PP>(em, w, g0[2 * j + h], g1[2 * j + h], rowv[tag]));
+      }
+    }
+    if (!more) break;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) c[j] = n[j];
+    pb = nb;
+  }
+}
+
+template <int G, bool PACK, bool MF = false>
 __global__ __launch_bounds__(64) void k_items_mixed(MixArgs a) {
   __shared__ float2 acc_lds[G][64];
   __shared__ float2 rowv[kMaxGroupRows];
@@ -612,7 +812,15 @@ __global__ __launch_bounds__(64) void k_items_mixed(MixArgs a) {
     } else {
       const int64_t m = g.split;
       if (a.parts & 2) seg_sum_mixed<K_PHE, PACK>(acc, a, item.lo, item.hi < m ? item.hi : m, lane, rowv, off);
-      if (a.parts & 4) seg_sum_mixed<K_PP, PACK>(acc, a, item.lo > m ? item.lo : m, item.hi, lane, rowv, off);
+      if (a.parts & 4) {
+        if constexpr (MF) {
+          const PpModel pm = a.ppm[g.inst];
+          seg_sum_mixed_pp_mf(acc, a, item.lo > m ? item.lo : m, item.hi, lane, rowv, off, pm,
+                              (uint32_t)g.row0 - off, a.hw + off);
+        } else {
+          seg_sum_mixed<K_PP, PACK>(acc, a, item.lo > m ? item.lo : m, item.hi, lane, rowv, off);
+        }
+      }
     }
   }
   __syncthreads();
@@ -626,13 +834,13 @@ __global__ __launch_bounds__(64) void k_items_mixed(MixArgs a) {
   }
 }
 
-template <bool PACK>
+template <bool PACK, bool MF = false>
 hipError_t launch_items_mixed_fmt(const MixArgs& a, int slots, hipStream_t s) {
   const int64_t nb = a.n_items;
   switch (slots) {
-    case 1: hipLaunchKernelGGL((k_items_mixed<1, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_items_mixed<8, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_items_mixed<16, PACK>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_items_mixed<1, PACK, MF>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_items_mixed<8, PACK, MF>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_items_mixed<16, PACK, MF>), dim3((unsigned)nb), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -645,6 +853,10 @@ hipError_t launch_items_mixed(const MixArgs& a, int slots, hipStream_t s) {
   if (a.wfmt == RTBTE_W_PACK8) {
     if (!a.info || a.pack_p < 1 || a.pack_p > 20 || a.pack_m != std::min(53 - 2 * a.pack_p, 23))
       return hipErrorInvalidValue;
+    if (a.ppm) {   // matrix-free ph-ph weights (per-item launch only)
+      if (a.blocks || !a.hw) return hipErrorInvalidValue;
+      return launch_items_mixed_fmt<true, true>(a, slots, s);
+    }
     if (a.blocks) {
       if (a.n_blocks == 0) return hipSuccess;
       if (!a.border || !a.tiles || !a.bnd) return hipErrorInvalidValue;
@@ -1511,11 +1723,6 @@ hipError_t launch_lincomb(double* out, const double* const* vecs, const double* 
 // prefactor * |M|^2 * delta(mismatch).  Positions come from ballots, so the
 // output order is the visiting order (emission before absorption for one
 // entry).
-__device__ __forceinline__ double gdelta(double x, double sigma) {
-  const double u = x / sigma;
-  return exp(-u * u) / (sigma * kSqrtPi);
-}
-
 struct Kept { bool em, ab; double wem, wab; int32_t o0; uint32_t o1; };
 
 // Destination row (instance-local) of a raw entry in the list being prepared.
@@ -1528,7 +1735,9 @@ __device__ __forceinline__ Kept classify(const PrepArgs& p, int64_t j) {
   const int64_t e = p.perm ? p.perm[j] : j;
   const int32_t r = p.row[e], a = p.i0[e], b = p.i1[e];
   const int32_t tag = (dest_of(p, e) % p.group_rows) << kTagShift;
-  const double v = p.val[e];
+  // no values (matrix-free ph-ph weights, recomputed at every right-hand
+  // side): stored weights are 0, so they set no mixed-precision block scale
+  const double v = p.val ? p.val[e] : 0.0;
   if (p.kind == 2) {  // ph-ph: row l, partners a, b
     const double w = p.hw[r], wa = p.hw[a], wb = p.hw[b];
     if (w < p.hw_cut || wa < p.hw_cut || wb < p.hw_cut) return k;

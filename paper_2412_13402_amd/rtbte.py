@@ -49,6 +49,13 @@ class Problem(ctypes.Structure):
     ]
 
 
+class PpModel(ctypes.Structure):
+    """rtbte_pp_model: the ph-ph matrix elements as a function of the triplet."""
+    _fields_ = [("dim", ctypes.c_int32), ("L", ctypes.c_int32), ("n_modes", ctypes.c_int32),
+                ("key0", ctypes.c_uint32), ("key1", ctypes.c_uint32), ("stream", ctypes.c_uint32),
+                ("ln_mu", ctypes.c_double), ("ln_sigma", ctypes.c_double)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int32), ("mixed_weights", ctypes.c_int32), ("device", ctypes.c_int32),
@@ -69,7 +76,7 @@ class Options(ctypes.Structure):
         ("fp64_check", ctypes.c_int32),
         ("small_nef", ctypes.c_int32),
         ("eta_fail_repeat", ctypes.c_double),
-        ("pp_fold", ctypes.c_int32), ("tiled", ctypes.c_int32),
+        ("pp_fold", ctypes.c_int32), ("tiled", ctypes.c_int32), ("pp_model", ctypes.c_void_p),
     ]
 
 
@@ -198,6 +205,9 @@ class Context:
             for k in ("n_el", "n_ph", "n_k_total", "n_q_total"):
                 setattr(p, k, int(P[k]))
             for k in ("eps", "hw", "eph_g2", "pp_v2"):
+                if k == "pp_v2" and P.get(k) is None:   # matrix-free ph-ph weights
+                    p.pp_v2 = None
+                    continue
                 a = np.ascontiguousarray(P[k], dtype=np.float64)
                 keep.append(a)
                 setattr(p, k, a.ctypes.data)
@@ -209,7 +219,20 @@ class Context:
             p.n_pp = len(P["pp_row"])
             for k in ("sigma_eph", "sigma_pp", "nsigma", "hw_cut"):
                 setattr(p, k, float(P[k]))
+        models = opt_kw.pop("pp_model", None)
         self.options = options if options is not None else default_options(**opt_kw)
+        if models is not None:
+            # one model per instance (a dict of rtbte_pp_model fields, or a list of them)
+            if isinstance(models, dict):
+                models = [models] * n
+            if len(models) != n:
+                raise ValueError("pp_model: one model per instance")
+            marr = (PpModel * n)()
+            for i, m in enumerate(models):
+                for k, v in m.items():
+                    setattr(marr[i], k, v)
+            keep.append(marr)
+            self.options.pp_model = ctypes.cast(marr, ctypes.c_void_p).value
         h = _vp()
         rc = L.rtbte_create(arr, n, ctypes.byref(self.options), ctypes.byref(h))
         if rc != OK:

@@ -137,6 +137,7 @@ def bose_einstein(hw, T):
 
 
 MASTER_SEED = 2412134020
+STREAM_PP = 0x70707033   # fourth Philox counter word of the |V3|^2 draws (gen.cpp)
 
 # Workload recipes.  Each recipe fixes the model, the problem parameters that
 # the method takes (sigma, n_sigma, hw_cut) and the initial state.
@@ -255,6 +256,16 @@ class Workload:
     @property
     def n_y(self) -> int:
         return self.n_el + self.n_ph
+
+    def pp_model(self) -> dict:
+        """How the generator drew |V3|^2 (the rtbte_pp_model fields): phonon
+        id = q * n_modes + nu over the L^dim grid, Philox4x32-10 keyed by the
+        seed's low and high words over the canonical sorted triplet ids and
+        the ph-ph stream word, Box-Muller normal, lognormal(v2_mu, v2_sig)."""
+        g, seed = self.grid, int(self.params["seed"])
+        return dict(dim=int(g["dim"]), L=int(g["L"]), n_modes=int(g["n_modes"]),
+                    key0=seed & 0xFFFFFFFF, key1=(seed >> 32) & 0xFFFFFFFF, stream=STREAM_PP,
+                    ln_mu=float(g["v2_mu"]), ln_sigma=float(g["v2_sig"]))
 
     def problem_arrays(self) -> dict:
         """The arrays and scalars the collision-integral problem is stated in."""

@@ -56,6 +56,26 @@ def test_fp64_rhs_full_size(full):
         assert rel_norm(g, ref) <= 1e-12
 
 
+def test_matrix_free_pp_full_size(full):
+    """Matrix-free ph-ph weights (the generator's |V3|^2 model evaluated at
+    every right-hand side; no stored values) at full size, FP64, every row."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    wl, o = full
+    ctx = P.Context(dict(wl.problem_arrays(), pp_v2=None), pp_model=wl.pp_model())
+    assert ctx.counts() == o.counts()
+    for nm, y in states(wl):
+        say(f"[fullsize] matrix-free ph-ph at {nm}")
+        out = torch.full((wl.n_y,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.rhs(to_dev(y), out, P.PART_ALL)
+        torch.cuda.synchronize()
+        g = out.cpu().numpy()
+        ref, S, A = o.rhs(y, scales=True)
+        worst = np.max(np.abs(g - ref) / np.maximum(A, 1e-300))
+        say(f"    worst row error / magnitude {worst:.2e}, normwise {rel_norm(g, ref):.2e}")
+        assert np.all(np.abs(g - ref) <= 1e-12 * A + 1e-300), f"{nm}: {worst:.3e}"
+
+
 def test_mixed_rhs_full_size(full):
     torch = torch_cuda()
     import paper_2412_13402_amd as P
