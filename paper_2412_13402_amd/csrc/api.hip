@@ -232,7 +232,7 @@ struct rtbte_ctx {
   Tile* tiles = nullptr;
   int64_t* bnd = nullptr;
   int64_t n_blocks = 0;
-  double tile_in_window = 0.0;    // fraction of channels whose other partner is staged
+  double tile_in_window = 0.0;    // fraction of tiles whose other partners are staged
 };
 
 static int fail(rtbte_ctx* c, int code, const char* fmt, ...) {
@@ -508,6 +508,7 @@ hipError_t build_tiles(rtbte_ctx* c, int64_t ich) {
   c->tblocks = nullptr; c->border = nullptr; c->tiles = nullptr; c->bnd = nullptr;
   c->n_items = c->n_blocks = 0;
   c->tiled = false;
+  c->tile_in_window = 0.0;
   // 1. segments and the offsets of their bounds
   struct SegH { int32_t group, kind, inst, n_kb; int64_t lo, hi, off; };
   std::vector<SegH> sh;
@@ -591,10 +592,15 @@ hipError_t build_tiles(rtbte_ctx* c, int64_t ich) {
     if (jobs_d) (void)hipFree(jobs_d);
     if (span_d) (void)hipFree(span_d);
     if (e != hipSuccess) return e;
+    // a tile whose other partners do not fit the window stages none of them
+    // (its gathers of the other partner all go to global memory)
     for (size_t k = 0; k < jobs.size(); ++k) {
       const uint32_t mn = span[2 * k], mx = span[2 * k + 1];
-      tiles[(size_t)job_tile[k]] = Tile{mn, (uint32_t)std::min<int64_t>((int64_t)mx - mn + 1, OC)};
+      const int64_t len = (int64_t)mx - mn + 1;
+      tiles[(size_t)job_tile[k]] = len <= OC ? Tile{mn, (uint32_t)len} : Tile{mn, 0u};
+      c->tile_in_window += len <= OC ? 1.0 : 0.0;
     }
+    c->tile_in_window /= (double)jobs.size();
   }
   // 5. blocks: each set through ranges of key blocks of about kTileWaves * ich channels
   struct ItemH { int32_t group; int64_t lo, hi; int32_t block, wave; };

@@ -929,24 +929,27 @@ __device__ __forceinline__ void stage(T* dst, const T* __restrict__ z, int64_t s
 }
 
 // The staged windows of one key block: key positions [klo, klo + klen),
-// other-partner positions [olo, olo + olen).
+// other-partner positions [olo, olo + olen) (olen = 0: none staged).
 template <typename T>
 struct Windows {
   const T* key;
   const T* oth;
   uint32_t klo, klen, olo, olen;
   // Populations of a channel whose (masked-in) partner words are lo, hi:
-  // the key from LDS; the other from LDS, or `glob` outside its window.
+  // the key from LDS; the other from LDS, or from `glob` in a tile without
+  // an other-partner window.
   template <int KIND>
   __device__ __forceinline__ void get(uint32_t lo, uint32_t hi, uint32_t pmask, bool valid,
                                       const T* __restrict__ glob, T& g0, T& g1) const {
     const uint32_t kp = (KIND == K_EPH ? hi : lo) & pmask;
     const uint32_t op = (KIND == K_EPH ? lo : hi) & pmask;
     const uint32_t ku = valid ? min(kp - klo, klen - 1u) : 0u;
-    const uint32_t ou = op - olo;
     const T gk = key[ku];
+    // olen == 0: the tile's other partners span more than the window holds
+    // and are all gathered from global memory (a choice made per tile, so
+    // the branch is the same for every lane)
     T go;
-    if (!valid || ou < olen) go = oth[valid ? ou : 0u];
+    if (olen) go = oth[valid ? min(op - olo, olen - 1u) : 0u];
     else go = glob[op];
     if (KIND == K_EPH) { g0 = go; g1 = gk; }
     else { g0 = gk; g1 = go; }
