@@ -74,6 +74,81 @@ def measured_traffic(workload, precision):
     return e.get("hbm_bytes_per_launch")
 
 
+TRAFFIC_LEGS = (("fp64", "k_items", ("roofline",)),
+                ("fp64_plain", "k_items", ("fp64_plain_channels", "roofline")),
+                ("mixed", "k_items_mixed", ("mixed", "roofline")))
+
+
+def _counter_means(path, counter):
+    """Per-kernel mean of one rocprofv3 counter (KiB per dispatch) and the
+    largest reading of a copy kernel, from a `--pmc` run's CSV output."""
+    import csv
+    import glob
+    acc, copy = {}, 0.0
+    for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                name, v = row["Kernel_Name"], float(row["Counter_Value"])
+                if "copyBuffer" in name:
+                    copy = max(copy, v)
+                acc.setdefault(name.split("(")[0], []).append(v)
+    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}, copy
+
+
+def _template_args(name):
+    return [a.strip() for a in name[name.index("<") + 1:name.rindex(">")].split(",")]
+
+
+def traffic_summary(fetch_dir, write_dir, bench_json, workload):
+    """Write profiles/traffic_<workload>.json from two rocprofv3 `--pmc` runs
+    of this benchmark with `--calibrate-copy` (FETCH_SIZE, then WRITE_SIZE)
+    and the JSON line the first run printed: HBM bytes per launch of each
+    collision kernel, each counter scaled by what it reads for the 1 GiB
+    device-to-device copy, beside the algorithmic bytes per launch."""
+    fetch, fcopy = _counter_means(fetch_dir, "FETCH_SIZE")
+    write, wcopy = _counter_means(write_dir, "WRITE_SIZE")
+    with open(bench_json) as f:
+        rec = json.loads(f.read().strip().splitlines()[-1])
+    gib = float(1 << 30)
+    fs, ws = gib / (fcopy * 1024), gib / (wcopy * 1024)
+    legs = ("--steps 2 --warmup 1 --no-cpu-baseline --no-errors --no-batched --no-toy --no-si3d --no-horizon "
+            "--no-matrix-free --calibrate-copy")
+    out = {"workload": rec["config"]["workload"],
+           "commands": [f"cd /tmp && rocprofv3 --pmc {c} -d <out>/{d} -o bench --output-format csv -- "
+                        f"python3 <repo>/bench.py {legs} > <out>/{d}.json" for c, d in
+                        (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))] +
+                       ["python3 <repo>/bench.py --traffic-summary <out>/fetch <out>/write <out>/fetch.json"],
+           "copy_reference": {"bytes_read": gib, "bytes_written": gib, "fetch_kib_raw": fcopy,
+                              "write_kib_raw": wcopy},
+           "fetch_scale": fs, "write_scale": ws}
+    for leg, base, keys in TRAFFIC_LEGS:
+        r = rec
+        for k in keys:
+            r = r.get(k) if r else None
+        if not r:
+            continue
+        pack = leg != "fp64_plain"
+        pick = [n for n in fetch if n.split("<")[0].endswith("::" + base)
+                and _template_args(n)[1] == ("true" if pack else "false")
+                and all(a == "false" for a in _template_args(n)[2:])]
+        if len(pick) != 1 or pick[0] not in write:
+            continue
+        n = pick[0]
+        hbm = (fetch[n][1] * fs + write[n][1] * ws) * 1024
+        out[leg] = {"kernel": n, "kernel_source_hash": kernel_source_hash(), "dispatches": fetch[n][0],
+                    "fetch_kib_per_dispatch_raw": fetch[n][1], "write_kib_per_dispatch_raw": write[n][1],
+                    "hbm_bytes_per_launch": hbm,
+                    "algorithmic_bytes_per_launch": r["algorithmic_bytes_per_launch"],
+                    "ratio": hbm / r["algorithmic_bytes_per_launch"]}
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps({k: v.get("ratio") for k, v in out.items() if isinstance(v, dict) and "ratio" in v}))
+
+
 def fp64_dtype(ctx):
     """The arithmetic type of the FP64 path, with the storage rounding of its
     channel weights named when the layout rounds them."""
@@ -173,7 +248,13 @@ def main():
                     help="0 (default): per-item collision kernels; 1: tiled (partners staged in LDS)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size reference for HBM counters)")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
+                    help="no run: write profiles/traffic_<workload>.json from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this benchmark with --calibrate-copy")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, args.workload if args.L is None else f"{args.workload}_L{args.L}")
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU row sharding is a design, not a build)", file=sys.stderr)
