@@ -80,11 +80,13 @@ TRAFFIC_LEGS = (("fp64", "k_items", ("roofline",)),
 
 
 def _counter_means(path, counter):
-    """Per-kernel mean of one rocprofv3 counter (KiB per dispatch) and the
-    largest reading of a copy kernel, from a `--pmc` run's CSV output."""
+    """Per-kernel mean of one rocprofv3 counter (KiB per dispatch), and its
+    reading for the run's first copy kernel (the 1 GiB device-to-device copy
+    of --calibrate-copy, the first copy the benchmark makes), from a `--pmc`
+    run's CSV output."""
     import csv
     import glob
-    acc, copy = {}, 0.0
+    acc, copy = {}, (None, 0.0)
     for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
         with open(f) as fh:
             for row in csv.DictReader(fh):
@@ -92,9 +94,11 @@ def _counter_means(path, counter):
                     continue
                 name, v = row["Kernel_Name"], float(row["Counter_Value"])
                 if "copyBuffer" in name:
-                    copy = max(copy, v)
+                    d = int(row["Dispatch_Id"])
+                    if copy[0] is None or d < copy[0]:
+                        copy = (d, v)
                 acc.setdefault(name.split("(")[0], []).append(v)
-    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}, copy
+    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}, copy[1]
 
 
 def _template_args(name):
@@ -802,10 +806,13 @@ def batched_leg(P, torch, np, args):
     wall_m = time.perf_counter() - w0
     steps_m = sum(ctx.stats(i)["n_accept"] + ctx.stats(i)["n_reject"] for i in range(n))
     ym = y.cpu().numpy()
-    # the batched collision kernel alone, HIP-event timed
+    # the batched collision kernel alone, HIP-event timed (after two
+    # untimed launches)
     out = torch.empty_like(y)
+    for _ in range(2):
+        ctx.rhs(y, out, P.PART_ALL)
     ctx.profile(True)
-    for _ in range(5):
+    for _ in range(20):
         ctx.rhs(y, out, P.PART_ALL)
     k_ms, k_n, k_bytes = ctx.profile_read()
     ctx.profile(False)
