@@ -14,7 +14,9 @@ Prints one JSON line:
   twice, is value_summed_channels);
 * roofline: the collision kernel's algorithmic bytes per launch over its
   HIP-event-timed duration, against the 8 TB/s HBM peak;
-* cpu_baseline: the FP64 oracle on this host's cores, same basis;
+* cpu_baseline: the FP64 oracle on this host's cores, same basis (and the
+  simulated ps/s it would reach on the horizon run, extrapolated from its
+  right-hand-side time);
 * horizon: simulated ps per second from the initial state to 1 ps, FP64 and
   mixed, printed and ARKODE PID forms, each with its end-time error against
   an FP64 reference at rtol 1e-9 (the top-level sim_ps_per_s is the FP64
@@ -24,7 +26,8 @@ Prints one JSON line:
   step against the oracle, populations after 1 ps of RK4 against FP64);
 * batched: 64 graphene-like instances in one autotuned, graph-replayed mixed
   context against the same instances one by one in FP64, with errors against
-  an FP64 reference and the mixed-vs-FP64 population error on fixed steps;
+  an FP64 reference, the mixed-vs-FP64 population error on fixed steps, and
+  the oracle's right-hand side on a sample of the instances;
 * si3d: the silicon-like 40^3 workload, MIS against the adaptive ERK, slow
   and fast right-hand-side rooflines, the oracle on a row sample;
 * toy: the small e-ph-only RK4 case beside the oracle.
@@ -409,6 +412,14 @@ def main():
                                     f"{args.horizon_fs:g} fs, end-time error vs an FP64 run at rtol "
                                     f"{args.ref_rtol:g}: carriers {hz['fp64']['err_carriers']:.2e}, phonons "
                                     f"{hz['fp64']['err_phonons']:.2e} (horizon)")
+        if "cpu_baseline" in rec:
+            # the oracle on the same run, extrapolated from its right-hand-side time
+            s_rhs = CS / rec["cpu_baseline"]["value"]
+            n_rhs = 5 * (hz["fp64"]["accepted"] + hz["fp64"]["rejected"])
+            rec["cpu_baseline"]["sim_ps_per_s_extrapolated"] = args.horizon_fs * 1e-3 / (n_rhs * s_rhs)
+            rec["cpu_baseline"]["sim_ps_per_s_note"] = (
+                f"extrapolated, not run: the FP64 run to {args.horizon_fs:g} fs takes {n_rhs} right-hand sides "
+                f"(5 per attempt), at the oracle's {s_rhs:.3f} s each")
     del ctx, ctx_m, o, leg
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -880,6 +891,10 @@ def batched_leg(P, torch, np, args):
         f"max |y - y_ref| at {args.batch_t_end:g} fs: batched mixed {max(err_m):.2e}, plain FP64 {max(err_f):.2e}; "
         f"mixed vs FP64 after {args.batch_rk4_fs:g} fs of RK4: {max(err_rk4):.2e}")
     inst_ps = n * args.batch_t_end * 1e-3
+    res_cpu = None
+    if not args.no_cpu_baseline:
+        res_cpu = batched_cpu_baseline(np, ws)
+        res_cpu["gpu_batched_kernel_channels_per_s"] = C / (kms * 1e-3)
     return {
         "workload": f"{n} graphene-like instances, sides uniform in 24..72, T_el uniform in 500..3000 K, "
                     f"adaptive Zonneveld ERK rtol {args.rtol:g}, each from its initial state to "
@@ -908,7 +923,32 @@ def batched_leg(P, torch, np, args):
                                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                                           "avg_launch_ms": kms, "algorithmic_bytes_per_launch": k_bytes / max(k_n, 1)},
         "generate_s": gen_s, "create_s": create_s,
+        "cpu_baseline": res_cpu,
     }
+
+
+def batched_cpu_baseline(np, ws, every=8, reps=3):
+    """The FP64 oracle's right-hand side on a sample of the batch (every
+    `every`-th instance, each at its initial state, `reps` evaluations after
+    its lists are built), in summed channels per second."""
+    from __graft_entry__ import _ensure_built
+    _ensure_built(need_oracle=True)
+    import oracle
+    sample = ws[::every]
+    ch, el = 0, 0.0
+    for w in sample:
+        o = oracle.Oracle(w.problem_arrays())
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = o.rhs(w.y0)
+        el += time.perf_counter() - t0
+        assert np.all(np.isfinite(r))
+        ch += reps * sum(o.counts())
+        del o
+    return {"value": ch / el, "unit": "channels/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{len(sample)} of the {len(ws)} instances (every {every}th; sides "
+                      f"{', '.join(str(w.grid['L']) for w in sample)}), {reps} right-hand sides each at the "
+                      f"initial state ({el:.2f} s; list builds untimed); summed channels"}
 
 
 def timed_steps(ctx, wl, args, C, label, start=None):
