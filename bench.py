@@ -108,7 +108,7 @@ def _template_args(name):
     return [a.strip() for a in name[name.index("<") + 1:name.rindex(">")].split(",")]
 
 
-def traffic_summary(fetch_dir, write_dir, bench_json, workload):
+def traffic_summary(fetch_dir, write_dir, bench_json, workload, out_path=None):
     """Write profiles/traffic_<workload>.json from two rocprofv3 `--pmc` runs
     of this benchmark with `--calibrate-copy` (FETCH_SIZE, then WRITE_SIZE)
     and the JSON line the first run printed: HBM bytes per launch of each
@@ -149,7 +149,7 @@ def traffic_summary(fetch_dir, write_dir, bench_json, workload):
                     "hbm_bytes_per_launch": hbm,
                     "algorithmic_bytes_per_launch": r["algorithmic_bytes_per_launch"],
                     "ratio": hbm / r["algorithmic_bytes_per_launch"]}
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    path = out_path or os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
