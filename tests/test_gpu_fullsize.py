@@ -9,6 +9,8 @@ Mixed (default weight format): the a priori bound of the mixed tests and a
 normwise relative error <= 1e-4; populations after 1 ps of RK4 (h = 4 fs, the
 same steps in both precisions) within 1e-6 of the FP64 path (parity unpinned:
 measured against the FP64 GPU path, itself checked against the oracle here).
+The benchmark's batch of 64 graphene-like instances is checked the same way
+in mixed precision, every row of every instance.
 """
 import numpy as np
 import pytest
@@ -147,3 +149,42 @@ def test_observables_full_size(full):
     assert np.allclose(T, obs.mode_temperature(wl.hw, y[ne:], modes, nm), rtol=1e-9, atol=0)
     T300 = ctx.mode_temperatures(to_dev(wl.y0), modes, nm)
     assert np.allclose(T300, 300.0, rtol=1e-9, atol=0)
+
+
+def test_batch64_mixed_rhs_full_size():
+    """The benchmark's batch at full size (64 graphene-like instances, sides
+    24..72, 1.8e9 channels) in mixed precision, in the launch shape the
+    autotuner chose for the committed benchmark line (4-row electron groups,
+    16-row phonon groups, 37337 channels per item): every row of every
+    instance within the mixed a priori bound of the FP64 oracle, and the
+    normwise error of each instance within 1e-4."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    say("[fullsize] generating the batch of 64")
+    ws = synth.build_batch(64)
+    ctx = P.Context([w.problem_arrays() for w in ws], precision=P.rtbte.MIXED, group_rows_el=4,
+                    group_rows_ph=16, item_channels=37337)
+    rng = np.random.default_rng(21)
+    y = np.concatenate([np.concatenate([rng.uniform(0.0, 1.0, w.n_el), rng.uniform(0.0, 4.0, w.n_ph)])
+                        for w in ws])
+    out = torch.full((len(y),), float("nan"), dtype=torch.float64, device="cuda")
+    say("[fullsize] batch of 64: mixed rhs")
+    ctx.rhs(to_dev(y), out, P.PART_ALL)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    uw = weight_u(ctx)
+    worst = 0.0
+    for i, w in enumerate(ws):
+        off, ne, nph = ctx.layout(i)
+        sl = slice(off, off + ne + nph)
+        o = oracle.Oracle(w.problem_arrays())
+        ref, S, A, M, Q = o.rhs(y[sl], scales=True, unweighted=True)
+        bound = (uw + 24 * U32) * A + U_SUB * o.max_weight() * M
+        assert np.all(np.abs(g[sl] - ref) <= bound + 1e-300), \
+            f"instance {i}: worst {np.max(np.abs(g[sl] - ref) / np.maximum(A, 1e-300)):.3e}"
+        err = rel_norm(g[sl], ref)
+        assert err <= 1e-4, (i, err)
+        worst = max(worst, err)
+        del o
+        if i % 16 == 15:
+            say(f"[fullsize] batch of 64: {i + 1} instances checked, worst normwise {worst:.2e}")
