@@ -196,8 +196,11 @@ typedef struct {
   int32_t tune;             /* 1: autotune the launch shape at create: for up to four row-group
                                layouts (the given or default one; 4 and 16 electron rows; 8
                                phonon rows) and three item sizes each (the given or default
-                               one, half, double), time full right-hand sides and keep the
-                               fastest.  Any shape gives the same results to rounding order.
+                               one, half, double), time 20 full right-hand sides each and
+                               keep the fastest; a shape tried later replaces the one kept
+                               only when it is more than 2 % faster (the timing noise), so the
+                               given or default shape stays unless another clearly beats it.
+                               Any shape gives the same results to rounding order.
                                Costs up to four layout builds; a cache hit costs one.        */
   const char *tune_cache;   /* text file of tuned shapes, one line per problem signature
                                (device, precision, sizes); read before tuning, appended

@@ -2183,8 +2183,12 @@ int time_rhs(rtbte_ctx* c, const double* y, double* ydot, int reps, double* ms) 
 
 // Coordinate search over launch shapes: rows per group (each candidate is a
 // full channel layout) and, for each layout, channels per work item (only the
-// item table is rebuilt).  The fastest context is kept; the shape goes to the
-// cache file.
+// item table is rebuilt).  The fastest context is kept, a later candidate
+// replacing the one kept only when it is faster by more than kTuneMargin
+// (the spread of repeated timings), so that the choice does not flip between
+// runs on noise; the shape goes to the cache file.
+constexpr double kTuneMargin = 0.02;
+constexpr int kTuneReps = 20;
 int tune_create(const rtbte_problem* P, int n, rtbte_options o, rtbte_ctx** out) {
   const char* path = o.tune_cache ? o.tune_cache : getenv("RTBTE_TUNE_CACHE");
   if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, RTBTE_E_HIP, "hipSetDevice failed");
@@ -2246,18 +2250,18 @@ int tune_create(const rtbte_problem* P, int n, rtbte_options o, rtbte_ctx** out)
         break;
       }
       double ms = 0.0;
-      rc = time_rhs(c, y, yd, 5, &ms);
+      rc = time_rhs(c, y, yd, kTuneReps, &ms);
       if (rc != RTBTE_OK) {
         g_create_error = c->err;
         break;
       }
-      if (ms < c_best) { c_best = ms; c_ich = ic; }
+      if (ms < c_best * (1.0 - kTuneMargin)) { c_best = ms; c_ich = ic; }
     }
     if (rc != RTBTE_OK) {
       rtbte_destroy(c);
       break;
     }
-    if (c_best < best_ms) {
+    if (c_best < best_ms * (1.0 - kTuneMargin)) {
       if (c->item_channels != c_ich && rebuild_items(c, c_ich) != hipSuccess) {
         rtbte_destroy(c);
         rc = fail(nullptr, RTBTE_E_NOMEM, "tuning: work items");
