@@ -258,7 +258,13 @@ def main():
     ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "BENCH_JSON"),
                     help="no run: write profiles/traffic_<workload>.json from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of this benchmark with --calibrate-copy")
+    ap.add_argument("--valu-summary", nargs=2, metavar=("PMC_DIR", "BENCH_JSON"),
+                    help="no run: write profiles/valu_matrix_free_<workload>.json from a rocprofv3 --pmc "
+                         "SQ_INSTS_VALU run of this benchmark (" + MF_VALU_LEGS + ")")
     args = ap.parse_args()
+    if args.valu_summary:
+        valu_summary(*args.valu_summary, args.workload if args.L is None else f"{args.workload}_L{args.L}")
+        return
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary, args.workload if args.L is None else f"{args.workload}_L{args.L}")
         return
@@ -436,11 +442,59 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-# VALU lane-instructions per ph-ph channel of the matrix-free FP64 kernel
-# (rocprofv3 SQ_INSTS_VALU x 64 over the ph-ph channels of one launch,
-# graphene-like workload: profiles/k_items_matrix_free_graphene2d.md)
-MF_VALU_PER_CHANNEL = 544
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock
+MF_VALU_LEGS = "--no-batched --no-si3d --no-horizon --no-toy --no-cpu-baseline --no-errors --no-plain --no-mixed " \
+               "--steps 2 --warmup 1"
+
+
+def valu_summary(pmc_dir, bench_json, workload, out_path=None):
+    """Write profiles/valu_matrix_free_<workload>.json from a rocprofv3
+    `--pmc SQ_INSTS_VALU` run of this benchmark (MF_VALU_LEGS) and the JSON
+    line it printed: VALU lane-instructions per stored ph-ph channel of the
+    matrix-free FP64 collision kernel, from its ph-ph-only launches (the
+    dispatches with the fewest instructions; the whole-RHS launches also
+    carry the e-ph and ph-e work)."""
+    import csv
+    import glob
+    vals = []
+    name = None
+    for f in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                n = row["Kernel_Name"].split("(")[0]
+                if row["Counter_Name"] != "SQ_INSTS_VALU" or not n.split("<")[0].endswith("::k_items"):
+                    continue
+                if _template_args(n)[1:] == ["true", "false", "true"]:   # packed FP64, matrix-free
+                    vals.append(float(row["Counter_Value"]))
+                    name = n
+    with open(bench_json) as f:
+        rec = json.loads(f.read().strip().splitlines()[-1])
+    stored_pp = rec["config"]["stored_channels"][2]
+    v = min(vals)
+    out = {"workload": rec["config"]["workload"],
+           "commands": [f"cd /tmp && rocprofv3 --pmc SQ_INSTS_VALU -d <out>/valu -o valu --output-format csv -- "
+                        f"python3 <repo>/bench.py {MF_VALU_LEGS} > <out>/valu.json",
+                        "python3 <repo>/bench.py --valu-summary <out>/valu <out>/valu.json"],
+           "kernel": name, "kernel_source_hash": kernel_source_hash(), "dispatches": len(vals),
+           "valu_wave_instructions_phph_launch": v, "stored_phph_channels": stored_pp,
+           "lane_instructions_per_channel": v * 64 / stored_pp}
+    path = out_path or os.path.join(ROOT, "profiles", f"valu_matrix_free_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps({"lane_instructions_per_channel": out["lane_instructions_per_channel"]}))
+
+
+def measured_mf_valu(workload):
+    """VALU lane-instructions per ph-ph channel of the matrix-free kernel from
+    the committed counter summary, if it was taken on the current kernel
+    source; else None."""
+    path = os.path.join(ROOT, "profiles", f"valu_matrix_free_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    return d["lane_instructions_per_channel"] if d.get("kernel_source_hash") == kernel_source_hash() else None
 
 
 def matrix_free_leg(P, torch, np, wl, args, ctx64, o):
@@ -469,11 +523,13 @@ def matrix_free_leg(P, torch, np, wl, args, ctx64, o):
             ref = kernel_roofline(ctx64, torch, y, P.PART_PHPH)
             leg["stored_weights_phph_ms"] = ref["avg_launch_ms"]
             leg["slowdown_vs_stored"] = leg["phph_ms"] / ref["avg_launch_ms"]
-            if MF_VALU_PER_CHANNEL:
-                ach = MF_VALU_PER_CHANNEL * stored[2] / (leg["phph_ms"] * 1e-3)
+            ipc = measured_mf_valu(args.workload if args.L is None else f"{args.workload}_L{args.L}")
+            leg["roofline"] = None
+            if ipc:
+                ach = ipc * stored[2] / (leg["phph_ms"] * 1e-3)
                 leg["roofline"] = {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
                                    "unit": "T VALU lane-instructions/s", "frac": ach / VALU_PEAK_LANE_OPS,
-                                   "instructions_per_channel": MF_VALU_PER_CHANNEL}
+                                   "instructions_per_channel": ipc}
             if o is not None:
                 out = torch.empty_like(y)
                 c.rhs(y, out, P.PART_ALL)
@@ -646,6 +702,7 @@ def achievable_bandwidth(torch, gib=4):
 
 def kernel_roofline(ctx, torch, y, parts, reps=3):
     out = torch.empty_like(y)
+    ctx.rhs(y, out, parts)      # untimed
     ctx.profile(True)
     for _ in range(reps):
         ctx.rhs(y, out, parts)

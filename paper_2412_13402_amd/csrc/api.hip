@@ -1117,8 +1117,11 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
       q.n_el = (uint32_t)problems[i].n_el;
       q.ln_mu = m.ln_mu;
       q.ln_sigma = m.ln_sigma;
-      q.pre = (36.0 * kPi / kHbarEvFs) / (double)problems[i].n_q_total;
-      q.sigma = problems[i].sigma_pp;
+      const double pre = (36.0 * kPi / kHbarEvFs) / (double)problems[i].n_q_total;
+      q.pre_norm = pre / (problems[i].sigma_pp * kSqrtPi);
+      q.rcp_sigma = 1.0 / problems[i].sigma_pp;
+      q.rcp_modes = 1.0 / (double)m.n_modes;
+      q.rcp_L = 1.0 / (double)m.L;
     }
     e = upload(&c->ppm, pm.data(), pm.size());
   }

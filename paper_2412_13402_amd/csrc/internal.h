@@ -111,12 +111,14 @@ struct Tile {
 };
 
 // Matrix-free ph-ph weights of one instance: the rtbte_pp_model, the
-// instance's ph-ph prefactor and width, whether its emission pairs are
-// folded, and where its phonons start.
+// instance's ph-ph prefactor over the delta's normalisation sigma sqrt(pi),
+// the reciprocal width, whether its emission pairs are folded, where its
+// phonons start, and FP64 reciprocals of the branch count and grid side
+// (the kernel divides phonon ids by them).
 struct PpModel {
   int32_t dim, L, n_modes, folded;
   uint32_t key0, key1, stream, n_el;
-  double ln_mu, ln_sigma, pre, sigma;
+  double ln_mu, ln_sigma, pre_norm, rcp_sigma, rcp_modes, rcp_L;
 };
 
 // Arguments of the collision kernel (per-item row sums).

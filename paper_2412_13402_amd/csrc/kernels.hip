@@ -242,17 +242,31 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
+// n / d for n < 2^31 and d >= 1 from the FP64 reciprocal rd = 1/d: the
+// truncated product is exact or, when n is a multiple of d, one short (its
+// relative error is below 2^-51, so it can never reach the next integer),
+// and one correction step makes it exact.
+__device__ __forceinline__ uint32_t div_rcp(uint32_t n, uint32_t d, double rd) {
+  uint32_t q = (uint32_t)((double)n * rd);
+  if (n - q * d >= d) ++q;
+  return q;
+}
+
+// -i mod L for 0 <= i < L
+__device__ __forceinline__ uint32_t neg_mod(uint32_t i, uint32_t L) { return i ? L - i : 0u; }
+
 // Time-reversed phonon state: -q on the periodic grid, the same branch.
 __device__ __forceinline__ uint32_t reversed_phonon(uint32_t id, const PpModel& m) {
   const uint32_t nm = (uint32_t)m.n_modes, L = (uint32_t)m.L;
-  const uint32_t q = id / nm, nu = id - q * nm;
+  const uint32_t q = div_rcp(id, nm, m.rcp_modes), nu = id - q * nm;
   uint32_t nq;
   if (m.dim == 2) {
-    const uint32_t i = q / L, j = q - i * L;
-    nq = ((L - i) % L) * L + (L - j) % L;
+    const uint32_t i = div_rcp(q, L, m.rcp_L), j = q - i * L;
+    nq = neg_mod(i, L) * L + neg_mod(j, L);
   } else {
-    const uint32_t i = q / (L * L), r = q - i * L * L, j = r / L, k = r - j * L;
-    nq = (((L - i) % L) * L + (L - j) % L) * L + (L - k) % L;
+    const uint32_t t = div_rcp(q, L, m.rcp_L), k = q - t * L;   // t = i L + j
+    const uint32_t i = div_rcp(t, L, m.rcp_L), j = t - i * L;
+    nq = (neg_mod(i, L) * L + neg_mod(j, L)) * L + neg_mod(k, L);
   }
   return nq * nm + nu;
 }
@@ -264,8 +278,9 @@ __device__ __forceinline__ void sort3(uint32_t& a, uint32_t& b, uint32_t& c) {
   if (a > b) { t = a; a = b; b = t; }
 }
 
-// |V3|^2 of the triplet (phonon ids l, a, b) under the model (rtbte_pp_model).
-__device__ __forceinline__ double model_v2(const PpModel& m, uint32_t l, uint32_t a, uint32_t b) {
+// ln |V3|^2 of the triplet (phonon ids l, a, b) under the model
+// (rtbte_pp_model): ln_mu + ln_sigma * (Box-Muller normal of the Philox draw).
+__device__ __forceinline__ double model_ln_v2(const PpModel& m, uint32_t l, uint32_t a, uint32_t b) {
   uint32_t x0 = l, x1 = a, x2 = b;
   uint32_t y0 = reversed_phonon(l, m), y1 = reversed_phonon(a, m), y2 = reversed_phonon(b, m);
   sort3(x0, x1, x2);
@@ -274,19 +289,21 @@ __device__ __forceinline__ double model_v2(const PpModel& m, uint32_t l, uint32_
   const uint4 r = philox10(rev ? make_uint4(y0, y1, y2, m.stream) : make_uint4(x0, x1, x2, m.stream), m.key0, m.key1);
   const double u1 = ((double)r.y + 0.5) * 0x1p-32, u2 = ((double)r.z + 0.5) * 0x1p-32;
   const double n = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
-  return exp(m.ln_mu + m.ln_sigma * n);
+  return m.ln_mu + m.ln_sigma * n;
 }
 
 // Weight of a ph-ph channel of row l (emission: prefactor, twice for a folded
 // pair; absorption: twice the prefactor) times |V3|^2 times the delta of its
-// energy mismatch.  Positions are relative to the instance.
+// energy mismatch x: |V3|^2 delta(x) = exp(ln |V3|^2 - (x / sigma)^2) /
+// (sigma sqrt(pi)), one exponential.  Positions are relative to the instance.
 __device__ __forceinline__ double mf_weight(const PpModel& m, bool em, uint32_t pl, uint32_t pa, uint32_t pb,
                                             const double* __restrict__ hwi) {
   const double wl = hwi[pl], wa = hwi[pa], wb = hwi[pb];
   const uint32_t l = pl - m.n_el, a = pa - m.n_el, b = pb - m.n_el;
-  const double v = model_v2(m, l, a, b);
-  if (em) return ((m.folded && a < b) ? 2.0 : 1.0) * m.pre * v * gdelta(-wl + wa + wb, m.sigma);
-  return (2.0 * m.pre) * v * gdelta(wl - wa + wb, m.sigma);
+  const double lv = model_ln_v2(m, l, a, b);
+  const double u = (em ? -wl + wa + wb : wl - wa + wb) * m.rcp_sigma;
+  const double f = em ? ((m.folded && a < b) ? 2.0 : 1.0) : 2.0;
+  return f * m.pre_norm * exp(lv - u * u);
 }
 
 // Packed FP64 ph-ph channels [s, e) with matrix-free weights: only the

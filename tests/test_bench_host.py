@@ -69,3 +69,24 @@ def test_traffic_summary(counter_runs, capsys):
     assert d["fp64_plain"]["ratio"] == pytest.approx((4.0e6 * 2 + 5000.0) * 1024 / 8.0e9)
     assert d["mixed"]["ratio"] == pytest.approx((2.0e6 * 2 + 5000.0) * 1024 / 4.0e9)
     assert all("rocprofv3 --pmc" in c for c in d["commands"][:2])
+
+
+def test_valu_summary(tmp_path):
+    """The ph-ph-only launches (fewest instructions) of the matrix-free FP64
+    kernel give the instructions per stored ph-ph channel."""
+    import bench
+    mf = "void rtbte::k_items<16, true, false, true>(rtbte::RowArgs)"
+    mf_mixed = "void rtbte::k_items_mixed<16, true, true>(rtbte::MixArgs)"
+    stored = "void rtbte::k_items<16, true, false, false>(rtbte::RowArgs)"
+    rows = [(1, stored, 3.6e8), (2, mf, 2.0e9), (3, mf, 2.0e9), (4, mf, 2.3e9), (5, mf, 2.3e9),
+            (6, mf_mixed, 1.0e9)]
+    _counter_csv(str(tmp_path / "valu" / "host"), "SQ_INSTS_VALU", rows)
+    rec = {"config": {"workload": "unit", "stored_channels": [10, 20, 3.2e8]}}
+    with open(tmp_path / "valu.json", "w") as f:
+        f.write(json.dumps(rec) + "\n")
+    out = tmp_path / "valu_out.json"
+    bench.valu_summary(str(tmp_path / "valu"), str(tmp_path / "valu.json"), "unit", out_path=str(out))
+    d = json.loads(out.read_text())
+    assert d["dispatches"] == 4 and d["kernel"] == "void rtbte::k_items<16, true, false, true>"
+    assert d["lane_instructions_per_channel"] == pytest.approx(2.0e9 * 64 / 3.2e8)
+    assert d["kernel_source_hash"] == bench.kernel_source_hash()
