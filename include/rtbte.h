@@ -377,7 +377,13 @@ int rtbte_step_adaptive(rtbte_ctx *ctx, double *y, double *t, double *h, double 
                         int32_t one_step, void *stream);
 
 /* Fixed-step classical RK4 on the full RHS (the prior-work baseline):
- * n_steps steps of size h_step from *t (device t, one entry per instance). */
+ * n_steps steps of size h_step from *t (device t, one entry per instance).
+ * A step whose result is not finite, or whose root mean square overflows,
+ * is not taken, and the call returns RTBTE_E_NONFINITE with y and t at the
+ * last state reached; fixed fast steps inside the multirate and splitting
+ * steps are checked the same way.  A step too long for the fastest
+ * scattering rates (the paper's failure mode of fixed steps) can also blow
+ * the populations up to large finite values, which are returned as they are. */
 int rtbte_step_rk4(rtbte_ctx *ctx, double *y, double *t, double h_step, int64_t n_steps,
                    void *stream);
 

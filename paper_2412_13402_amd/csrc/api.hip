@@ -1561,7 +1561,16 @@ int enqueue_step(rtbte_ctx* c, double* y, int parts, const double* forcing, Inst
     f.lte = c->lte;
     HIPCHK(c, rhs_launch(c, z, parts, st, f, true, s));
   }
-  if (tb.embedded) HIPCHK(c, launch_wrms(c->lte, y, c->info_d, st, c->partial, c->n_inst, c->nchunk, ctl, s));
+  if (tb.embedded) {
+    HIPCHK(c, launch_wrms(c->lte, y, c->info_d, st, c->partial, c->n_inst, c->nchunk, ctl, s));
+  } else {
+    // fixed steps: the RMS of the candidate state, so that a step that
+    // diverges (a non-finite or overflowing state) is caught and not committed
+    Ctl rms = ctl;
+    rms.rtol = 0.0;
+    rms.atol_el = rms.atol_ph = 1.0;
+    HIPCHK(c, launch_wrms(c->ynew, y, c->info_d, st, c->partial, c->n_inst, c->nchunk, rms, s));
+  }
   HIPCHK(c, launch_control(st, c->partial, c->info_d, c->n_inst, c->nchunk, ctl, s));
   HIPCHK(c, launch_commit(y, c->ynew, c->row_inst, st, c->ny, s));
   return RTBTE_OK;

@@ -1502,6 +1502,15 @@ __global__ void k_control(InstState* st, const double* partial, const InstInfo* 
   s.n_attempt++;
   s.n_evals += c.stages;
   if (c.fixed) {
+    // the partial sums hold the candidate state's RMS: a non-finite value
+    // (the state diverged or overflowed) ends the run at the last state
+    if (!isfinite(wrms_total(partial, inst, nchunk, (int64_t)info[inst].n_el + info[inst].n_ph))) {
+      s.status = -5;  // RTBTE_E_NONFINITE
+      s.done = 1;
+      s.accepted = 0;
+      st[inst] = s;
+      return;
+    }
     s.accepted = 1;
     s.n_accept++;
     s.steps_left--;

@@ -69,7 +69,9 @@ def test_rk4_stability_limit_on_toy():
     """The toy's e-ph Jacobian has spectral radius ~2.3/fs, so RK4 is stable
     below ~1.19 fs: at h = 1 fs (the fixed-step baseline run to 100 fs) the
     GPU follows the oracle's RK4 step for step; at h = 1.25 fs the
-    populations blow up on the GPU just as in the oracle."""
+    populations blow up on the GPU just as in the oracle (the run either
+    ends with blown-up finite populations or stops with RTBTE_E_NONFINITE at
+    the last finite state)."""
     torch = torch_cuda()
     import paper_2412_13402_amd as P
     wl = wl_of("toy2d")
@@ -79,17 +81,48 @@ def test_rk4_stability_limit_on_toy():
         ctx = P.Context(wl.problem_arrays())
         y = to_dev(wl.y0)
         t = torch.zeros(1, dtype=torch.float64, device="cuda")
-        ctx.step_rk4(y, t, h, n)
+        code = 0
+        try:
+            ctx.step_rk4(y, t, h, n)
+        except P.RtbteError as e:
+            code = e.code
         torch.cuda.synchronize()
         g = y.cpu().numpy()
         if h == 1.0:
+            assert code == 0
             yr = wl.y0.copy()
             for _ in range(n):
                 yr = I.rk4_step(o.rhs, yr, h)
             assert np.all(np.isfinite(g)) and close(g, yr, 1e-11)
             assert np.all((g[:wl.n_el] > 0) & (g[:wl.n_el] < 1.001))
         else:
-            assert (not np.all(np.isfinite(g))) or np.max(np.abs(g)) > 1e6
+            assert code in (0, P.rtbte.E_NONFINITE)
+            assert np.all(np.isfinite(g)) and np.max(np.abs(g)) > 1e6
+
+
+def test_rk4_nonfinite_step_is_not_taken():
+    """A fixed step whose result is not finite is not committed: the call
+    returns RTBTE_E_NONFINITE with y and t as they were before that step."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    ctx = P.Context(Pr)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    say("[int] RK4: 3 steps, then a NaN in y")
+    ctx.step_rk4(y, t, 0.5, 3)
+    torch.cuda.synchronize()
+    y3 = y.cpu().numpy().copy()
+    assert t.item() == 1.5 and np.all(np.isfinite(y3))
+    y[7] = float("nan")
+    y_bad = y.cpu().numpy().copy()
+    with pytest.raises(P.RtbteError) as e:
+        ctx.step_rk4(y, t, 0.5, 4)
+    assert e.value.code == P.rtbte.E_NONFINITE
+    torch.cuda.synchronize()
+    g = y.cpu().numpy()
+    assert t.item() == 1.5
+    assert np.isnan(g[7]) and np.array_equal(np.delete(g, 7), np.delete(y_bad, 7))
 
 
 def test_starting_step_matches_oracle():
