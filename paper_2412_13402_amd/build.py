@@ -15,7 +15,8 @@ def hipcc_command(out=LIB, arch="gfx950"):
     return [hipcc, "-O3", "-std=c++17", f"--offload-arch={arch}", "-fPIC", "-shared", "-fopenmp",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
-            "-o", out] + SOURCES
+            "-o", out] + SOURCES + ["-L", os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"),
+                                    "-lrocprofiler-sdk-roctx"]
 
 
 def example_command(out=EXAMPLE):

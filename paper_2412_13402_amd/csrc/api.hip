@@ -15,6 +15,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <string>
 #include <vector>
 
@@ -31,6 +33,16 @@ hipError_t launch_select_max_norm(const double* partial, const InstInfo* info, i
                                   double* sel_partial, InstInfo* sel_info, hipStream_t s);
 hipError_t launch_broadcast_first(double* p, int64_t n, hipStream_t s);
 }
+
+// A roctx range over a library call or a poll interval, shown by
+// `rocprofv3 --marker-trace` beside the kernels it enqueued (a host-side
+// marker: no stream work, nothing recorded into captured graphs).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePush(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 namespace {
 
@@ -1441,6 +1453,7 @@ int check_fp64(rtbte_ctx* c, const double* y, hipStream_t s) {
 }  // namespace
 
 extern "C" int rtbte_check_fp64(rtbte_ctx* c, const double* y, double* err, void* stream) {
+  TraceRange tr("rtbte_check_fp64");
   if (!c) return RTBTE_E_INVAL;
   if (!c->mixed || !c->keep64)
     return fail(c, RTBTE_E_UNSUPPORTED, "rtbte_check_fp64 needs an RTBTE_MIXED context created with fp64_check > 0");
@@ -1453,6 +1466,7 @@ extern "C" int rtbte_check_fp64(rtbte_ctx* c, const double* y, double* err, void
 }
 
 extern "C" int rtbte_rates(rtbte_ctx* c, const double* y, double* rates, int32_t parts, void* stream) {
+  TraceRange tr("rtbte_rates");
   if (!c) return RTBTE_E_INVAL;
   if (c->mixed) return fail(c, RTBTE_E_UNSUPPORTED, "rtbte_rates needs an RTBTE_FP64 context");
   if (!y || !rates || parts < 1 || parts > 7) return fail(c, RTBTE_E_INVAL, "rtbte_rates: bad arguments");
@@ -1465,6 +1479,7 @@ extern "C" int rtbte_rates(rtbte_ctx* c, const double* y, double* rates, int32_t
 }
 
 extern "C" int rtbte_rhs(rtbte_ctx* c, const double* y, double* ydot, int32_t parts, void* stream) {
+  TraceRange tr("rtbte_rhs");
   if (!c) return RTBTE_E_INVAL;
   if (!y || !ydot || parts < 1 || parts > 7) return fail(c, RTBTE_E_INVAL, "rtbte_rhs: bad arguments");
   if (y == ydot) return fail(c, RTBTE_E_INVAL, "rtbte_rhs: y and ydot must not overlap");
@@ -1702,6 +1717,7 @@ int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_ste
   // every instance done at the end of the last poll interval)
   int64_t left = fixed_steps;
   while (!done) {
+    TraceRange tr_poll("rtbte poll interval");
     const int n = fixed_steps > 0 && left > 0 ? (int)std::min<int64_t>(per_poll, left) : per_poll;
     if (fixed_steps > 0) left -= n;
     if (graph) {
@@ -1734,6 +1750,7 @@ int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_ste
 
 extern "C" int rtbte_step_adaptive(rtbte_ctx* c, double* y, double* t, double* h, double t_out,
                                    int32_t one_step, void* stream) {
+  TraceRange tr("rtbte_step_adaptive");
   if (!c) return RTBTE_E_INVAL;
   if (!y || !t || !h || !std::isfinite(t_out)) return fail(c, RTBTE_E_INVAL, "step_adaptive: bad arguments");
   HIPCHK(c, hipSetDevice(c->device));
@@ -1744,6 +1761,7 @@ extern "C" int rtbte_step_adaptive(rtbte_ctx* c, double* y, double* t, double* h
 
 extern "C" int rtbte_step_rk4(rtbte_ctx* c, double* y, double* t, double h_step, int64_t n_steps,
                               void* stream) {
+  TraceRange tr("rtbte_step_rk4");
   if (!c) return RTBTE_E_INVAL;
   if (!y || !t || !(h_step > 0) || n_steps < 0) return fail(c, RTBTE_E_INVAL, "step_rk4: bad arguments");
   if (n_steps == 0) return RTBTE_OK;
@@ -1843,6 +1861,7 @@ int mis_setup(rtbte_ctx* c, double* y, double* t, double* h_fast, double t_out, 
 
 extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* h_fast, double t_out,
                                     double h_slow, int32_t one_step, void* stream) {
+  TraceRange tr("rtbte_step_multirate");
   if (!c) return RTBTE_E_INVAL;
   if (!(h_slow > 0)) return fail(c, RTBTE_E_INVAL, "step_multirate: bad arguments");
   hipStream_t s = (hipStream_t)stream;
@@ -1888,6 +1907,7 @@ extern "C" int rtbte_step_multirate(rtbte_ctx* c, double* y, double* t, double* 
 
 extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t, double* h_fast, double* h_slow,
                                              double t_out, int32_t one_step, void* stream) {
+  TraceRange tr("rtbte_step_multirate_adaptive");
   if (!c) return RTBTE_E_INVAL;
   if (!h_slow) return fail(c, RTBTE_E_INVAL, "step_multirate_adaptive: bad arguments");
   hipStream_t s = (hipStream_t)stream;
@@ -1982,6 +2002,7 @@ extern "C" int rtbte_step_multirate_adaptive(rtbte_ctx* c, double* y, double* t,
 
 extern "C" int rtbte_step_split(rtbte_ctx* c, double* y, double* t, double h_fast, double h_slow, double t_out,
                                 void* stream) {
+  TraceRange tr("rtbte_step_split");
   if (!c) return RTBTE_E_INVAL;
   if (!y || !t || !(h_fast > 0) || !(h_slow > 0) || !std::isfinite(t_out))
     return fail(c, RTBTE_E_INVAL, "step_split: bad arguments");
@@ -2310,6 +2331,7 @@ int tune_create(const rtbte_problem* P, int n, rtbte_options o, rtbte_ctx** out)
 
 extern "C" int rtbte_create(const rtbte_problem* problems, int32_t n_inst, const rtbte_options* opts,
                             rtbte_ctx** out) {
+  TraceRange tr("rtbte_create");
   g_create_error.clear();
   if (!out) return fail(nullptr, RTBTE_E_INVAL, "out is NULL");
   *out = nullptr;
