@@ -264,7 +264,17 @@ typedef struct {
   int32_t status;                           /* RTBTE_* status of the last stepping call */
   double err_vs_fp64_last;                  /* last ||f_mixed - f_fp64|| / ||f_fp64|| of
                                                this instance (fp64_check); -1: none     */
+  int32_t health;                           /* RTBTE_HEALTH_* bits: populations found out
+                                               of their physical range in the state after
+                                               a poll interval of a stepping call, since
+                                               create or rtbte_reset (0: none)          */
 } rtbte_stats;
+
+/* Health bits (rtbte_stats.health): an electron occupation outside
+ * [-1e-6, 1 + 1e-6] (or not a number), a phonon occupation below -1e-6 (or
+ * not a number).  Informational: the run goes on (a diverging fixed-step run,
+ * for instance, sets them long before its state overflows). */
+enum { RTBTE_HEALTH_F_RANGE = 1, RTBTE_HEALTH_N_NEGATIVE = 2 };
 
 void rtbte_default_options(rtbte_options *opts);
 

@@ -245,6 +245,7 @@ struct rtbte_ctx {
   int64_t* bnd = nullptr;
   int64_t n_blocks = 0;
   double tile_in_window = 0.0;    // fraction of tiles whose other partners are staged
+  int32_t* health = nullptr;      // [n_inst] RTBTE_HEALTH_* bits since create / reset
 };
 
 static int fail(rtbte_ctx* c, int code, const char* fmt, ...) {
@@ -436,7 +437,7 @@ void free_ctx(rtbte_ctx* c) {
                 c->st_fast, c->st_slow, c->mra, c->mis_keep, c->energy_d,
                 c->kbuf[0], c->kbuf[1], c->kbuf[2], c->kbuf[3], c->kbuf[4], c->zb[0], c->zb[1],
                 c->ynew, c->lte, c->tmp, c->tmp2, c->fs[0], c->fs[1], c->fs[2], c->forcing,
-                c->partial, c->tvec, c->summary_d, c->tblocks, c->border, c->tiles, c->bnd, c->ppm};
+                c->partial, c->tvec, c->summary_d, c->tblocks, c->border, c->tiles, c->bnd, c->ppm, c->health};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   for (auto& g : c->graphs) {
@@ -1165,6 +1166,7 @@ static int create_impl(const rtbte_problem* problems, int32_t n_inst, const rtbt
   if (e == hipSuccess) c->st = dalloc<InstState>((size_t)n_inst, &e);
   if (e == hipSuccess) c->st_fast = dalloc<InstState>((size_t)n_inst, &e);
   if (e == hipSuccess) c->st_slow = dalloc<InstState>(1, &e);
+  if (e == hipSuccess) c->health = dalloc<int32_t>((size_t)std::max(n_inst, 1), &e);
   if (e != hipSuccess) {
     fail(c, e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP, "work buffers: %s", hipGetErrorString(e));
     return cleanup(e == hipErrorOutOfMemory ? RTBTE_E_NOMEM : RTBTE_E_HIP);
@@ -1204,6 +1206,7 @@ extern "C" int rtbte_reset(rtbte_ctx* c) {
   HIPCHK(c, hipMemcpy(c->st, s.data(), s.size() * sizeof(InstState), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->st_fast, s.data(), s.size() * sizeof(InstState), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->st_slow, s.data(), sizeof(InstState), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(c->health, 0, (size_t)c->n_inst * sizeof(int32_t)));
   c->extra_rhs[0] = c->extra_rhs[1] = c->extra_rhs[2] = 0;
   c->slow_steps = 0;
   c->split_slow_evals = 0;
@@ -1732,6 +1735,7 @@ int run(rtbte_ctx* c, double* y, double* t, double* h, double t_out, int one_ste
         if (rc) return rc;
       }
     }
+    HIPCHK(c, launch_health(y, c->info_d, c->health, c->n_inst, kHealthTol, s));
     int rc = poll(c, st, c->n_inst, t, h, s, &done, &worst);
     if (rc) return rc;
     if (c->keep64 && ++c->polls >= c->opt.fp64_check) {
@@ -2036,10 +2040,12 @@ extern "C" int rtbte_step_split(rtbte_ctx* c, double* y, double* t, double h_fas
 extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* out) {
   if (!c || !out || inst < 0 || inst >= c->n_inst) return RTBTE_E_INVAL;
   InstState s, f, w;
+  int32_t health = 0;
   if (hipSetDevice(c->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
       hipMemcpy(&s, c->st + inst, sizeof s, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(&f, c->st_fast + inst, sizeof f, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(&w, c->st_slow, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(&w, c->st_slow, sizeof w, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&health, c->health + inst, sizeof health, hipMemcpyDeviceToHost) != hipSuccess)
     return RTBTE_E_HIP;
   std::memset(out, 0, sizeof *out);
   // ERK steps, plus MIS slow steps (fixed and adaptive; common to a batch)
@@ -2059,6 +2065,7 @@ extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* ou
   out->eps_last = s.eps;
   out->err_vs_fp64_last = c->err64[(size_t)inst];
   out->status = c->last_status;
+  out->health = health;
   return RTBTE_OK;
 }
 

@@ -17,6 +17,7 @@ constexpr uint32_t kIdxMask = 0x7fffffffu;
 constexpr int32_t kTagShift = 27;                   // row tag inside a group: bits 27..30 of i0
 constexpr int32_t kPosMask = 0x07ffffff;            // state index: bits 0..26 of i0 / i1
 constexpr int kMaxGroupRows = 16;
+constexpr double kHealthTol = 1e-6;                 // occupations checked against [-tol, 1 + tol] / [-tol, inf)
 
 // A stored channel, 16 bytes, streamed once per right-hand-side evaluation.
 // Channels of a group of up to 16 consecutive destination rows are stored
@@ -256,6 +257,11 @@ hipError_t launch_control(InstState* st, const double* partial, const InstInfo* 
                           int nchunk, Ctl c, hipStream_t s);
 hipError_t launch_commit(double* y, const double* ynew, const int32_t* row_inst,
                          const InstState* st, int64_t n, hipStream_t s);
+// health[inst] |= 1 when an electron occupation of y leaves [-tol, 1 + tol]
+// (or is not a number), |= 2 when a phonon occupation is below -tol (or not a
+// number); one block per instance
+hipError_t launch_health(const double* y, const InstInfo* info, int32_t* health, int n_inst, double tol,
+                         hipStream_t s);
 hipError_t launch_begin(InstState* st, const double* t_in, const double* h_in, int n_inst,
                         double t_out, int one_step, double h_cap, int64_t fixed_steps,
                         double fixed_h, hipStream_t s);

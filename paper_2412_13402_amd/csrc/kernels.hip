@@ -1579,6 +1579,27 @@ __global__ void k_commit(double* __restrict__ y, const double* __restrict__ ynew
   if (st[inst].accepted) y[i] = ynew[i];
 }
 
+__global__ __launch_bounds__(256) void k_health(const double* __restrict__ y, const InstInfo* info,
+                                                int32_t* health, double tol) {
+  const InstInfo in = info[blockIdx.x];
+  int f_bad = 0, n_bad = 0;
+  for (int64_t i = threadIdx.x; i < in.n_el; i += 256) {
+    const double f = y[in.off + i];
+    f_bad |= !(f >= -tol && f <= 1.0 + tol);
+  }
+  for (int64_t i = threadIdx.x; i < in.n_ph; i += 256) n_bad |= !(y[in.off + in.n_el + i] >= -tol);
+  f_bad = __syncthreads_or(f_bad);
+  n_bad = __syncthreads_or(n_bad);
+  if (threadIdx.x == 0 && (f_bad || n_bad)) health[blockIdx.x] |= (f_bad ? 1 : 0) | (n_bad ? 2 : 0);
+}
+
+hipError_t launch_health(const double* y, const InstInfo* info, int32_t* health, int n_inst, double tol,
+                         hipStream_t s) {
+  if (n_inst == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_health, dim3((unsigned)n_inst), dim3(256), 0, s, y, info, health, tol);
+  return hipGetLastError();
+}
+
 hipError_t launch_commit(double* y, const double* ynew, const int32_t* row_inst,
                          const InstState* st, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;

@@ -20,6 +20,7 @@ FP64, MIXED = 0, 1
 # weight formats of MIXED (rtbte.h): automatic, packed 8-byte words, FP16 + 11-bit tail,
 # FP16, BF16 for e-ph / FP16 for ph-ph
 W_AUTO, W_PACK8, W_F16X, W_F16, W_BF16_EPH = 0, 1, 2, 3, 4
+HEALTH_F_RANGE, HEALTH_N_NEGATIVE = 1, 2
 # FP64 channel layouts (rtbte.h)
 F64_AUTO, F64_PACKED, F64_PLAIN = 0, 1, 2
 
@@ -87,7 +88,7 @@ class Stats(ctypes.Structure):
         ("n_fast_accept", ctypes.c_int64), ("n_fast_reject", ctypes.c_int64),
         ("t", ctypes.c_double), ("h_last", ctypes.c_double), ("h_min", ctypes.c_double),
         ("h_max", ctypes.c_double), ("eps_last", ctypes.c_double), ("status", ctypes.c_int32),
-        ("err_vs_fp64_last", ctypes.c_double),
+        ("err_vs_fp64_last", ctypes.c_double), ("health", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -68,7 +68,9 @@ def test_rk4_fixed_steps_match_oracle():
 def test_rk4_stability_limit_on_toy():
     """The toy's e-ph Jacobian has spectral radius ~2.3/fs, so RK4 is stable
     below ~1.19 fs: at h = 1 fs (the fixed-step baseline run to 100 fs) the
-    GPU follows the oracle's RK4 step for step; at h = 1.25 fs the
+    GPU follows the oracle's RK4 step for step (and reports the same health
+    bits: the stiff modes ring, and phonon occupations dip below zero); at
+    h = 1.25 fs the
     populations blow up on the GPU just as in the oracle (the run either
     ends with blown-up finite populations or stops with RTBTE_E_NONFINITE at
     the last finite state)."""
@@ -91,13 +93,49 @@ def test_rk4_stability_limit_on_toy():
         if h == 1.0:
             assert code == 0
             yr = wl.y0.copy()
-            for _ in range(n):
+            bits = 0
+            for k in range(1, n + 1):
                 yr = I.rk4_step(o.rhs, yr, h)
+                if k % 8 == 0 or k == n:        # the states the library checks (one per poll of 8 steps)
+                    f, N = yr[:wl.n_el], yr[wl.n_el:]
+                    bits |= (1 if np.any((f < -1e-6) | (f > 1 + 1e-6)) else 0) | (2 if np.any(N < -1e-6) else 0)
             assert np.all(np.isfinite(g)) and close(g, yr, 1e-11)
             assert np.all((g[:wl.n_el] > 0) & (g[:wl.n_el] < 1.001))
+            # stable, but ringing: phonon occupations dip below zero (to -0.99
+            # in the oracle's run), which the health bits report
+            assert bits & P.rtbte.HEALTH_N_NEGATIVE
+            assert ctx.stats()["health"] == bits
         else:
             assert code in (0, P.rtbte.E_NONFINITE)
             assert np.all(np.isfinite(g)) and np.max(np.abs(g)) > 1e6
+            # the blown-up occupations leave their physical range
+            assert ctx.stats()["health"] & P.rtbte.HEALTH_F_RANGE
+
+
+def test_health_bits():
+    """Occupations outside their physical range set the instance's health
+    bits (sticky until rtbte_reset); the run goes on; healthy instances of
+    the same batch keep 0."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    ctx = P.Context([Pr, Pr, Pr])
+    ne = Pr["n_el"]
+    ys = [y0.copy(), y0.copy(), y0.copy()]
+    ys[1][3] = 1.5              # an electron occupation above 1
+    ys[2][ne + 4] = -0.25       # a negative phonon occupation
+    y = to_dev(np.concatenate(ys))
+    t = torch.zeros(3, dtype=torch.float64, device="cuda")
+    say("[int] health bits")
+    ctx.step_rk4(y, t, 0.05, 2)
+    torch.cuda.synchronize()
+    hb = [ctx.stats(i)["health"] for i in range(3)]
+    assert hb[0] == 0
+    assert hb[1] & P.rtbte.HEALTH_F_RANGE
+    assert hb[2] & P.rtbte.HEALTH_N_NEGATIVE
+    assert np.all(t.cpu().numpy() == 0.1)
+    ctx.reset()
+    assert [ctx.stats(i)["health"] for i in range(3)] == [0, 0, 0]
 
 
 def test_rk4_nonfinite_step_is_not_taken():
