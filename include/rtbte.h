@@ -476,7 +476,7 @@ int rtbte_get_tuning_source(const rtbte_ctx *ctx, int32_t *source, double *rhs_m
 int64_t rtbte_graph_launches(const rtbte_ctx *ctx);
 
 /* Checkpoint of the integrator state kept in the context (PID histories,
- * step sizes, counters; not y, which the caller owns).  With buf == NULL,
+ * step sizes, counters, health bits; not y, which the caller owns).  With buf == NULL,
  * *len receives the size needed. */
 int rtbte_get_state(const rtbte_ctx *ctx, void *buf, size_t *len);
 int rtbte_set_state(rtbte_ctx *ctx, const void *buf, size_t len);

@@ -2071,7 +2071,8 @@ extern "C" int rtbte_get_stats(const rtbte_ctx* c, int32_t inst, rtbte_stats* ou
 
 extern "C" int rtbte_get_state(const rtbte_ctx* c, void* buf, size_t* len) {
   if (!c || !len) return RTBTE_E_INVAL;
-  const size_t need = (2 * (size_t)c->n_inst + 1) * sizeof(InstState) + 5 * sizeof(int64_t);
+  const size_t ns = (2 * (size_t)c->n_inst + 1) * sizeof(InstState);
+  const size_t need = ns + 5 * sizeof(int64_t) + (size_t)c->n_inst * sizeof(int32_t);
   if (!buf) {
     *len = need;
     return RTBTE_OK;
@@ -2083,17 +2084,20 @@ extern "C" int rtbte_get_state(const rtbte_ctx* c, void* buf, size_t* len) {
       hipMemcpy(p + c->n_inst * sizeof(InstState), c->st_fast, c->n_inst * sizeof(InstState),
                 hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(p + 2 * c->n_inst * sizeof(InstState), c->st_slow, sizeof(InstState), hipMemcpyDeviceToHost) !=
-          hipSuccess)
+          hipSuccess ||
+      hipMemcpy(p + ns + 5 * sizeof(int64_t), c->health, (size_t)c->n_inst * sizeof(int32_t),
+                hipMemcpyDeviceToHost) != hipSuccess)
     return RTBTE_E_HIP;
   int64_t tail[5] = {c->extra_rhs[0], c->extra_rhs[1], c->extra_rhs[2], c->slow_steps, c->split_slow_evals};
-  std::memcpy(p + (2 * c->n_inst + 1) * sizeof(InstState), tail, sizeof tail);
+  std::memcpy(p + ns, tail, sizeof tail);
   *len = need;
   return RTBTE_OK;
 }
 
 extern "C" int rtbte_set_state(rtbte_ctx* c, const void* buf, size_t len) {
   if (!c || !buf) return RTBTE_E_INVAL;
-  const size_t need = (2 * (size_t)c->n_inst + 1) * sizeof(InstState) + 5 * sizeof(int64_t);
+  const size_t ns = (2 * (size_t)c->n_inst + 1) * sizeof(InstState);
+  const size_t need = ns + 5 * sizeof(int64_t) + (size_t)c->n_inst * sizeof(int32_t);
   if (len != need) return fail(c, RTBTE_E_INVAL, "state size %zu, expected %zu", len, need);
   const char* p = (const char*)buf;
   HIPCHK(c, hipSetDevice(c->device));
@@ -2102,8 +2106,10 @@ extern "C" int rtbte_set_state(rtbte_ctx* c, const void* buf, size_t len) {
                       hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->st_slow, p + 2 * c->n_inst * sizeof(InstState), sizeof(InstState),
                       hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->health, p + ns + 5 * sizeof(int64_t), (size_t)c->n_inst * sizeof(int32_t),
+                      hipMemcpyHostToDevice));
   int64_t tail[5];
-  std::memcpy(tail, p + (2 * c->n_inst + 1) * sizeof(InstState), sizeof tail);
+  std::memcpy(tail, p + ns, sizeof tail);
   c->extra_rhs[0] = tail[0];
   c->extra_rhs[1] = tail[1];
   c->extra_rhs[2] = tail[2];

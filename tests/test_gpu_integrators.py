@@ -134,6 +134,9 @@ def test_health_bits():
     assert hb[1] & P.rtbte.HEALTH_F_RANGE
     assert hb[2] & P.rtbte.HEALTH_N_NEGATIVE
     assert np.all(t.cpu().numpy() == 0.1)
+    other = P.Context([Pr, Pr, Pr])              # the bits travel with a checkpoint
+    other.set_state(ctx.get_state())
+    assert [other.stats(i)["health"] for i in range(3)] == hb
     ctx.reset()
     assert [ctx.stats(i)["health"] for i in range(3)] == [0, 0, 0]
 
