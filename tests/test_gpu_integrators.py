@@ -703,6 +703,28 @@ def test_multirate_failure_leaves_the_start_of_the_failing_slow_step():
     assert close(y.cpu().numpy(), yr, 1e-11)
 
 
+def test_multirate_fixed_fast_nonfinite_is_reported():
+    """MIS with fixed RK4 fast steps from a state holding a NaN: the first
+    fast step is not finite, the call reports RTBTE_E_NONFINITE, and y and t
+    hold the start of the slow step (no slow step completed)."""
+    torch = torch_cuda()
+    import paper_2412_13402_amd as P
+    Pr, y0 = coupled()
+    y0 = y0.copy()
+    y0[5] = np.nan
+    say("[int] MIS, fixed fast steps, NaN in y")
+    ctx = P.Context(Pr, fast_mode=1, h_fast=0.25)
+    y = to_dev(y0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hf = torch.full((1,), 0.25, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.RtbteError) as e:
+        ctx.step_multirate(y, t, hf, 4.0, 1.0)
+    assert e.value.code == P.rtbte.E_NONFINITE
+    torch.cuda.synchronize()
+    assert t.item() == 0.0
+    assert np.array_equal(y.cpu().numpy(), y0, equal_nan=True)
+
+
 def test_batched_multirate_adaptive_resume_is_bitwise():
     """Checkpoint a batched run with the adaptive slow step (the shared slow
     controller and each instance's fast controller are in the saved state),
