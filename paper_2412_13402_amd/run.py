@@ -128,6 +128,7 @@ def main(argv=None):
                generate_s=gen_s, create_s=create_s, steps=one("n_accept"), rejected=one("n_reject"),
                fast_steps=one("n_fast_accept"), rhs_eph=one("n_rhs_eph"), rhs_phph=one("n_rhs_phph"),
                h_last=one("h_last"), h_slow_last=float(hs[0].item()) if a.method == "mis-adaptive" else None,
+               health=one("health"),
                options=dict(rtol=a.rtol, atol_el=a.atol_el, atol_ph=a.atol_ph, h=a.h, h_slow=a.h_slow,
                             h_fast=a.h_fast, fast_rtol=a.fast_rtol, pid_alt_sign=a.pid_alt_sign,
                             batch=a.batch, batch_L=list(a.batch_L), batch_T=list(a.batch_T)),

@@ -31,6 +31,7 @@ def test_run_driver(method, extra, capsys):
     assert abs(res["history"][-1]["carriers"] - n0) <= 1e-9 * n0
     T = res["history"][-1]["phonon_T_K"]
     assert len(T) == wl.grid["n_modes"] and all(np.isfinite(T)) and all(x > 0 for x in T)
+    assert out["health"] == 0          # occupations stayed in their physical range
 
 
 @pytest.mark.parametrize("method,extra", [("erk", []), ("mis-adaptive", ["--h-slow", "0.5", "--h-fast", "0"])])
@@ -44,7 +45,7 @@ def test_run_driver_batch(method, extra, capsys):
     res = run.main(["--workload", "graphene2d", "--batch", "3", "--batch-L", "8", "12", "--method", method,
                     "--t-end", "20", "--checks", "2"] + extra)
     out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
-    assert out["n_inst"] == 3 and len(out["steps"]) == 3
+    assert out["n_inst"] == 3 and len(out["steps"]) == 3 and out["health"] == [0, 0, 0]
     ws = synth.build_batch(3, (8, 12), (500.0, 3000.0))
     last = res["history"][-1]["instances"]
     for w, e in zip(ws, last):
